@@ -1,0 +1,178 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the
+benchmark.
+
+This module only builds test matrices; it performs none of the factorization's
+arithmetic.  All random numbers come from numpy's PCG64 generator so that a
+(seed, shape) pair names the same bytes on every machine.  Matrices are float64,
+Fortran (column-major) ordered, exactly symmetric (the upper triangle is
+mirrored), so their bytes are also their row-major bytes.
+
+Recipes (the paper fixes none of them; they are the workloads of the dense
+Cholesky benchmarks):
+  spd_bbt       A = B B^T + n I, B_ij ~ N(0,1) from PCG64(seed) filled in C order
+  spd_kappa     A = Q diag(s) Q^T, Q Haar-orthogonal (QR of a Gaussian, seed+1000,
+                column signs fixed by sign(diag R)), s_i = kappa^(-i/(n-1))
+  rhs           B ~ N(0,1), n x nrhs, seed+2000
+  minij_scaled  A_ij = d_i d_j min(i+1, j+1), d_j = 2^((j mod 7) - 3); its
+                factor is U_ij = d_j (i <= j), exact in binary floating point
+  pascal        A_ij = C(i+j, i); U_ij = C(j, i)
+  laplacian1d   tridiag(-1, 2, -1)
+  batch         n_i ~ U{lo..hi} (PCG64(seed).integers, endpoint inclusive),
+                then each B_i from the same stream and A_i = B_i B_i^T + n_i I
+"""
+from __future__ import annotations
+
+from math import comb
+
+import numpy as np
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def _symmetrize_upper(A: np.ndarray) -> np.ndarray:
+    """Mirror the upper triangle into the lower one (exact symmetry)."""
+    T = np.triu(A)
+    S = T + np.triu(T, 1).T
+    return np.asfortranarray(S)
+
+
+def gaussian(n: int, m: int, seed: int) -> np.ndarray:
+    """n x m N(0,1) matrix, drawn in C order from PCG64(seed)."""
+    return _rng(seed).standard_normal((n, m), dtype=np.float64)
+
+
+def spd_bbt(n: int, seed: int = 0) -> np.ndarray:
+    """A = B B^T + n I with B ~ N(0,1) (n x n) from PCG64(seed); kappa <~ 5."""
+    B = gaussian(n, n, seed)
+    A = B @ B.T
+    A[np.diag_indices(n)] += float(n)
+    return _symmetrize_upper(A)
+
+
+def spd_bbt_torch(n: int, seed: int, device):
+    """Same recipe as spd_bbt, with the product B B^T formed by torch on
+    ``device`` (fast at n = 16384).  The bytes can differ from spd_bbt in the
+    last bit because the product's summation order differs; both are exactly
+    symmetric SPD matrices of the same distribution.  Returns a torch tensor in
+    column-major layout (strides (1, n))."""
+    import torch
+
+    B = torch.from_numpy(gaussian(n, n, seed)).to(device)
+    A = B @ B.T
+    del B
+    A.diagonal().add_(float(n))
+    A = torch.triu(A)
+    A = A + torch.triu(A, 1).T
+    return A.T.contiguous().T  # symmetric: same bytes, column-major strides
+
+
+def haar_orthogonal(n: int, seed: int) -> np.ndarray:
+    """Q from the QR of an n x n Gaussian with the column signs of
+    sign(diag(R)) folded in (Haar-distributed)."""
+    G = gaussian(n, n, seed)
+    Q, R = np.linalg.qr(G)
+    sgn = np.sign(np.diag(R))
+    sgn[sgn == 0] = 1.0
+    return Q * sgn
+
+
+def kappa_spectrum(n: int, kappa: float) -> np.ndarray:
+    """s_i = kappa^(-i/(n-1)), i = 0..n-1 (1 down to 1/kappa)."""
+    if n == 1:
+        return np.ones(1)
+    return float(kappa) ** (-np.arange(n, dtype=np.float64) / (n - 1))
+
+
+def spd_kappa(n: int, kappa: float, seed: int = 0) -> np.ndarray:
+    """A = Q diag(s) Q^T with condition number kappa (2-norm)."""
+    Q = haar_orthogonal(n, seed + 1000)
+    s = kappa_spectrum(n, kappa)
+    A = (Q * s) @ Q.T
+    return _symmetrize_upper(A)
+
+
+def spd_kappa_torch(n: int, kappa: float, seed: int, device):
+    """spd_kappa with the QR and products done by torch on ``device`` (for
+    n = 16384).  Column-major torch tensor."""
+    import torch
+
+    G = torch.from_numpy(gaussian(n, n, seed + 1000)).to(device)
+    Q, R = torch.linalg.qr(G)
+    del G
+    sgn = torch.sign(torch.diagonal(R))
+    sgn[sgn == 0] = 1.0
+    del R
+    Q.mul_(sgn)
+    s = torch.from_numpy(kappa_spectrum(n, kappa)).to(device)
+    A = (Q * s) @ Q.T
+    del Q
+    A = torch.triu(A)
+    A = A + torch.triu(A, 1).T
+    return A.T.contiguous().T
+
+
+def rhs(n: int, nrhs: int, seed: int = 0) -> np.ndarray:
+    """Right-hand sides, n x nrhs N(0,1) from PCG64(seed + 2000), Fortran."""
+    return np.asfortranarray(gaussian(nrhs, n, seed + 2000).T)
+
+
+def minij_scaled(n: int) -> np.ndarray:
+    """A_ij = d_i d_j min(i+1, j+1), d_j = 2^((j mod 7) - 3).
+
+    Its Cholesky factor is U_ij = d_j for i <= j: every intermediate of the
+    factorization is an integer times a power of two, so FP64, FP32 and BF16
+    arithmetic all reproduce it exactly.  The column-dependent scale d makes a
+    transposed tile visible."""
+    d = 2.0 ** ((np.arange(n) % 7) - 3)
+    idx = np.arange(1, n + 1)
+    M = np.minimum.outer(idx, idx).astype(np.float64)
+    return np.asfortranarray(M * np.outer(d, d))
+
+
+def minij_factor(n: int) -> np.ndarray:
+    """The exact upper factor of minij_scaled(n): U_ij = d_j for i <= j."""
+    d = 2.0 ** ((np.arange(n) % 7) - 3)
+    return np.asfortranarray(np.triu(np.ones((n, n)) * d[None, :]))
+
+
+def pascal(n: int) -> np.ndarray:
+    """Symmetric Pascal matrix P_ij = C(i+j, i) (exact in FP64 for n <= 29)."""
+    return np.asfortranarray(np.array([[float(comb(i + j, i)) for j in range(n)] for i in range(n)]))
+
+
+def pascal_factor(n: int) -> np.ndarray:
+    """Its upper Cholesky factor U_ij = C(j, i)."""
+    return np.asfortranarray(np.array([[float(comb(j, i)) if i <= j else 0.0 for j in range(n)]
+                                       for i in range(n)]))
+
+
+def laplacian1d(n: int) -> np.ndarray:
+    A = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    return np.asfortranarray(A)
+
+
+def batch_sizes(count: int, seed: int = 0, lo: int = 16, hi: int = 512) -> np.ndarray:
+    """n_i ~ U{lo..hi} (inclusive), int32."""
+    return _rng(seed).integers(lo, hi, endpoint=True, size=count).astype(np.int32)
+
+
+def batch(count: int, seed: int = 0, lo: int = 16, hi: int = 512):
+    """(sizes, matrices): n_i ~ U{lo..hi} from PCG64(seed), then, from the same
+    stream, B_i (n_i x n_i, C order) one after another and A_i = B_i B_i^T +
+    n_i I."""
+    g = _rng(seed)
+    sizes = g.integers(lo, hi, endpoint=True, size=count).astype(np.int32)
+    return sizes, _batch_from(g, sizes)
+
+
+def _batch_from(g, sizes):
+    out = []
+    for n in sizes:
+        n = int(n)
+        B = g.standard_normal((n, n), dtype=np.float64)
+        A = B @ B.T
+        A[np.diag_indices(n)] += float(n)
+        out.append(_symmetrize_upper(A))
+    return out

@@ -1,0 +1,209 @@
+"""FP64 CPU oracle for the dense blocked Cholesky A = U^T U (arXiv 1601.05871,
+Fig. "dense-chol").
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``; never by the library.  It shares no
+code with the GPU path.  The arithmetic lives in ``oracle.c`` (plain loops,
+FP64, no contraction); this module marshals numpy arrays into it and adds the
+accuracy metrics (plain numpy in FP64).
+
+Every matrix is a 2-D numpy float64 array in column-major (Fortran) order;
+only its upper triangle is read or written by the factor routines.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import build as _build, LIB_PATH
+
+_lib = None
+
+
+def load(path: str) -> ctypes.CDLL:
+    """Load an oracle shared library and declare its signatures."""
+    L = ctypes.CDLL(path)
+    if True:
+        i64, i32, dp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+        L.oracle_potrf_upper.argtypes = [i64, dp, i64, i32]
+        L.oracle_potrf_upper.restype = i32
+        L.oracle_potrf_upper_steps.argtypes = [i64, dp, i64, i64, i32]
+        L.oracle_potrf_upper_steps.restype = i32
+        L.oracle_potrf_blocked.argtypes = [i64, dp, i64, i64, i32, i64]
+        L.oracle_potrf_blocked.restype = i32
+        L.oracle_trsm_upper_t.argtypes = [i64, i64, dp, i64, dp, i64]
+        L.oracle_trsm_upper_t.restype = None
+        L.oracle_syrk_upper.argtypes = [i64, i64, dp, i64, dp, i64]
+        L.oracle_syrk_upper.restype = None
+        L.oracle_gemm_tn.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64]
+        L.oracle_gemm_tn.restype = None
+        L.oracle_solve_upper.argtypes = [i64, i64, dp, i64, dp, i64]
+        L.oracle_solve_upper.restype = None
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = i32
+    return L
+
+
+def lib() -> ctypes.CDLL:
+    """Load liboracle.so, compiling it first if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            _build()
+        _lib = load(LIB_PATH)
+    return _lib
+
+
+def _fortran(a: np.ndarray) -> np.ndarray:
+    if a.dtype != np.float64 or a.ndim != 2 or not a.flags.f_contiguous:
+        raise TypeError("oracle expects a 2-D float64 Fortran-ordered array")
+    return a
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _ld(a: np.ndarray) -> int:
+    # leading dimension of a Fortran-ordered array (also for column slices)
+    return a.strides[1] // 8 if a.shape[1] > 1 else max(1, a.shape[0])
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
+
+
+def potrf(A: np.ndarray, threads: int = 1, steps: int | None = None) -> tuple[np.ndarray, int]:
+    """O1: unblocked Cholesky (Fig. "dense-chol" at b = 1) on a copy of A.
+
+    Returns (A_out, info).  A_out's upper triangle holds U (or, if ``steps`` is
+    given, the first ``steps`` rows of U above the Schur complement); its
+    strictly lower triangle is A's, untouched.  info = 0 on success, else the
+    1-based column of the first pivot that is not > 0.
+    """
+    W = np.array(_fortran(A), dtype=np.float64, order="F", copy=True)
+    n = W.shape[0]
+    js = n if steps is None else int(steps)
+    info = lib().oracle_potrf_upper_steps(n, _ptr(W), max(1, n), js, int(threads))
+    return W, int(info)
+
+
+def potrf_inplace(W: np.ndarray, lda: int, n: int, threads: int = 0, steps: int | None = None) -> int:
+    """O1 in place on a Fortran buffer (used for timing the oracle)."""
+    js = n if steps is None else int(steps)
+    return int(lib().oracle_potrf_upper_steps(n, _ptr(W), lda, js, int(threads)))
+
+
+def potrf_blocked(A: np.ndarray, b: int, variant: int, iters: int = -1) -> tuple[np.ndarray, int]:
+    """O2: the blocked loop of Fig. "dense-chol" for loop invariant
+    ``variant`` (1 bordered, 2 left-looking, 3 right-looking) on a copy of A."""
+    W = np.array(_fortran(A), dtype=np.float64, order="F", copy=True)
+    n = W.shape[0]
+    info = lib().oracle_potrf_blocked(n, _ptr(W), max(1, n), int(b), int(variant), int(iters))
+    return W, int(info)
+
+
+def trsm_upper_t(U: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Returns triu(U)^{-T} X (the TRSM step of Fig. "dense-chol")."""
+    U = np.asfortranarray(U, dtype=np.float64)
+    Y = np.array(X, dtype=np.float64, order="F", copy=True)
+    b, m = Y.shape
+    lib().oracle_trsm_upper_t(b, m, _ptr(U), max(1, U.shape[0]), _ptr(Y), max(1, b))
+    return Y
+
+
+def syrk_upper(C: np.ndarray, P: np.ndarray) -> np.ndarray:
+    """Returns C - P^T P on the upper triangle (the HERK step); C's strictly
+    lower triangle is returned unchanged."""
+    P = np.asfortranarray(P, dtype=np.float64)
+    D = np.array(C, dtype=np.float64, order="F", copy=True)
+    k, m = P.shape
+    lib().oracle_syrk_upper(m, k, _ptr(P), max(1, k), _ptr(D), max(1, m))
+    return D
+
+
+def gemm_tn(C: np.ndarray, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Returns C - X^T Y (the off-diagonal block form of the HERK step)."""
+    X = np.asfortranarray(X, dtype=np.float64)
+    Y = np.asfortranarray(Y, dtype=np.float64)
+    D = np.array(C, dtype=np.float64, order="F", copy=True)
+    k, mr = X.shape
+    nc = Y.shape[1]
+    lib().oracle_gemm_tn(mr, nc, k, _ptr(X), max(1, k), _ptr(Y), max(1, k), _ptr(D), max(1, mr))
+    return D
+
+
+def solve(U: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """O3: X with U^T U X = B (forward then back substitution)."""
+    U = np.asfortranarray(U, dtype=np.float64)
+    X = np.array(B, dtype=np.float64, order="F", copy=True)
+    if X.ndim == 1:
+        X = X.reshape(-1, 1, order="F")
+    n, nrhs = X.shape
+    lib().oracle_solve_upper(n, nrhs, _ptr(U), max(1, U.shape[0]), _ptr(X), max(1, n))
+    return X
+
+
+# ----------------------------------------------------------------------------
+# Metrics (O4), FP64 numpy.  U is read from the upper triangle only.
+
+def upper(M: np.ndarray) -> np.ndarray:
+    return np.triu(M)
+
+
+def sym_from_upper(A: np.ndarray) -> np.ndarray:
+    """The symmetric matrix whose upper triangle is A's."""
+    T = np.triu(A)
+    return T + np.triu(T, 1).T
+
+
+def factor_backward_error(A: np.ndarray, U: np.ndarray) -> float:
+    """beta_F = ||A - U^T U||_F / ||A||_F, with A symmetric from its upper part."""
+    S = sym_from_upper(A)
+    Uu = np.triu(U)
+    R = S - Uu.T @ Uu
+    return float(np.linalg.norm(R) / np.linalg.norm(S))
+
+
+def factor_backward_error_est(A: np.ndarray, U: np.ndarray, seed: int = 0, k: int = 8) -> float:
+    """Randomized estimate ||(A - U^T U) X||_F / (||A||_F ||X||_F), X n x k
+    N(0,1), computed as A X - U^T (U X) in O(n^2 k) (used where n is too large
+    for the exact norm).  A is symmetric from its upper triangle."""
+    n = A.shape[0]
+    X = np.random.Generator(np.random.PCG64(seed)).standard_normal((n, k))
+    Au = np.triu(A)
+    AX = Au @ X + np.triu(A, 1).T @ X
+    Uu = np.triu(U)
+    R = AX - Uu.T @ (Uu @ X)
+    nA = np.sqrt(2.0 * np.sum(Au * Au) - np.sum(np.diag(A) ** 2))
+    return float(np.linalg.norm(R) / (nA * np.linalg.norm(X)))
+
+
+def solve_backward_error(A: np.ndarray, X: np.ndarray, B: np.ndarray) -> float:
+    """Normwise backward error eta = ||b - A x||_inf / (||A||_inf ||x||_inf +
+    ||b||_inf), the maximum over the columns; A symmetric from its upper part."""
+    S = sym_from_upper(A)
+    X = X.reshape(X.shape[0], -1)
+    B = B.reshape(B.shape[0], -1)
+    R = B - S @ X
+    nA = np.max(np.sum(np.abs(S), axis=1))
+    eta = 0.0
+    for c in range(X.shape[1]):
+        den = nA * np.max(np.abs(X[:, c])) + np.max(np.abs(B[:, c]))
+        eta = max(eta, float(np.max(np.abs(R[:, c])) / den))
+    return eta
+
+
+def forward_difference(U_hat: np.ndarray, U_ref: np.ndarray) -> float:
+    """||U_hat - U_ref||_F / ||U_ref||_F over the upper triangles."""
+    D = np.triu(U_hat) - np.triu(U_ref)
+    return float(np.linalg.norm(D) / np.linalg.norm(np.triu(U_ref)))
+
+
+def flops(n: int) -> float:
+    """Algorithmic flop count of a Cholesky factorization (LAPACK potrf count):
+    n^3/3 + n^2/2 + n/6 = n(n+1)(2n+1)/6."""
+    n = int(n)
+    return float(n * (n + 1) * (2 * n + 1) // 6)

@@ -1,0 +1,255 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU oracle for the dense Cholesky of
+ * Kim, Rajamanickam, Stelle, Edwards, Olivier, "Task Parallel Incomplete
+ * Cholesky Factorization using 2D Partitioned-Block Layout" (arXiv 1601.05871).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library links, loads or calls this
+ * file; only the tests, the smoke check and the benchmark's CPU-baseline leg
+ * do.  It shares no code, header or constant with the GPU path.
+ *
+ * Conventions (all functions):
+ *   - column-major storage, element (i, j) at A[i + j*lda];
+ *   - only the upper triangle (i <= j) of a symmetric operand is read, and
+ *     only the upper triangle of the factor is written; the strictly lower
+ *     triangle is never touched;
+ *   - IEEE binary64, round to nearest even, no contraction (the build uses
+ *     -ffp-contract=off -fno-fast-math); sqrt is the correctly rounded libm
+ *     sqrt;
+ *   - the operation is A := Chol(A) with A = U^T U and U upper triangular with
+ *     a positive diagonal (Fig. "dense-chol" and its caption: the update
+ *     A22 - A12^T A12 and triu() fix the upper-triangular form).
+ *
+ * Every update below applies the rank-1 terms of the Schur complement one at a
+ * time, in increasing pivot order, each product rounded and then subtracted.
+ * With that choice the blocked variants perform, element by element, exactly
+ * the same sequence of floating-point operations as the unblocked loop, so they
+ * agree with it bit for bit at every block size (the paper notes the blocked
+ * algorithm works equally for scalar entries, b = 1: blocking only regroups
+ * the same arithmetic).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define AT(A, lda, i, j) ((A)[(int64_t)(i) + (int64_t)(j) * (int64_t)(lda)])
+
+/* nthreads <= 0: the OpenMP default (all cores); otherwise that many threads. */
+static int pick_threads(int nthreads) {
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/*
+ * O1: unblocked right-looking Cholesky, the loop of Fig. "dense-chol" with
+ * block size b = 1 (Sec. "Numeric factorization: Cholesky-by-blocks").
+ * Runs the first `jstop` pivot steps (jstop >= n: the whole factorization).
+ * After s steps, rows 0..s-1 of the upper triangle hold the final rows of U
+ * and the trailing upper triangle holds the Schur complement.
+ *
+ * Step j, with alpha11 = A(j,j), a12 = A(j, j+1:n), A22 = A(j+1:n, j+1:n):
+ *   alpha11 := sqrt(alpha11)                       CHOL of a 1x1 block
+ *   a12     := a12 / alpha11                       TRSM (triu(alpha11)^{-T} a12)
+ *   A22     := A22 - a12^T a12   (upper part)      HERK (real: SYRK)
+ * Breakdown (the paper is silent): the first pivot that is not > 0 (this also
+ * catches NaN) stops the loop and returns its 1-based column index.
+ * Returns 0 on success.
+ */
+int oracle_potrf_upper_steps(int64_t n, double *A, int64_t lda, int64_t jstop, int nthreads) {
+    int nt = pick_threads(nthreads);
+    (void)nt;
+    if (jstop > n) jstop = n;
+    double *row = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!row) return -1;
+    for (int64_t j = 0; j < jstop; ++j) {
+        double a = AT(A, lda, j, j);
+        if (!(a > 0.0)) {
+            free(row);
+            return (int)(j + 1);
+        }
+        double d = sqrt(a);
+        AT(A, lda, j, j) = d;
+        /* a12 := a12 / alpha11, and keep a copy of row j of U */
+        for (int64_t c = j + 1; c < n; ++c) {
+            AT(A, lda, j, c) = AT(A, lda, j, c) / d;
+            row[c] = AT(A, lda, j, c);
+        }
+        /* A22(i, c) -= U(j, i) * U(j, c) for j < i <= c (upper triangle) */
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
+        for (int64_t c = j + 1; c < n; ++c) {
+            double ujc = row[c];
+            double *col = &AT(A, lda, 0, c);
+            for (int64_t i = j + 1; i <= c; ++i) {
+                double p = row[i] * ujc;
+                col[i] = col[i] - p;
+            }
+        }
+    }
+    free(row);
+    return 0;
+}
+
+int oracle_potrf_upper(int64_t n, double *A, int64_t lda, int nthreads) {
+    return oracle_potrf_upper_steps(n, A, lda, n, nthreads);
+}
+
+/*
+ * X := triu(U)^{-T} X, U is b x b upper triangular, X is b x m.
+ * This is the TRSM of Fig. "dense-chol", A12 := triu(A11)^{-T} A12 (the figure
+ * prints ^{-1}; only the transposed solve satisfies A = U^T U, see the
+ * readings list).  Solves U^T X_new = X_old by forward substitution, row by
+ * row: x_s := x_s / U(s,s); then x_r -= U(s,r) * x_s for r > s.
+ */
+void oracle_trsm_upper_t(int64_t b, int64_t m, const double *U, int64_t ldu, double *X, int64_t ldx) {
+    for (int64_t c = 0; c < m; ++c) {
+        double *x = &AT(X, ldx, 0, c);
+        for (int64_t s = 0; s < b; ++s) {
+            x[s] = x[s] / AT(U, ldu, s, s);
+            for (int64_t r = s + 1; r < b; ++r) {
+                double p = AT(U, ldu, s, r) * x[s];
+                x[r] = x[r] - p;
+            }
+        }
+    }
+}
+
+/*
+ * C := C - P^T P on the upper triangle of the m x m matrix C; P is k x m.
+ * The HERK of Fig. "dense-chol" (real arithmetic: SYRK); off-diagonal blocks
+ * of the by-blocks form are the same formula (GEMM).  The k rank-1 terms are
+ * subtracted one by one in increasing row order of P.
+ */
+void oracle_syrk_upper(int64_t m, int64_t k, const double *P, int64_t ldp, double *C, int64_t ldc) {
+    for (int64_t j = 0; j < m; ++j)
+        for (int64_t i = 0; i <= j; ++i) {
+            double acc = AT(C, ldc, i, j);
+            for (int64_t r = 0; r < k; ++r) {
+                double p = AT(P, ldp, r, i) * AT(P, ldp, r, j);
+                acc = acc - p;
+            }
+            AT(C, ldc, i, j) = acc;
+        }
+}
+
+/*
+ * C := C - X^T Y, C is mr x nc (full), X is k x mr, Y is k x nc.
+ * Terms subtracted one by one in increasing row order of X and Y.
+ */
+void oracle_gemm_tn(int64_t mr, int64_t nc, int64_t k, const double *X, int64_t ldx, const double *Y,
+                    int64_t ldy, double *C, int64_t ldc) {
+    for (int64_t j = 0; j < nc; ++j)
+        for (int64_t i = 0; i < mr; ++i) {
+            double acc = AT(C, ldc, i, j);
+            for (int64_t r = 0; r < k; ++r) {
+                double p = AT(X, ldx, r, i) * AT(Y, ldy, r, j);
+                acc = acc - p;
+            }
+            AT(C, ldc, i, j) = acc;
+        }
+}
+
+/*
+ * O2: the blocked loop of Fig. "dense-chol" in FLAME partition/repartition
+ * form, for the three loop invariants of A = U^T U.  At iteration start A_TL is
+ * k x k; A11 is bk x bk with bk = min(b, n - k) (the "Determine block size b"
+ * step; the last block takes what is left).  With m = n - k - bk:
+ *
+ *   A00 = A(0:k, 0:k)      A01 = A(0:k, k:k+bk)      A02 = A(0:k, k+bk:n)
+ *                          A11 = A(k:k+bk, k:k+bk)   A12 = A(k:k+bk, k+bk:n)
+ *                                                    A22 = A(k+bk:n, k+bk:n)
+ *
+ * variant 3 (right-looking, the one the paper prints):
+ *   A11 := Chol(A11);  A12 := triu(A11)^{-T} A12;  A22 := A22 - A12^T A12
+ * variant 2 (left-looking):
+ *   A11 := A11 - A01^T A01;  A11 := Chol(A11);
+ *   A12 := A12 - A01^T A02;  A12 := triu(A11)^{-T} A12
+ * variant 1 (bordered):
+ *   A01 := triu(A00)^{-T} A01;  A11 := A11 - A01^T A01;  A11 := Chol(A11)
+ *
+ * `iters` < 0 runs to completion; otherwise the loop stops after that many
+ * iterations so a test can inspect the loop invariant.  Returns the LAPACK-style
+ * breakdown index (k + local index) or 0.
+ */
+int oracle_potrf_blocked(int64_t n, double *A, int64_t lda, int64_t b, int variant, int64_t iters) {
+    if (b <= 0) return -4;
+    int64_t it = 0;
+    for (int64_t k = 0; k < n; k += b) {
+        if (iters >= 0 && it >= iters) break;
+        ++it;
+        int64_t bk = (n - k < b) ? (n - k) : b;
+        int64_t m = n - k - bk;
+        double *A01 = &AT(A, lda, 0, k);
+        double *A02 = &AT(A, lda, 0, k + bk);
+        double *A11 = &AT(A, lda, k, k);
+        double *A12 = &AT(A, lda, k, k + bk);
+        double *A22 = &AT(A, lda, k + bk, k + bk);
+        const double *A00 = &AT(A, lda, 0, 0);
+        int info;
+        if (variant == 3) {
+            info = oracle_potrf_upper(bk, A11, lda, 1);
+            if (info) return (int)(k + info);
+            oracle_trsm_upper_t(bk, m, A11, lda, A12, lda);
+            oracle_syrk_upper(m, bk, A12, lda, A22, lda);
+        } else if (variant == 2) {
+            oracle_syrk_upper(bk, k, A01, lda, A11, lda);
+            info = oracle_potrf_upper(bk, A11, lda, 1);
+            if (info) return (int)(k + info);
+            oracle_gemm_tn(bk, m, k, A01, lda, A02, lda, A12, lda);
+            oracle_trsm_upper_t(bk, m, A11, lda, A12, lda);
+        } else if (variant == 1) {
+            oracle_trsm_upper_t(k, bk, A00, lda, A01, lda);
+            oracle_syrk_upper(bk, k, A01, lda, A11, lda);
+            info = oracle_potrf_upper(bk, A11, lda, 1);
+            if (info) return (int)(k + info);
+        } else {
+            return -5;
+        }
+    }
+    return 0;
+}
+
+/*
+ * O3: solve A X = B with A = U^T U, in place on B (n x nrhs): forward
+ * substitution U^T Y = B, then back substitution U X = Y, column by column.
+ * Terms are subtracted one by one in increasing (forward) or decreasing (back)
+ * index order.  The paper does not state a solve; it is the use of the factor
+ * (preconditioned iterative methods for SPD systems, Sec. "Introduction").
+ */
+void oracle_solve_upper(int64_t n, int64_t nrhs, const double *U, int64_t ldu, double *B, int64_t ldb) {
+    for (int64_t c = 0; c < nrhs; ++c) {
+        double *x = &AT(B, ldb, 0, c);
+        /* U^T y = b: y_r = (b_r - sum_{s<r} U(s,r) y_s) / U(r,r) */
+        for (int64_t r = 0; r < n; ++r) {
+            double acc = x[r];
+            for (int64_t s = 0; s < r; ++s) {
+                double p = AT(U, ldu, s, r) * x[s];
+                acc = acc - p;
+            }
+            x[r] = acc / AT(U, ldu, r, r);
+        }
+        /* U x = y: x_r = (y_r - sum_{s>r} U(r,s) x_s) / U(r,r) */
+        for (int64_t r = n - 1; r >= 0; --r) {
+            double acc = x[r];
+            for (int64_t s = n - 1; s > r; --s) {
+                double p = AT(U, ldu, r, s) * x[s];
+                acc = acc - p;
+            }
+            x[r] = acc / AT(U, ldu, r, r);
+        }
+    }
+}
