@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""Benchmark of the blocked Cholesky A = U^T U (Fig. "dense-chol") on one
+MI355X.
+
+A step is one FP64 factorization of the n = 16384 SPD matrix A = B B^T + n I
+(B ~ N(0,1), PCG64 seed), right-looking loop, block size 128, lookahead.
+Each timed step factors its own pre-generated copy already resident in HBM,
+so the timed region holds nothing but the K factorizations.  Prints one JSON
+line with GFLOP/s (potrf flop count n^3/3 + n^2/2 + n/6), the live roofline of
+the dominant kernel (the trailing SYRK/GEMM, from per-launch HIP events), the
+mixed-precision time to solution against the FP64 path at equal backward
+error, and the CPU oracle's rate on the host cores.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GFLOP/s & %MFMA peak at n=16384, mixed vs FP64, equal backward err"
+PEAK_F64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+PEAK_F32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def potrf_flops(n: int) -> float:
+    return float(n * (n + 1) * (2 * n + 1) // 6)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--nb", type=int, default=128)
+    ap.add_argument("--variant", type=int, default=3)
+    ap.add_argument("--lookahead", type=int, default=1)
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--kappa", type=float, default=1e4)
+    ap.add_argument("--trail", default="f32")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the factorization of one matrix is measured on a single "
+              "MI355X (no collectives in this build); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    import inputs
+    import paper_1601_05871_amd as fl
+
+    fl.lib()  # fails loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, K, W = args.n, max(1, args.steps), max(0, args.warmup)
+    log(f"generating A = B B^T + n I, n={n}, seed={args.seed}")
+    P = inputs.spd_bbt_torch(n, args.seed, dev)  # pristine, column-major
+    copies = [torch.empty_strided((n, n), (1, n), dtype=torch.float64, device=dev) for _ in range(K)]
+    infos = torch.zeros(K, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def factor(M, info):
+        return fl.factor(M, variant=args.variant, nb=args.nb, lookahead=args.lookahead, graph=args.graph, info=info)
+
+    log(f"warmup x{W}")
+    for _ in range(W):
+        copies[0].copy_(P)
+        factor(copies[0], infos[0:1])
+    for c in copies:
+        c.copy_(P)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K factorizations, inputs resident in HBM -------------
+    log(f"timing {K} factorizations")
+    fl.trace_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(K):
+        factor(copies[i], infos[i:i + 1])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    ev_ms = ev0.elapsed_time(ev1)
+    trace = fl.trace_collect()
+    fl.trace_enable(False)
+    ms_per_step = ev_ms / K
+    info_h = infos.cpu().numpy()
+    if np.any(info_h != 0):
+        log(f"factorization reported breakdown: {info_h}")
+        return 1
+    gflops = potrf_flops(n) / (ms_per_step * 1e-3) / 1e9
+    log(f"{ms_per_step:.3f} ms/factorization = {gflops:.1f} GFLOP/s (wall {wall_ms / K:.3f} ms)")
+
+    # dominant kernel: the trailing update (SYRK/GEMM on FP64 matrix cores)
+    g = trace["gemm"]
+    gemm_tflops = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    roofline = {
+        "kernel": "k_gemm_tn<F64> (trailing SYRK/GEMM)",
+        "bound": "mfma",
+        "achieved": round(gemm_tflops, 3),
+        "peak": PEAK_F64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(gemm_tflops / PEAK_F64_TFLOPS, 4),
+        "traffic": None,
+        "launches_per_step": g["launches"] / K,
+        "avg_launch_ms": g["ms"] / max(1, g["launches"]),
+        "avg_launch_gflop": g["flops"] / max(1, g["launches"]) / 1e9,
+    }
+    breakdown = {k: {"launches": v["launches"] // K, "ms": round(v["ms"] / K, 4),
+                     "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] > 0 else None}
+                 for k, v in trace.items()}
+
+    # ---- accuracy of the timed result (randomized backward-error estimate) --
+    log("backward error of the FP64 factor")
+    beta = factor_backward_error_est(P, copies[0])
+
+    result = {
+        "metric": METRIC,
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"dense SPD Cholesky n={n} FP64, A = B B^T + n I (B ~ N(0,1), PCG64 seed {args.seed})",
+            "n": n, "nb": args.nb, "variant": {1: "bordered", 2: "left-looking", 3: "right-looking"}[args.variant],
+            "lookahead": bool(args.lookahead), "graph": bool(args.graph),
+        },
+        "pct_fp64_mfma_peak": round(100.0 * gflops / (PEAK_F64_TFLOPS * 1e3), 2),
+        "beta_F": beta,
+        "roofline": roofline,
+        "kernels_per_step": breakdown,
+    }
+    del copies
+    torch.cuda.empty_cache()
+
+    if not args.no_mixed:
+        result["mixed"] = mixed_leg(args, n, dev, fl, inputs, torch)
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_leg(P, n, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def factor_backward_error_est(A_dev, U_dev, k: int = 8, seed: int = 0) -> float:
+    """||(A - U^T U) X||_F / (||A||_F ||X||_F) for X n x k N(0,1), formed on
+    the host in FP64 numpy (A from its upper triangle)."""
+    A = A_dev.cpu().numpy()
+    U = np.triu(U_dev.cpu().numpy())
+    n = A.shape[0]
+    X = np.random.Generator(np.random.PCG64(seed)).standard_normal((n, k))
+    Au = np.triu(A)
+    AX = Au @ X + np.triu(A, 1).T @ X
+    R = AX - U.T @ (U @ X)
+    nA = np.sqrt(2.0 * np.sum(Au * Au) - np.sum(np.diag(A) ** 2))
+    return float(np.linalg.norm(R) / (nA * np.linalg.norm(X)))
+
+
+def mixed_leg(args, n, dev, fl, inputs, torch):
+    """Time to solution of A0 x = b (kappa = args.kappa, one right-hand side)
+    at backward error <= 1e-13: FP64 factor + solve vs low-precision trailing
+    updates + FP64 iterative refinement, on the same A0 and b."""
+    log(f"mixed leg: generating A0 = Q diag(s) Q^T, kappa={args.kappa:g}")
+    A0 = inputs.spd_kappa_torch(n, args.kappa, args.seed, dev)
+    b = torch.from_numpy(inputs.rhs(n, 1, args.seed)).to(dev)
+    b = b.as_strided((n, 1), (1, n))
+    W = torch.empty_strided((n, n), (1, n), dtype=torch.float64, device=dev)
+    x = torch.empty_strided((n, 1), (1, n), dtype=torch.float64, device=dev)
+    out = {"kappa": args.kappa, "nrhs": 1, "tol": 1e-13}
+    stream = torch.cuda.current_stream()
+
+    def run(trail: str):
+        W.copy_(A0)
+        x.copy_(b)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        info = fl.factor(W, variant=3, nb=args.nb if trail == "native" else 256, trail=trail,
+                         lookahead=args.lookahead)
+        if trail == "native":
+            fl.solve(W, x)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rep = {"iters": 0, "status": 0}
+        else:
+            rep = fl.solve(W, x, A0=A0, tol=1e-13, max_iter=50)
+            e1.record(stream)
+            torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        wall = (time.perf_counter() - t0) * 1e3
+        eta = solve_backward_error_dev(A0, x, b, torch)
+        return {"ms": round(ms, 3), "wall_ms": round(wall, 3), "eta": eta, "info": int(info.item()),
+                "iters": rep["iters"], "status": rep["status"]}
+
+    for trail in ("native", args.trail):
+        log(f"mixed leg: {trail}")
+        run(trail)  # warm-up (graph-free; workspace allocation)
+        out[trail] = run(trail)
+    base, mix = out["native"], out[args.trail]
+    out["trail"] = args.trail
+    out["speedup_vs_fp64"] = round(base["ms"] / mix["ms"], 3) if mix["ms"] > 0 else None
+    out["equal_backward_error"] = bool(base["eta"] <= 1e-13 and mix["eta"] <= 1e-13)
+    return out
+
+
+def solve_backward_error_dev(A0, x, b, torch) -> float:
+    """eta = ||b - A0 x||_inf / (||A0||_inf ||x||_inf + ||b||_inf) with torch
+    FP64 on the device (measurement only; A0 symmetric from its upper part)."""
+    Au = torch.triu(A0)
+    S = Au + torch.triu(A0, 1).T
+    r = b - S @ x
+    nA = torch.max(torch.sum(torch.abs(S), dim=1))
+    val = torch.max(torch.abs(r)) / (nA * torch.max(torch.abs(x)) + torch.max(torch.abs(b)))
+    del S, Au
+    return float(val.item())
+
+
+def cpu_leg(P, n: int, seconds: float):
+    """The CPU oracle (plain unblocked FP64 loop, OpenMP over columns) on the
+    host cores, timed on the first J pivot steps of the same n x n matrix
+    (J chosen for ~`seconds` of work); rate = the algorithmic flops of those
+    steps / time."""
+    import oracle
+
+    log("cpu baseline: oracle on the host cores")
+    A = np.asfortranarray(P.cpu().numpy())
+    threads = oracle.max_threads()
+
+    def step_flops(j0: int, j1: int) -> float:
+        f = 0.0
+        for j in range(j0, j1):
+            r = n - j - 1
+            f += 1 + r + r * (r + 1)  # sqrt, r divisions, r(r+1)/2 multiply-subtract pairs
+        return f
+
+    W = A.copy(order="F")
+    t0 = time.perf_counter()
+    oracle.potrf_inplace(W, n, n, threads=0, steps=2)
+    t_probe = time.perf_counter() - t0
+    J = int(max(2, min(n, 2 * seconds / max(t_probe, 1e-6))))
+    W = A.copy(order="F")
+    t0 = time.perf_counter()
+    oracle.potrf_inplace(W, n, n, threads=0, steps=J)
+    t = time.perf_counter() - t0
+    fl = step_flops(0, J)
+    return {"value": round(fl / t / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {J} of {n} pivot steps of the unblocked oracle on the same n={n} matrix "
+                      f"({fl / 1e9:.1f} GFLOP, {t:.1f} s)"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

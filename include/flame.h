@@ -1,0 +1,245 @@
+/*
+ * flame.h -- C ABI of the MI355X (gfx950) blocked Cholesky library.
+ *
+ * Operation: A := Chol(A) for a symmetric positive definite A, in place, with
+ * A = U^T U and U upper triangular with a positive diagonal.  This is the
+ * blocked algorithm of Kim et al., "Task Parallel Incomplete Cholesky
+ * Factorization using 2D Partitioned-Block Layout" (arXiv 1601.05871),
+ * Fig. "dense-chol" (A11 := Chol(A11); A12 := triu(A11)^{-T} A12;
+ * A22 := A22 - A12^T A12), and the two other loop invariants of the same
+ * partitioned matrix expression (bordered, left-looking).
+ *
+ * Conventions for every entry point:
+ *   - matrices are column-major: element (i, j) of A is A[i + j*lda];
+ *   - only the upper triangle (i <= j) of a symmetric operand is read; only
+ *     the upper triangle of A is written; the strictly lower triangle is never
+ *     referenced;
+ *   - pointers are DEVICE pointers unless marked "host"; the caller owns all
+ *     memory it passes and the library never frees it;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream);
+ *     work is enqueued on it and the call returns without synchronizing,
+ *     except where a function says otherwise;
+ *   - return value: 0 = enqueued; -i = argument i (1-based) is invalid, checked
+ *     on the host before anything is enqueued; > 0 = a FLAME_ERR_* code.
+ *   - numerical breakdown is not a return code: it is written to the device
+ *     `info` (LAPACK potrf convention): 0 = success; j > 0 = the leading j x j
+ *     minor is not positive definite (the first pivot that is not > 0, or NaN,
+ *     is at 1-based column j).  The upper triangle then holds partial results
+ *     (unspecified); the lower triangle is still untouched.
+ */
+#ifndef FLAME_H
+#define FLAME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define FLAME_OK 0
+#define FLAME_ERR_HIP 1           /* a HIP runtime call failed (see flame_status_string) */
+#define FLAME_ERR_NOMEM 2         /* device workspace allocation failed */
+#define FLAME_ERR_NOT_CONVERGED 3 /* refinement reached max_iter above tol */
+#define FLAME_ERR_UNSUPPORTED 4   /* valid but unsupported combination */
+
+/* ---- enumerations ------------------------------------------------------- */
+typedef enum { FLAME_F64 = 0, FLAME_F32 = 1 } flame_dtype_t;
+
+/* The three loop invariants of A = U^T U after A_TL (k x k) is processed:
+ *   BORDERED (1): A_TL = U_TL;                       A_TR, A_BR untouched
+ *   LEFT     (2): A_TL = U_TL, A_TR = U_TR;          A_BR untouched
+ *   RIGHT    (3): A_TL = U_TL, A_TR = U_TR, A_BR = A_BR - U_TR^T U_TR
+ * RIGHT is the loop the paper prints (Fig. "dense-chol").  AUTO (0) lets the
+ * library choose (learned selector, else autotuner table, else RIGHT). */
+typedef enum {
+    FLAME_VAR_AUTO = 0,
+    FLAME_VAR_BORDERED = 1,
+    FLAME_VAR_LEFT = 2,
+    FLAME_VAR_RIGHT = 3
+} flame_variant_t;
+
+/* Arithmetic of the trailing update A22 := A22 - A12^T A12 (RIGHT variant).
+ * NATIVE: the matrix dtype.  F32 / BF16 (FP64 matrices only): A12 is rounded
+ * to FP32 / BF16 (round to nearest even) after its FP64 TRSM, the product is
+ * formed on FP32 / BF16 matrix cores with FP32 accumulation and subtracted
+ * from the FP64 A22 in FP64.  The diagonal-block factorization and the TRSM
+ * stay FP64.  The result is a lower-accuracy factor meant for
+ * flame_solve with refinement. */
+typedef enum { FLAME_TRAIL_NATIVE = 0, FLAME_TRAIL_F32 = 1, FLAME_TRAIL_BF16 = 2 } flame_trail_t;
+
+/* Options; a NULL pointer means all zeros (= defaults). */
+typedef struct {
+    int32_t variant;   /* flame_variant_t; 0 = choose */
+    int32_t nb;        /* block size b (A11 is b x b, the last block min(b, n-k));
+                          0 = choose; valid range 1..256 */
+    int32_t trail;     /* flame_trail_t */
+    int32_t lookahead; /* RIGHT variant: 0 = default (on), 1 = on, -1 = off.
+                          On: the next diagonal block and panel are updated first
+                          and factored on a second stream while the rest of the
+                          trailing update runs. */
+    int32_t graph;     /* 0 = default (off), 1 = capture the loop once per
+                          (n, lda, A, info, options, stream) in a HIP graph and
+                          replay it on later calls with the same key */
+    int32_t reserved[3];
+} flame_opts_t;
+
+/* ---- factorization ------------------------------------------------------ */
+
+/* A := Chol(A) (Fig. "dense-chol"), in place, upper triangle.
+ *   dtype  FLAME_F64 (A is double*) or FLAME_F32 (A is float*)
+ *   n      order of A, n >= 0
+ *   A      device, column-major, lda x n, upper triangle read and overwritten
+ *   lda    >= max(1, n)
+ *   opts   host, may be NULL
+ *   info   device, one int32, written asynchronously (see above)
+ *   stream hipStream_t or NULL
+ * Errors: -1 dtype, -2 n, -3 A (NULL with n > 0), -4 lda, -5 opts (bad field),
+ * -6 info (NULL); FLAME_ERR_UNSUPPORTED for trail != NATIVE with dtype F32 or
+ * with variant != RIGHT. */
+int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opts_t *opts, int32_t *info,
+                 void *stream);
+
+/* ---- solve and iterative refinement ----------------------------------- */
+
+typedef struct {
+    const double *A0; /* device, the original FP64 matrix (upper triangle read), lda0 x n */
+    int64_t lda0;     /* >= max(1, n) */
+    double tol;       /* stop when eta <= tol (e.g. 1e-13) */
+    int32_t max_iter; /* correction steps allowed (>= 0) */
+    int32_t reserved;
+} flame_refine_t;
+
+typedef struct {
+    int32_t iters;  /* correction steps taken */
+    int32_t reserved;
+    double eta_max; /* final normwise backward error, max over the columns:
+                       ||b - A0 x||_inf / (||A0||_inf ||x||_inf + ||b||_inf) */
+} flame_solve_report_t;
+
+/* Solves A X = B with A = U^T U from flame_factor: U^T Y = B, then U X = Y.
+ *   dtype  FLAME_F64 or FLAME_F32 (U and B of that type); refinement needs F64
+ *   n      order, >= 0;  nrhs  number of right-hand sides, >= 0
+ *   U      device, the factor (upper triangle), ldu x n
+ *   B      device, n x nrhs, ldb >= max(1, n); overwritten with X
+ *   refine host, NULL = one plain solve.  Otherwise: x = solve(U, b); then
+ *          repeat { r = b - A0 x (FP64); eta = ...; stop if eta <= tol;
+ *          d = solve(U, r); x = x + d } at most max_iter corrections.  Each
+ *          step reads eta back to the host, so this call synchronizes the
+ *          stream.  Returns FLAME_ERR_NOT_CONVERGED (X holds the last iterate,
+ *          report the last eta) if eta > tol after max_iter corrections.
+ *   report host, may be NULL; filled when refine is given.
+ * Errors: -1 dtype, -2 n, -3 nrhs, -4 U, -5 ldu, -6 B, -7 ldb, -8 refine. */
+int flame_solve(int32_t dtype, int64_t n, int64_t nrhs, const void *U, int64_t ldu, void *B, int64_t ldb,
+                const flame_refine_t *refine, flame_solve_report_t *report, void *stream);
+
+/* ---- batched factorization ---------------------------------------------- */
+
+/* Factors `batch` independent matrices A_i := Chol(A_i) in one persistent
+ * kernel launch (replayed from a HIP graph after the first call with the same
+ * arguments).  All arrays are device arrays of length `batch`:
+ *   n[i]    order of A_i, 0 <= n[i] <= 1024 (larger: info[i] = -1, untouched)
+ *   A[i]    device pointer to A_i (column-major), dtype as given
+ *   lda[i]  >= max(1, n[i]) (else info[i] = -1)
+ *   info[i] per-matrix breakdown index (as for flame_factor)
+ *   opts    host, may be NULL (nb is ignored; variant must be AUTO or RIGHT)
+ * A breakdown in one matrix leaves every other matrix's result unaffected.
+ * Errors: -1 dtype, -2 batch (< 0), -3 n, -4 A, -5 lda, -6 info, -7 opts. */
+int flame_batched_factor(int32_t dtype, int32_t batch, const int32_t *n, void *const *A, const int32_t *lda,
+                         int32_t *info, const flame_opts_t *opts, void *stream);
+
+/* ---- block operations of the loop body (Fig. "dense-chol") ------------- */
+/* Exposed so each kernel of the loop can be checked on its own.  Same
+ * conventions as above; `dtype` selects double or float operands. */
+
+/* A := Chol(A) for one diagonal block, 0 <= n <= 256, one kernel.  Breakdown
+ * writes info = info_base + j (j the 1-based local column) if *info == 0.
+ * Errors: -1 dtype, -2 n, -3 A, -4 lda, -5 info. */
+int flame_op_chol(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, int64_t info_base,
+                  void *stream);
+
+/* X := triu(U)^{-T} X: U is b x b (upper triangle read), X is b x m,
+ * 0 <= b <= 256.  Errors: -1 dtype, -2 b, -3 m, -4 U, -5 ldu, -6 X, -7 ldx. */
+int flame_op_trsm(int32_t dtype, int64_t b, int64_t m, const void *U, int64_t ldu, void *X, int64_t ldx,
+                  void *stream);
+
+/* C := C - X^T Y on the upper triangle (i <= j) if `upper`, else on all of C.
+ * C is mr x nc, X is k x mr, Y is k x nc (columns of X and Y contiguous in k).
+ * With X == Y and mr == nc this is the SYRK/HERK step.  `trail` selects the
+ * product arithmetic for dtype F64 as in flame_trail_t; for F32 / BF16 the
+ * operands X, Y are float / bfloat16 (uint16 storage) and C is double.
+ * Errors: -1 dtype, -2 trail, -3 mr, -4 nc, -5 k, -6 X, -7 ldx, -8 Y, -9 ldy,
+ * -10 C, -11 ldc. */
+int flame_op_gemm_tn(int32_t dtype, int32_t trail, int32_t upper, int64_t mr, int64_t nc, int64_t k,
+                     const void *X, int64_t ldx, const void *Y, int64_t ldy, void *C, int64_t ldc,
+                     void *stream);
+
+/* ---- selector and autotuner ---------------------------------------------- */
+
+/* Loads the weights of the learned (variant, nb) selector: a 3-layer FP32 MLP
+ * in -> 64 -> 64 -> FLAME_SEL_CLASSES with ReLU, features (log2 n, log2 batch,
+ * is_f64, is_f32, log10 kappa), classes = variant in {1,2,3} x nb in
+ * {32,64,128,256} (class c -> variant 1 + c / 4, nb = 32 << (c % 4)).
+ * `w` (host) holds W1[64][5], b1[64], W2[64][64], b2[64], W3[12][64], b3[12],
+ * row-major, count = FLAME_SEL_NPARAM floats.  Copied to the device.
+ * Errors: -1 w, -2 count. */
+#define FLAME_SEL_FEATURES 5
+#define FLAME_SEL_HIDDEN 64
+#define FLAME_SEL_CLASSES 12
+#define FLAME_SEL_NPARAM (64 * 5 + 64 + 64 * 64 + 64 + 12 * 64 + 12)
+int flame_selector_load(const float *w, int64_t count);
+
+/* Runs the selector's inference kernel for one shape; returns (variant, nb)
+ * in host memory.  Synchronous.  Without loaded weights returns
+ * FLAME_ERR_UNSUPPORTED.  Errors: -1 n, -2 batch, -3 dtype, -4 kappa,
+ * -5 variant, -6 nb. */
+int flame_select(int64_t n, int64_t batch, int32_t dtype, double kappa, int32_t *variant, int32_t *nb);
+
+/* Batch inference: `count` feature rows (host, count x FLAME_SEL_FEATURES)
+ * -> class logits (host, count x FLAME_SEL_CLASSES).  Synchronous. */
+int flame_select_logits(const float *features, int64_t count, float *logits);
+
+/* Exhaustive autotuner: times every candidate (variant in {1,2,3} x nb in
+ * {32,64,128,256}) for an n x n factorization of `dtype` on a scratch copy of
+ * A (A itself is restored), `reps` timed runs each after one warm-up, and
+ * writes the median milliseconds per candidate to times_ms (host, 12 doubles,
+ * class order as for the selector; a failed candidate gets +inf).  Records the
+ * best candidate in the library's tuning table used by VAR_AUTO.
+ * Synchronous.  Errors: -1 dtype, -2 n, -3 A, -4 lda, -5 reps, -6 times_ms. */
+int flame_autotune(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t reps, double *times_ms,
+                   void *stream);
+
+/* ---- per-kernel timing (instrumentation) --------------------------------- */
+
+/* Kernel classes of the loop body. */
+#define FLAME_KC_CHOL 0  /* diagonal block, A11 := Chol(A11) */
+#define FLAME_KC_TRSM 1  /* panel, A12 := triu(A11)^{-T} A12 */
+#define FLAME_KC_GEMM 2  /* trailing update, C := C - X^T Y (SYRK/HERK and GEMM) */
+#define FLAME_KC_OTHER 3 /* solves, residuals, casts, fills */
+#define FLAME_KC_COUNT 4
+
+/* Instrumentation, not part of the factorization.  While enabled (on != 0),
+ * every kernel launch made by this library on the calling thread is
+ * bracketed with HIP events on the stream it is launched on, and its
+ * algorithmic work is recorded: flops (a trailing update of an M x N block
+ * with inner dimension K counts 2*K per updated element) and bytes (each
+ * operand element read once plus each result element written once).
+ * Enabling clears previous records.  Not available inside a HIP graph
+ * capture (graph replays are not recorded).  Errors: none. */
+int flame_trace_enable(int32_t on);
+
+/* Synchronizes the recorded events and sums them per kernel class: launches,
+ * milliseconds (sum of per-launch event durations), flops and bytes (host
+ * arrays of FLAME_KC_COUNT entries each; any may be NULL).
+ * Errors: FLAME_ERR_HIP if an event query fails. */
+int flame_trace_collect(int64_t *launches, double *ms, double *flops, double *bytes);
+
+/* ---- status -------------------------------------------------------------- */
+const char *flame_status_string(int status);
+const char *flame_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLAME_H */

@@ -1,0 +1,255 @@
+"""MI355X (gfx950) blocked Cholesky A = U^T U (arXiv 1601.05871,
+Fig. "dense-chol" and its derived loop invariants).
+
+Thin ctypes binding over ``libflame.so`` (declared in ``include/flame.h``):
+argument marshalling only -- every step of the factorization, solve and
+refinement runs in the library's HIP kernels.  PyTorch supplies device memory
+and the current stream.  Importing this module does not load the library;
+the first call does, and raises if it has not been built (there is no CPU
+fallback).
+
+Matrices are column-major: a 2-D torch tensor ``A`` with ``A.stride(0) == 1``
+and ``A.stride(1) == lda >= n`` (for a contiguous row-major tensor pass
+``A.mT``, or use :func:`colmajor`).  Only the upper triangle is read/written.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libflame.so")
+
+F64, F32 = 0, 1
+VAR_AUTO, VAR_BORDERED, VAR_LEFT, VAR_RIGHT = 0, 1, 2, 3
+TRAIL = {"native": 0, "f32": 1, "bf16": 2}
+FLAME_OK, FLAME_ERR_HIP, FLAME_ERR_NOMEM, FLAME_ERR_NOT_CONVERGED, FLAME_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+
+SEL_FEATURES, SEL_HIDDEN, SEL_CLASSES = 5, 64, 12
+SEL_NPARAM = 64 * 5 + 64 + 64 * 64 + 64 + 12 * 64 + 12
+
+# every symbol include/flame.h declares
+EXPORTS = (
+    "flame_factor", "flame_solve", "flame_batched_factor", "flame_op_chol", "flame_op_trsm",
+    "flame_op_gemm_tn", "flame_selector_load", "flame_select", "flame_select_logits", "flame_autotune",
+    "flame_trace_enable", "flame_trace_collect", "flame_status_string", "flame_version",
+)
+KC_CHOL, KC_TRSM, KC_GEMM, KC_OTHER = 0, 1, 2, 3
+
+
+class FlameError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        self.status = status
+        super().__init__(f"{fn} returned {status}: {status_string(status)}")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("nb", ctypes.c_int32), ("trail", ctypes.c_int32),
+                ("lookahead", ctypes.c_int32), ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class Refine(ctypes.Structure):
+    _fields_ = [("A0", ctypes.c_void_p), ("lda0", ctypes.c_int64), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("reserved", ctypes.c_int32), ("eta_max", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libflame.so (built by ``python -m paper_1601_05871_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_05871_amd.build` "
+                           "(the HIP library is required; there is no fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
+    L.flame_factor.argtypes = [i32, i64, vp, i64, ctypes.POINTER(Opts), vp, vp]
+    L.flame_solve.argtypes = [i32, i64, i64, vp, i64, vp, i64, ctypes.POINTER(Refine),
+                              ctypes.POINTER(SolveReport), vp]
+    L.flame_batched_factor.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.POINTER(Opts), vp]
+    L.flame_op_chol.argtypes = [i32, i64, vp, i64, vp, i64, vp]
+    L.flame_op_trsm.argtypes = [i32, i64, i64, vp, i64, vp, i64, vp]
+    L.flame_op_gemm_tn.argtypes = [i32, i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp]
+    L.flame_selector_load.argtypes = [vp, i64]
+    L.flame_select.argtypes = [i64, i64, i32, dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.flame_select_logits.argtypes = [vp, i64, vp]
+    L.flame_autotune.argtypes = [i32, i64, vp, i64, i32, vp, vp]
+    L.flame_trace_enable.argtypes = [i32]
+    L.flame_trace_collect.argtypes = [vp, vp, vp, vp]
+    L.flame_status_string.argtypes = [ctypes.c_int]
+    L.flame_status_string.restype = ctypes.c_char_p
+    L.flame_version.argtypes = []
+    L.flame_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("flame_status_string", "flame_version"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    return lib().flame_status_string(int(status)).decode()
+
+
+def version() -> str:
+    return lib().flame_version().decode()
+
+
+def _check(fn: str, rc: int, ok=(FLAME_OK,)) -> int:
+    if rc not in ok:
+        raise FlameError(fn, rc)
+    return rc
+
+
+# ---- torch marshalling ------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr() -> int:
+    torch = _torch()
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype} (float64 or float32)")
+
+
+def _colmajor_ld(t, rows: int | None = None) -> int:
+    """Leading dimension of a column-major 2-D device tensor."""
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if not t.is_cuda:
+        raise ValueError("expected a device (HIP) tensor")
+    r, c = t.shape
+    if c > 1 and r > 1 and t.stride(0) != 1:
+        raise ValueError("expected column-major strides (1, lda); pass A.mT of a contiguous tensor")
+    ld = t.stride(1) if c > 1 else max(r, 1)
+    return max(int(ld), max(1, r))
+
+
+def colmajor(t):
+    """A column-major copy (or view) of a 2-D tensor with the same values."""
+    return t.mT.contiguous().mT
+
+
+def _opts(variant, nb, trail, lookahead, graph) -> Opts:
+    o = Opts()
+    o.variant = int(variant)
+    o.nb = int(nb)
+    o.trail = TRAIL[trail] if isinstance(trail, str) else int(trail)
+    o.lookahead = int(lookahead)
+    o.graph = int(graph)
+    return o
+
+
+def factor(A, variant: int = VAR_RIGHT, nb: int = 128, trail="native", lookahead: int = 0, graph: int = 0,
+           info=None):
+    """A := Chol(A) in place (upper triangle).  Returns the device int32
+    ``info`` tensor (0, or the 1-based column of the first non-positive pivot).
+    Asynchronous on the current stream."""
+    torch = _torch()
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    lda = _colmajor_ld(A)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    o = _opts(variant, nb, trail, lookahead, graph)
+    rc = lib().flame_factor(_dtype_code(A), n, A.data_ptr(), lda, ctypes.byref(o), info.data_ptr(), _stream_ptr())
+    _check("flame_factor", rc)
+    return info
+
+
+def solve(U, B, A0=None, tol: float = 1e-13, max_iter: int = 30):
+    """Solves A X = B in place on B (column-major, n x nrhs) with A = U^T U.
+    With ``A0`` (the original FP64 matrix) runs FP64 iterative refinement and
+    returns the report (iters, eta_max) and the status; otherwise returns
+    None.  Refinement synchronizes the stream."""
+    n = U.shape[0]
+    nrhs = B.shape[1]
+    ldu = _colmajor_ld(U)
+    ldb = _colmajor_ld(B)
+    dt = _dtype_code(U)
+    if B.dtype != U.dtype:
+        raise TypeError("U and B must have the same dtype")
+    if A0 is None:
+        rc = lib().flame_solve(dt, n, nrhs, U.data_ptr(), ldu, B.data_ptr(), ldb, None, None, _stream_ptr())
+        _check("flame_solve", rc)
+        return None
+    ref = Refine()
+    ref.A0 = A0.data_ptr()
+    ref.lda0 = _colmajor_ld(A0)
+    ref.tol = float(tol)
+    ref.max_iter = int(max_iter)
+    rep = SolveReport()
+    rc = lib().flame_solve(dt, n, nrhs, U.data_ptr(), ldu, B.data_ptr(), ldb, ctypes.byref(ref), ctypes.byref(rep),
+                           _stream_ptr())
+    _check("flame_solve", rc, ok=(FLAME_OK, FLAME_ERR_NOT_CONVERGED))
+    return {"iters": rep.iters, "eta": rep.eta_max, "status": rc}
+
+
+def batched_factor(ns, ptrs, ldas, info, dtype=F64, opts: Opts | None = None):
+    """Factors len(ns) matrices in one launch.  ``ns``, ``ldas``, ``info``:
+    device int32 tensors; ``ptrs``: device int64 tensor of matrix addresses."""
+    rc = lib().flame_batched_factor(int(dtype), int(ns.numel()), ns.data_ptr(), ptrs.data_ptr(), ldas.data_ptr(),
+                                    info.data_ptr(), ctypes.byref(opts) if opts is not None else None,
+                                    _stream_ptr())
+    _check("flame_batched_factor", rc)
+    return info
+
+
+def trace_enable(on: bool = True) -> None:
+    """Per-launch HIP-event timing of the library's kernels (instrumentation)."""
+    _check("flame_trace_enable", lib().flame_trace_enable(int(bool(on))))
+
+
+def trace_collect() -> dict:
+    """Per kernel class: launches, ms, flops, bytes (synchronizes)."""
+    arr_i = (ctypes.c_int64 * 4)()
+    ms, fl_, by = (ctypes.c_double * 4)(), (ctypes.c_double * 4)(), (ctypes.c_double * 4)()
+    _check("flame_trace_collect", lib().flame_trace_collect(arr_i, ms, fl_, by))
+    names = ("chol", "trsm", "gemm", "other")
+    return {names[k]: {"launches": int(arr_i[k]), "ms": ms[k], "flops": fl_[k], "bytes": by[k]} for k in range(4)}
+
+
+# ---- block operations of the loop body -------------------------------------
+
+def op_chol(A, info, info_base: int = 0):
+    rc = lib().flame_op_chol(_dtype_code(A), A.shape[0], A.data_ptr(), _colmajor_ld(A), info.data_ptr(),
+                             int(info_base), _stream_ptr())
+    _check("flame_op_chol", rc)
+
+
+def op_trsm(U, X):
+    rc = lib().flame_op_trsm(_dtype_code(U), X.shape[0], X.shape[1], U.data_ptr(), _colmajor_ld(U), X.data_ptr(),
+                             _colmajor_ld(X), _stream_ptr())
+    _check("flame_op_trsm", rc)
+
+
+def op_gemm_tn(C, X, Y, upper: bool, trail="native", dtype=None):
+    """C := C - X^T Y (upper triangle only if ``upper``).  For trail 'f32' /
+    'bf16' X and Y are float32 / bfloat16 tensors and C is float64."""
+    torch = _torch()
+    k = X.shape[0]
+    if dtype is None:
+        dtype = F32 if (C.dtype == torch.float32) else F64
+    tr = TRAIL[trail] if isinstance(trail, str) else int(trail)
+    rc = lib().flame_op_gemm_tn(int(dtype), tr, int(bool(upper)), C.shape[0], C.shape[1], k, X.data_ptr(),
+                                _colmajor_ld(X), Y.data_ptr(), _colmajor_ld(Y), C.data_ptr(), _colmajor_ld(C),
+                                _stream_ptr())
+    _check("flame_op_gemm_tn", rc)

@@ -1,0 +1,135 @@
+// C ABI entry points (include/flame.h): host-side argument checks, option
+// defaults, dispatch.  Nothing is enqueued when a check fails.
+#include <cmath>
+#include <cstring>
+
+#include "flame_internal.h"
+
+using namespace flame;
+
+namespace {
+
+constexpr int kMaxNb = 256;
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+// Fills defaults; returns 0 or -5 (bad option field).
+int normalize_opts(const flame_opts_t *in, int32_t dtype, int64_t n, flame_opts_t *o) {
+    if (in != nullptr)
+        *o = *in;
+    else
+        std::memset(o, 0, sizeof(*o));
+    if (o->variant < FLAME_VAR_AUTO || o->variant > FLAME_VAR_RIGHT) return -5;
+    if (o->nb < 0 || o->nb > kMaxNb) return -5;
+    if (o->trail < FLAME_TRAIL_NATIVE || o->trail > FLAME_TRAIL_BF16) return -5;
+    if (o->lookahead < -1 || o->lookahead > 1) return -5;
+    if (o->graph < 0 || o->graph > 1) return -5;
+    if (o->variant == FLAME_VAR_AUTO) {
+        int32_t v = FLAME_VAR_RIGHT, nb = 0;
+        if (flame_select(n, 1, dtype, 0.0, &v, &nb) != FLAME_OK) {
+            v = FLAME_VAR_RIGHT;
+            nb = 0;
+        }
+        o->variant = v;
+        if (o->nb == 0) o->nb = nb;
+    }
+    if (o->nb == 0) o->nb = 128;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opts_t *opts, int32_t *info,
+                 void *stream) {
+    if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
+    if (n < 0 || n > ((int64_t)1 << 31) - 1) return -2;
+    if (A == nullptr && n > 0) return -3;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (info == nullptr) return -6;
+    flame_opts_t o;
+    int rc = normalize_opts(opts, dtype, n, &o);
+    if (rc) return rc;
+    if (o.trail != FLAME_TRAIL_NATIVE && (dtype != FLAME_F64 || o.variant != FLAME_VAR_RIGHT))
+        return FLAME_ERR_UNSUPPORTED;
+    return factor_dispatch(dtype, n, A, lda, o, info, as_stream(stream));
+}
+
+int flame_op_chol(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, int64_t info_base, void *stream) {
+    if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
+    if (n < 0 || n > kMaxNb) return -2;
+    if (A == nullptr && n > 0) return -3;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (info == nullptr) return -5;
+    if (dtype == FLAME_F64)
+        return launch_chol_block<double>((int)n, static_cast<double *>(A), lda, info, info_base, as_stream(stream));
+    return launch_chol_block<float>((int)n, static_cast<float *>(A), lda, info, info_base, as_stream(stream));
+}
+
+int flame_op_trsm(int32_t dtype, int64_t b, int64_t m, const void *U, int64_t ldu, void *X, int64_t ldx,
+                  void *stream) {
+    if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
+    if (b < 0 || b > kMaxNb) return -2;
+    if (m < 0) return -3;
+    if (U == nullptr && b > 0) return -4;
+    if (ldu < (b > 1 ? b : 1)) return -5;
+    if (X == nullptr && b > 0 && m > 0) return -6;
+    if (ldx < (b > 1 ? b : 1)) return -7;
+    if (dtype == FLAME_F64)
+        return launch_trsm_panel<double>((int)b, m, static_cast<const double *>(U), ldu, static_cast<double *>(X),
+                                         ldx, nullptr, as_stream(stream));
+    return launch_trsm_panel<float>((int)b, m, static_cast<const float *>(U), ldu, static_cast<float *>(X), ldx,
+                                    nullptr, as_stream(stream));
+}
+
+int flame_op_gemm_tn(int32_t dtype, int32_t trail, int32_t upper, int64_t mr, int64_t nc, int64_t k, const void *X,
+                     int64_t ldx, const void *Y, int64_t ldy, void *C, int64_t ldc, void *stream) {
+    if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
+    if (trail < FLAME_TRAIL_NATIVE || trail > FLAME_TRAIL_BF16) return -2;
+    if (dtype == FLAME_F32 && trail != FLAME_TRAIL_NATIVE) return -2;
+    if (mr < 0) return -3;
+    if (nc < 0) return -4;
+    if (k < 0) return -5;
+    const bool any = mr > 0 && nc > 0;
+    if (X == nullptr && any && k > 0) return -6;
+    if (ldx < (k > 1 ? k : 1)) return -7;
+    if (Y == nullptr && any && k > 0) return -8;
+    if (ldy < (k > 1 ? k : 1)) return -9;
+    if (C == nullptr && any) return -10;
+    if (ldc < (mr > 1 ? mr : 1)) return -11;
+    if (!any) return FLAME_OK;
+    Prec p = Prec::F64;
+    bool cd = true;
+    if (dtype == FLAME_F32) {
+        p = Prec::F32;
+        cd = false;
+    } else if (trail == FLAME_TRAIL_F32) {
+        p = Prec::F32;
+    } else if (trail == FLAME_TRAIL_BF16) {
+        p = Prec::BF16;
+    }
+    return launch_gemm_tn(p, cd, upper != 0, mr, nc, k, X, ldx, Y, ldy, C, ldc, nullptr, as_stream(stream));
+}
+
+const char *flame_status_string(int status) {
+    if (status < 0) return "invalid argument (the negated status is its 1-based position)";
+    switch (status) {
+        case FLAME_OK:
+            return "success";
+        case FLAME_ERR_HIP:
+            return hipGetErrorString(last_hip_error());
+        case FLAME_ERR_NOMEM:
+            return "device workspace allocation failed";
+        case FLAME_ERR_NOT_CONVERGED:
+            return "iterative refinement did not reach the tolerance";
+        case FLAME_ERR_UNSUPPORTED:
+            return "unsupported combination of arguments";
+        default:
+            return "unknown status";
+    }
+}
+
+const char *flame_version(void) { return "flame-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

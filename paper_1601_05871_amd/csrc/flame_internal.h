@@ -1,0 +1,119 @@
+// Internal declarations shared by the kernels, the loop drivers and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+
+#include "flame.h"
+
+namespace flame {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Result of a HIP call inside the library; the last failing code is kept for
+// flame_status_string.
+void set_last_hip_error(hipError_t e);
+hipError_t last_hip_error();
+
+#define FLAME_HIP(call)                                  \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) {                          \
+            ::flame::set_last_hip_error(e_);             \
+            return FLAME_ERR_HIP;                        \
+        }                                                \
+    } while (0)
+
+#define FLAME_CHECK_LAUNCH()                                 \
+    do {                                                     \
+        hipError_t e_ = hipGetLastError();                   \
+        if (e_ != hipSuccess) {                              \
+            ::flame::set_last_hip_error(e_);                 \
+            return FLAME_ERR_HIP;                            \
+        }                                                    \
+    } while (0)
+
+// Instrumentation: trace_begin returns a record id (or -1 when tracing is
+// off or the stream is capturing); trace_end closes it with the launch's
+// algorithmic flops and bytes.
+int trace_begin(int kclass, hipStream_t s);
+void trace_end(int id, hipStream_t s, double flops, double bytes);
+
+// ---- kernel launchers (each returns 0 or a FLAME_ERR_* code) --------------
+
+// info[0] := 0 (a fill kernel, so that the loop can be captured in a graph).
+int launch_zero_i32(int32_t *p, int64_t count, hipStream_t s);
+
+// Diagonal block A := Chol(A), n <= 256, one workgroup.  Skips all work if
+// *info != 0 on entry; on breakdown at local column j writes
+// info = info_base + j.
+template <typename T>
+int launch_chol_block(int n, T *A, int64_t lda, int32_t *info, int64_t info_base, hipStream_t s);
+
+// X := triu(U)^{-T} X, U b x b (b <= 256), X b x m.  Skips if info && *info.
+template <typename T>
+int launch_trsm_panel(int b, int64_t m, const T *U, int64_t ldu, T *X, int64_t ldx, const int32_t *info,
+                      hipStream_t s);
+
+// Operand precisions of the trailing product.
+enum class Prec { F64, F32, BF16 };
+
+// C := C - X^T Y (upper: only i <= j written), X k x M, Y k x N, C M x N.
+//   F64:  X, Y, C double
+//   F32:  X, Y float;  C float (cfloat) or double (!cfloat)
+//   BF16: X, Y bf16 (uint16 storage); C double
+// Skips if info && *info.
+int launch_gemm_tn(Prec p, bool c_is_double, bool upper, int64_t M, int64_t N, int64_t K, const void *X,
+                   int64_t ldx, const void *Y, int64_t ldy, void *C, int64_t ldc, const int32_t *info,
+                   hipStream_t s);
+
+// Y (rows x cols, ldy) := round(X) to float / bf16, column by column.
+int launch_round_panel(Prec p, int64_t rows, int64_t cols, const double *X, int64_t ldx, void *Y, int64_t ldy,
+                       const int32_t *info, hipStream_t s);
+
+// ---- solve and residual kernels -------------------------------------------
+template <typename T>
+int launch_trsv_fwd(int64_t n, int64_t nrhs, const T *U, int64_t ldu, T *B, int64_t ldb, hipStream_t s);
+template <typename T>
+int launch_trsv_bwd(int64_t n, int64_t nrhs, const T *U, int64_t ldu, T *B, int64_t ldb, hipStream_t s);
+
+// R := B - A0 X with A0 symmetric from its upper triangle (FP64); with
+// want_rowsums also rowsums[i] = sum_j |A0(i, j)| (for ||A0||_inf).
+int launch_residual(int64_t n, int64_t nrhs, const double *A0, int64_t lda0, const double *X, int64_t ldx,
+                    const double *B, int64_t ldb, double *R, int64_t ldr, double *rowsums, bool want_rowsums,
+                    hipStream_t s);
+int launch_axpy_cols(int64_t n, int64_t nrhs, const double *D, int64_t ldd, double *X, int64_t ldx,
+                     hipStream_t s);
+int launch_copy_cols(int64_t n, int64_t nrhs, const double *S, int64_t lds, double *D, int64_t ldd,
+                     hipStream_t s);
+// eta[c] = ||r_c||_inf / (||A0||_inf ||x_c||_inf + ||b_c||_inf), eta[nrhs] = max.
+int launch_eta_full(int64_t n, int64_t nrhs, const double *R, int64_t ldr, const double *X, int64_t ldx,
+                    const double *B, int64_t ldb, const double *rowsums, double *eta, hipStream_t s);
+
+// ---- batched -------------------------------------------------------------
+template <typename T>
+int launch_batched(int32_t batch, const int32_t *n, void *const *A, const int32_t *lda, int32_t *info,
+                   int32_t *order, int32_t *counter, int32_t *hist, hipStream_t s);
+
+// ---- selector --------------------------------------------------------------
+int launch_selector(const float *w, const float *feat, int64_t count, float *logits, hipStream_t s);
+
+// ---- per-device context: side stream, events, workspace, graph cache ------
+struct DevCtx;
+DevCtx *ctx_for_current_device();
+// Workspace slot `slot` (0 factor panel, 1 solve, 2 batched, 3 selector) of
+// at least `bytes` (grown under a lock, kept until the process ends).
+enum { kWsFactor = 0, kWsSolve = 1, kWsBatched = 2, kWsSelector = 3, kWsSlots = 4 };
+int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out);
+hipStream_t ctx_side_stream(DevCtx *c);
+hipEvent_t ctx_event(DevCtx *c, int i);
+
+// Loop drivers (driver.cpp).
+int factor_dispatch(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opts_t &o, int32_t *info,
+                    hipStream_t s);
+
+}  // namespace flame

@@ -1,0 +1,86 @@
+// Per-launch HIP-event timing of the library's kernels (instrumentation for
+// measuring each kernel class against its roofline while the real loop runs).
+#include <vector>
+
+#include "flame_internal.h"
+
+namespace flame {
+
+namespace {
+
+struct Rec {
+    int kclass;
+    hipEvent_t a, b;
+    double flops, bytes;
+};
+
+struct TraceState {
+    bool on = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+};
+
+thread_local TraceState g_tr;
+
+hipEvent_t pool_event() {
+    if (g_tr.used == g_tr.pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_tr.pool.push_back(e);
+    }
+    return g_tr.pool[g_tr.used++];
+}
+
+}  // namespace
+
+int trace_begin(int kclass, hipStream_t s) {
+    if (!g_tr.on) return -1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
+    Rec r{kclass, pool_event(), pool_event(), 0.0, 0.0};
+    if (r.a == nullptr || r.b == nullptr) return -1;
+    if (hipEventRecord(r.a, s) != hipSuccess) return -1;
+    g_tr.recs.push_back(r);
+    return (int)g_tr.recs.size() - 1;
+}
+
+void trace_end(int id, hipStream_t s, double flops, double bytes) {
+    if (id < 0) return;
+    Rec &r = g_tr.recs[id];
+    r.flops = flops;
+    r.bytes = bytes;
+    (void)hipEventRecord(r.b, s);
+}
+
+}  // namespace flame
+
+using namespace flame;
+
+extern "C" int flame_trace_enable(int32_t on) {
+    g_tr.on = (on != 0);
+    g_tr.recs.clear();
+    g_tr.used = 0;
+    return FLAME_OK;
+}
+
+extern "C" int flame_trace_collect(int64_t *launches, double *ms, double *flops, double *bytes) {
+    int64_t L[FLAME_KC_COUNT] = {0, 0, 0, 0};
+    double T[FLAME_KC_COUNT] = {0, 0, 0, 0}, F[FLAME_KC_COUNT] = {0, 0, 0, 0}, B[FLAME_KC_COUNT] = {0, 0, 0, 0};
+    for (const Rec &r : g_tr.recs) {
+        FLAME_HIP(hipEventSynchronize(r.b));
+        float t = 0.f;
+        FLAME_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        L[r.kclass] += 1;
+        T[r.kclass] += t;
+        F[r.kclass] += r.flops;
+        B[r.kclass] += r.bytes;
+    }
+    for (int k = 0; k < FLAME_KC_COUNT; ++k) {
+        if (launches) launches[k] = L[k];
+        if (ms) ms[k] = T[k];
+        if (flops) flops[k] = F[k];
+        if (bytes) bytes[k] = B[k];
+    }
+    return FLAME_OK;
+}

@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every symbol include/flame.h declares, argument validation returns
+-i before anything touches the device, status strings, and the tile
+enumeration of the trailing update (compiled for the host)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1601_05871_amd as fl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "flame.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(flame_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fl.lib()
+    declared = _declared()
+    assert len(declared) >= 12
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(fl.EXPORTS) == declared
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in fl.version()
+    assert fl.status_string(0) == "success"
+    assert "invalid" in fl.status_string(-3)
+    assert "tolerance" in fl.status_string(fl.FLAME_ERR_NOT_CONVERGED)
+
+
+def _opts(**kw):
+    o = fl.Opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((7, 4, FAKE, 4, None, FAKE, None), -1),
+    ((0, -1, FAKE, 4, None, FAKE, None), -2),
+    ((0, 4, None, 4, None, FAKE, None), -3),
+    ((0, 4, FAKE, 3, None, FAKE, None), -4),
+    ((0, 4, FAKE, 4, None, None, None), -6),
+])
+def test_factor_argument_errors(args, expect):
+    assert fl.lib().flame_factor(*args) == expect
+
+
+@pytest.mark.parametrize("field,value", [("variant", 9), ("nb", 257), ("nb", -1), ("trail", 3),
+                                         ("lookahead", 2), ("graph", 5)])
+def test_factor_bad_options(field, value):
+    o = _opts(**{field: value})
+    assert fl.lib().flame_factor(0, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == -5
+
+
+def test_factor_unsupported_mixed_combinations():
+    o = _opts(variant=3, trail=1)
+    assert fl.lib().flame_factor(1, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == fl.FLAME_ERR_UNSUPPORTED
+    o = _opts(variant=2, trail=2)
+    assert fl.lib().flame_factor(0, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == fl.FLAME_ERR_UNSUPPORTED
+
+
+def test_solve_argument_errors():
+    L = fl.lib()
+    assert L.flame_solve(3, 4, 1, FAKE, 4, FAKE, 4, None, None, None) == -1
+    assert L.flame_solve(0, -2, 1, FAKE, 4, FAKE, 4, None, None, None) == -2
+    assert L.flame_solve(0, 4, -1, FAKE, 4, FAKE, 4, None, None, None) == -3
+    assert L.flame_solve(0, 4, 1, None, 4, FAKE, 4, None, None, None) == -4
+    assert L.flame_solve(0, 4, 1, FAKE, 2, FAKE, 4, None, None, None) == -5
+    assert L.flame_solve(0, 4, 1, FAKE, 4, None, 4, None, None, None) == -6
+    assert L.flame_solve(0, 4, 1, FAKE, 4, FAKE, 1, None, None, None) == -7
+    r = fl.Refine()
+    r.A0, r.lda0, r.tol, r.max_iter = None, 4, 1e-13, 3
+    assert L.flame_solve(0, 4, 1, FAKE, 4, FAKE, 4, ctypes.byref(r), None, None) == -8
+    r.A0 = 0x1000
+    assert L.flame_solve(1, 4, 1, FAKE, 4, FAKE, 4, ctypes.byref(r), None, None) == fl.FLAME_ERR_UNSUPPORTED
+
+
+def test_op_argument_errors():
+    L = fl.lib()
+    assert L.flame_op_chol(0, 257, FAKE, 300, FAKE, 0, None) == -2
+    assert L.flame_op_trsm(0, 300, 4, FAKE, 300, FAKE, 300, None) == -2
+    assert L.flame_op_gemm_tn(1, 2, 1, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, None) == -2
+    assert L.flame_op_gemm_tn(0, 0, 1, 4, 4, 4, FAKE, 3, FAKE, 4, FAKE, 4, None) == -7
+    assert L.flame_op_gemm_tn(0, 0, 1, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 3, None) == -11
+
+
+def test_batched_and_selector_argument_errors():
+    L = fl.lib()
+    assert L.flame_batched_factor(2, 1, FAKE, FAKE, FAKE, FAKE, None, None) == -1
+    assert L.flame_batched_factor(0, -1, FAKE, FAKE, FAKE, FAKE, None, None) == -2
+    assert L.flame_selector_load(None, fl.SEL_NPARAM) == -1
+    assert L.flame_selector_load(FAKE, 3) == -2
+    v, nb = ctypes.c_int32(), ctypes.c_int32()
+    assert L.flame_select(-1, 1, 0, 1.0, ctypes.byref(v), ctypes.byref(nb)) == -1
+
+
+TILE_PROBE = r'''
+#include <cstdio>
+#include <vector>
+#include "tile_map.h"
+using namespace flame;
+int main() {
+    for (int upper = 0; upper < 2; ++upper)
+    for (int tm = 1; tm <= 40; ++tm)
+    for (int tn = 1; tn <= 40; ++tn) {
+        if (upper && tm > tn) continue;
+        long long nt = tile_count(tm, tn, upper);
+        long long expect = 0;
+        for (int I = 0; I < tm; ++I) for (int J = 0; J < tn; ++J) if (!upper || I <= J) ++expect;
+        if (nt != expect) { printf("count %d %d %d\n", upper, tm, tn); return 1; }
+        std::vector<int> seen(tm * tn, 0);
+        std::vector<int> seenw(nt, 0);
+        for (long long w = 0; w < nt; ++w) {
+            long long t = xcd_remap(w, nt);
+            if (t < 0 || t >= nt || seenw[t]++) { printf("remap %lld\n", w); return 1; }
+            int I, J; tile_of(t, tm, tn, upper, I, J);
+            if (I < 0 || I >= tm || J < 0 || J >= tn || (upper && I > J) || seen[I * tn + J]++) {
+                printf("tile %d %d %d t=%lld -> %d %d\n", upper, tm, tn, t, I, J); return 1; }
+        }
+    }
+    printf("ok\n");
+    return 0;
+}
+'''
+
+
+def test_tile_enumeration_is_a_bijection(tmp_path):
+    src = tmp_path / "probe.cpp"
+    src.write_text(TILE_PROBE)
+    exe = tmp_path / "probe"
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I", os.path.join(ROOT, "paper_1601_05871_amd", "csrc"),
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout
