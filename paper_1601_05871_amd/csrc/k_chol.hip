@@ -1,17 +1,19 @@
 // CHOL step of the loop body (Fig. "dense-chol"): A11 := Chol(A11) for one
 // diagonal block of order n <= 256, upper triangle, in place.
 //
-// One workgroup of four wavefronts walks the block in 64-column sub-blocks
+// One workgroup of four wavefronts walks the block in SB-column sub-blocks
 // (the same right-looking loop one level down):
-//   (a) wavefront 0 factors the 64 x 64 diagonal sub-block in registers: lane c
-//       holds column c, the pivot and the row of U are broadcast with
+//   (a) wavefront 0 factors the SB x SB diagonal sub-block in registers: lane
+//       c holds column c, the pivot and the row of U are broadcast with
 //       v_readlane, so the unblocked loop (b = 1 in the figure) runs without a
 //       barrier or an LDS round trip;
 //   (b) every thread solves one column of the sub-block's row panel against the
 //       fresh U (the TRSM step), U staged in LDS;
-//   (c) the trailing block takes the rank-64 update (the HERK step) from the
+//   (c) the trailing block takes the rank-SB update (the HERK step) from the
 //       panel, staged in LDS.
-// The block lives in L2 between the steps (512 KiB at n = 256 in FP64).
+// SB = 32 keeps the unrolled register code of (a) and (b) small enough to stay
+// in the instruction cache while the loop over sub-blocks repeats it.  The
+// block lives in L2 between the steps (512 KiB at n = 256 in FP64).
 #include "flame_internal.h"
 
 namespace flame {
@@ -28,15 +30,17 @@ __device__ __forceinline__ float rdlane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// Unblocked right-looking Cholesky of a w x w (w <= 64) upper block held one
+constexpr int SB = 32;  // sub-block order
+
+// Unblocked right-looking Cholesky of a w x w (w <= SB) upper block held one
 // column per lane: a[i] = A(i, lane) for i <= lane (other entries 0).  On
 // return a[i] = U(i, lane) for i <= lane.  Returns 0, or the 1-based local
 // column of the first pivot that is not > 0 (the rest is then unspecified).
 template <typename T>
-__device__ __forceinline__ int chol_wave_regs(T (&a)[64], int w, int lane) {
+__device__ __forceinline__ int chol_wave_regs(T (&a)[SB], int w, int lane) {
     int bad = 0;
 #pragma unroll
-    for (int j = 0; j < 64; ++j) {
+    for (int j = 0; j < SB; ++j) {
         if (j < w && bad == 0) {
             const T djj = rdlane(a[j], j);  // pivot A(j, j), uniform
             if (!(djj > T(0))) {
@@ -46,7 +50,7 @@ __device__ __forceinline__ int chol_wave_regs(T (&a)[64], int w, int lane) {
                 const T q = a[j] / s;  // U(j, c) = A(j, c) / U(j, j)
                 a[j] = (lane == j) ? s : (lane > j ? q : a[j]);
 #pragma unroll
-                for (int i = j + 1; i < 64; ++i) {
+                for (int i = j + 1; i < SB; ++i) {
                     if (i < w) {
                         const T uji = rdlane(a[j], i);  // U(j, i), uniform
                         a[i] = a[i] - uji * a[j];       // A(i, c) -= U(j, i) U(j, c)
@@ -61,29 +65,37 @@ __device__ __forceinline__ int chol_wave_regs(T (&a)[64], int w, int lane) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_chol_block(int n, T *__restrict__ A, int64_t lda, int32_t *__restrict__ info,
                                                     int64_t info_base) {
-    __shared__ T Us[64][65];   // U of the current diagonal sub-block, [row][col]
-    __shared__ T Ps[64][196];  // the sub-block's row panel after its TRSM, [row][col]
+    constexpr int RMAX = 256 - SB;  // widest trailing block
+    __shared__ T Us[SB][SB + 1];    // U of the current diagonal sub-block, [row][col]
+    __shared__ T Ps[SB][RMAX + 4];  // the sub-block's row panel after its TRSM, [row][col]
     __shared__ int s_bad;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     if (info != nullptr && *info != 0) return;  // an earlier block broke down
 
-    for (int r0 = 0; r0 < n; r0 += 64) {
-        const int w = min(64, n - r0);
+    for (int r0 = 0; r0 < n; r0 += SB) {
+        const int w = min(SB, n - r0);
         const int rest = n - r0 - w;
         // (a) diagonal sub-block in the registers of wavefront 0
         if (wave == 0) {
-            T a[64];
-            T *col = A + r0 + (int64_t)(r0 + lane) * lda;
+            T a[SB];
+            T *col = A + r0 + (int64_t)(r0 + (lane < w ? lane : 0)) * lda;
+            // unconditional loads from clamped rows (no branch per element, so
+            // they are all in flight at once); unused entries are zeroed
 #pragma unroll
-            for (int i = 0; i < 64; ++i) a[i] = (lane < w && i <= lane) ? col[i] : T(0);
+            for (int i = 0; i < SB; ++i) {
+                const T v = col[min(i, w - 1)];
+                a[i] = (lane < w && i <= lane) ? v : T(0);
+            }
             const int bad = chol_wave_regs(a, w, lane);
             if (lane == 0) s_bad = bad;
+            if (lane < w) {
 #pragma unroll
-            for (int i = 0; i < 64; ++i) {
-                if (lane < w && i <= lane) col[i] = a[i];
-                if (lane < w) Us[i][lane] = a[i];
+                for (int i = 0; i < SB; ++i) {
+                    if (i <= lane) col[i] = a[i];
+                    Us[i][lane] = a[i];
+                }
             }
         }
         __syncthreads();
@@ -94,25 +106,25 @@ __global__ __launch_bounds__(256) void k_chol_block(int n, T *__restrict__ A, in
         if (rest > 0) {
             // (b) row panel: column c = r0 + w + tid, rows r0 .. r0 + w - 1
             if (tid < rest) {
-                T x[64];
+                T x[SB];
                 T *colc = A + r0 + (int64_t)(r0 + w + tid) * lda;
 #pragma unroll
-                for (int i = 0; i < 64; ++i) x[i] = (i < w) ? colc[i] : T(0);
+                for (int i = 0; i < SB; ++i) {
+                    const T v = colc[min(i, w - 1)];
+                    x[i] = (i < w) ? v : T(0);
+                }
 #pragma unroll
-                for (int q = 0; q < 64; ++q) {
+                for (int q = 0; q < SB; ++q) {
                     if (q < w) {
                         x[q] = x[q] / Us[q][q];
 #pragma unroll
-                        for (int t = q + 1; t < 64; ++t)
-                            if (t < w) x[t] = x[t] - Us[q][t] * x[q];
+                        for (int t = q + 1; t < SB; ++t) x[t] = x[t] - Us[q][t] * x[q];
                     }
                 }
 #pragma unroll
-                for (int i = 0; i < 64; ++i) {
-                    if (i < w) {
-                        colc[i] = x[i];
-                        Ps[i][tid] = x[i];
-                    }
+                for (int i = 0; i < SB; ++i) {
+                    if (i < w) colc[i] = x[i];
+                    Ps[i][tid] = (i < w) ? x[i] : T(0);
                 }
             }
             __syncthreads();

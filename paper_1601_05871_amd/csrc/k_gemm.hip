@@ -14,9 +14,10 @@
 //     lane: both operands assign the same k to the same (g, t) slot, so the
 //     contraction is exact whatever the hardware's k order inside a slot;
 //   - the next k-chunk is loaded while the current one is multiplied;
-//   - the C tile is the accumulator (its column-major 4-row runs match the
-//     MFMA output layout: lane holds rows 4g..4g+3 of column r): it is loaded
-//     at the start, X is negated, and the tile is written back once.
+//   - the C tile is the accumulator: it is loaded at the start, X is negated,
+//     and the tile is written back once (mfma_frag gives the element each
+//     accumulator item holds; 16 lanes always cover 64 or 128 contiguous
+//     bytes of one column of C).
 // Precisions: F64 (v_mfma_f64_16x16x4_f64), F32 (v_mfma_f32_16x16x4_f32) and
 // BF16 inputs (v_mfma_f32_16x16x32_bf16), FP32 accumulation for the latter
 // two; with an FP64 C the FP32 sum is subtracted in FP64 at the end.
@@ -49,8 +50,10 @@ struct Tr<Prec::BF16> {
     static constexpr int NMF = 2;
 };
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 union Frag {
-    uint4 u[2];
+    u32x4 u[2];
     double d[4];
     float f[8];
     bf16x8 b[2];
@@ -70,29 +73,43 @@ struct GemmP {
     int upper;
 };
 
-// One 32-byte fragment: column `col` of a K x ncols operand, k range
-// [k, k + VEC).  Out-of-range columns and k are zero.
+// One 32-byte fragment of a K x ncols operand: column `col` (already clamped
+// to a valid column), k range [k, k + VEC) entirely inside [0, K).  No
+// branches, so the compiler can keep many of these loads in flight.
 template <Prec P, bool VECLD>
 __device__ __forceinline__ void load_frag(Frag &f, const typename Tr<P>::in_t *__restrict__ base, int64_t ld,
-                                          int64_t col, int64_t ncols, int64_t k, int64_t K) {
+                                          int64_t col, int64_t k) {
     using in_t = typename Tr<P>::in_t;
     constexpr int VEC = Tr<P>::VEC;
-    if (col >= ncols) {
-        f.u[0] = make_uint4(0, 0, 0, 0);
-        f.u[1] = make_uint4(0, 0, 0, 0);
-        return;
-    }
     const in_t *p = base + col * ld + k;
-    if (VECLD && k + VEC <= K) {
-        const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    if constexpr (VECLD) {
+        const u32x4 *q = reinterpret_cast<const u32x4 *>(p);
         f.u[0] = q[0];
         f.u[1] = q[1];
     } else {
         in_t tmp[VEC];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) tmp[e] = (k + e < K) ? p[e] : in_t(0);
+        for (int e = 0; e < VEC; ++e) tmp[e] = p[e];
         __builtin_memcpy(&f, tmp, sizeof(Frag));
     }
+}
+
+// The same for the last, partial k chunk: elements at k + e >= K are zero
+// (their address is clamped to k = K - 1 and the value discarded).
+template <Prec P>
+__device__ __forceinline__ void load_frag_tail(Frag &f, const typename Tr<P>::in_t *__restrict__ base, int64_t ld,
+                                               int64_t col, int64_t k, int64_t K) {
+    using in_t = typename Tr<P>::in_t;
+    constexpr int VEC = Tr<P>::VEC;
+    const in_t *p = base + col * ld;
+    in_t tmp[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const int64_t kk = k + e;
+        const in_t v = p[kk < K ? kk : K - 1];
+        tmp[e] = (kk < K) ? v : in_t(0);
+    }
+    __builtin_memcpy(&f, tmp, sizeof(Frag));
 }
 
 template <Prec P>
@@ -104,16 +121,23 @@ __device__ __forceinline__ void negate(Frag &f) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) f.f[e] = -f.f[e];
     } else {
-        f.u[0] ^= make_uint4(0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u);
-        f.u[1] ^= make_uint4(0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u);
+        f.u[0] ^= u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+        f.u[1] ^= u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
     }
 }
 
+// acc += (fragment of X)^T (fragment of Y) over the fragment's k range.
+// FP64: the 16x16x4 FP64 MFMA returns D[g + 4v][r] in lane r + 16g, item v,
+// so Y is passed as the row operand and X as the column operand: lane
+// (r, g) then holds (X^T Y)(row r, column g + 4v) of the 16 x 16 block, and
+// 16 lanes with the same g cover 16 consecutive rows of one column of C.
+// FP32 / BF16 MFMAs return D[4g + v][r]: X is the row operand and lane (r, g)
+// holds (X^T Y)(row 4g + v, column r), four consecutive rows of one column.
 template <Prec P>
 __device__ __forceinline__ void mfma_frag(typename Tr<P>::acc_t &acc, const Frag &a, const Frag &b) {
     if constexpr (P == Prec::F64) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.d[t], b.d[t], acc, 0, 0, 0);
+        for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(b.d[t], a.d[t], acc, 0, 0, 0);
     } else if constexpr (P == Prec::F32) {
 #pragma unroll
         for (int t = 0; t < 8; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.f[t], b.f[t], acc, 0, 0, 0);
@@ -121,6 +145,30 @@ __device__ __forceinline__ void mfma_frag(typename Tr<P>::acc_t &acc, const Frag
 #pragma unroll
         for (int t = 0; t < 2; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.b[t], b.b[t], acc, 0, 0, 0);
     }
+}
+
+// The same for one 16-byte half h of the fragments (the first or second half
+// of the fragment's k range).
+template <Prec P>
+__device__ __forceinline__ void mfma_half(typename Tr<P>::acc_t &acc, const u32x4 &a, const u32x4 &b) {
+    if constexpr (P == Prec::F64) {
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        const d2v x = __builtin_bit_cast(d2v, a), y = __builtin_bit_cast(d2v, b);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(y[0], x[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(y[1], x[1], acc, 0, 0, 0);
+    } else if constexpr (P == Prec::F32) {
+        const f4 x = __builtin_bit_cast(f4, a), y = __builtin_bit_cast(f4, b);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x[t], y[t], acc, 0, 0, 0);
+    } else {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                      acc, 0, 0, 0);
+    }
+}
+
+__device__ __forceinline__ u32x4 negate_half(Prec P, u32x4 v) {
+    if (P == Prec::F64) return v ^ u32x4{0u, 0x80000000u, 0u, 0x80000000u};
+    return v ^ u32x4{0x80000000u, 0x80000000u, 0x80000000u, 0x80000000u};
 }
 
 // CT: element type of C.  CINIT: the accumulator starts from C (C's type is
@@ -152,8 +200,18 @@ __global__ __launch_bounds__(256, 1) void k_gemm_tn(GemmP p) {
     CT *__restrict__ C = static_cast<CT *>(p.C);
     const int64_t M = p.M, N = p.N, K = p.K, ldc = p.ldc;
 
+    // C element of accumulator item v of block (a, b) of this lane (see mfma_frag)
+    auto crow = [&](int a, int v) -> int64_t {
+        return (P == Prec::F64) ? row0 + 16 * a + r : row0 + 16 * a + 4 * g + v;
+    };
+    auto ccol = [&](int b, int v) -> int64_t {
+        return (P == Prec::F64) ? col0 + 16 * b + g + 4 * v : col0 + 16 * b + r;
+    };
+    constexpr bool ROWRUN = (P != Prec::F64);  // items v are 4 consecutive rows
+
     acc_t acc[4][4];
-    // accumulator init (C tile, or zero)
+    // accumulator init: the C tile (or zero).  Loads are unconditional from
+    // clamped addresses; entries outside C are never stored.
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -161,114 +219,292 @@ __global__ __launch_bounds__(256, 1) void k_gemm_tn(GemmP p) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[a][b][v] = 0;
             if constexpr (CINIT) {
-                const int64_t col = col0 + 16 * b + r;
-                const int64_t row = row0 + 16 * a + 4 * g;
-                if (col < N) {
-                    const CT *cp = C + row + col * ldc;
+                if constexpr (ROWRUN) {
+                    const int64_t col = min(ccol(b, 0), N - 1);
+                    const int64_t row = crow(a, 0);
                     if (VECLD && row + 3 < M) {
-                        if constexpr (sizeof(CT) == 8) {
-                            const double2 *q = reinterpret_cast<const double2 *>(cp);
-                            double2 lo = q[0], hi = q[1];
-                            acc[a][b][0] = lo.x;
-                            acc[a][b][1] = lo.y;
-                            acc[a][b][2] = hi.x;
-                            acc[a][b][3] = hi.y;
-                        } else {
-                            float4 q = *reinterpret_cast<const float4 *>(cp);
-                            acc[a][b][0] = q.x;
-                            acc[a][b][1] = q.y;
-                            acc[a][b][2] = q.z;
-                            acc[a][b][3] = q.w;
-                        }
+                        float4 q = *reinterpret_cast<const float4 *>(C + row + col * ldc);
+                        acc[a][b][0] = q.x;
+                        acc[a][b][1] = q.y;
+                        acc[a][b][2] = q.z;
+                        acc[a][b][3] = q.w;
                     } else {
 #pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            if (row + v < M) acc[a][b][v] = cp[v];
+                        for (int v = 0; v < 4; ++v) acc[a][b][v] = C[min(row + v, M - 1) + col * ldc];
                     }
+                } else {
+                    const int64_t row = min(crow(a, 0), M - 1);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[a][b][v] = C[row + min(ccol(b, v), N - 1) * ldc];
                 }
             }
         }
 
-    Frag fa[4], fb[4];
+    // operand columns, clamped into range: an out-of-range column only feeds
+    // rows >= M or columns >= N of the product, which are never stored
+    int64_t xcol[4], ycol[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) xcol[a] = min(row0 + 16 * a + r, M - 1);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) ycol[b] = min(col0 + 16 * b + r, N - 1);
     const int64_t kg = (int64_t)g * VEC;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) load_frag<P, VECLD>(fa[a], X, p.ldx, row0 + 16 * a + r, M, kg, K);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) load_frag<P, VECLD>(fb[b], Y, p.ldy, col0 + 16 * b + r, N, kg, K);
+    const int64_t nfull = K / CK;
 
-    for (int64_t k0 = 0; k0 < K; k0 += CK) {
-        Frag na[4], nb[4];
-        const bool more = k0 + CK < K;
-        if (more) {
+    auto load_chunk = [&](Frag(&fx)[4], Frag(&fy)[4], int64_t k0) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-                load_frag<P, VECLD>(na[a], X, p.ldx, row0 + 16 * a + r, M, k0 + CK + kg, K);
+        for (int a = 0; a < 4; ++a) load_frag<P, VECLD>(fx[a], X, p.ldx, xcol[a], k0 + kg);
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                load_frag<P, VECLD>(nb[b], Y, p.ldy, col0 + 16 * b + r, N, k0 + CK + kg, K);
-        }
+        for (int b = 0; b < 4; ++b) load_frag<P, VECLD>(fy[b], Y, p.ldy, ycol[b], k0 + kg);
+    };
+    auto compute = [&](Frag(&fx)[4], Frag(&fy)[4]) {
         if constexpr (CINIT) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) negate<P>(fa[a]);
+            for (int a = 0; a < 4; ++a) negate<P>(fx[a]);
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) mfma_frag<P>(acc[a][b], fa[a], fb[b]);
-        if (more) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a) fa[a] = na[a];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) fb[b] = nb[b];
+            for (int b = 0; b < 4; ++b) mfma_frag<P>(acc[a][b], fx[a], fy[b]);
+    };
+
+    // software pipeline with two register buffers used in turn (no copies,
+    // so the loads of the next chunk stay in flight while this one multiplies)
+    Frag fa[4], fb[4], ga[4], gb[4];
+    if (nfull > 0) {
+        load_chunk(fa, fb, 0);
+        int64_t c = 0;
+        for (; c + 2 < nfull; c += 2) {
+            load_chunk(ga, gb, (c + 1) * CK);
+            compute(fa, fb);
+            load_chunk(fa, fb, (c + 2) * CK);
+            compute(ga, gb);
+        }
+        if (c + 1 < nfull) {
+            load_chunk(ga, gb, (c + 1) * CK);
+            compute(fa, fb);
+            compute(ga, gb);
+        } else {
+            compute(fa, fb);
         }
     }
+    if (nfull * CK < K) {
+        const int64_t k0 = nfull * CK + kg;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) load_frag_tail<P>(fa[a], X, p.ldx, xcol[a], k0, K);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) load_frag_tail<P>(fb[b], Y, p.ldy, ycol[b], k0, K);
+        compute(fa, fb);
+    }
 
-    // write back (upper: only i <= j)
+    // write back (upper: only i <= j); the quarter is interior when all its
+    // elements are stored
+    const bool interior = (row0 + 64 <= M) && (col0 + 64 <= N) && (!p.upper || row0 + 63 <= col0);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int64_t col = col0 + 16 * b + r;
-            const int64_t row = row0 + 16 * a + 4 * g;
-            if (col >= N) continue;
-            CT *cp = C + row + col * ldc;
-            const bool full = (row + 3 < M) && (!p.upper || row + 3 <= col);
-            if constexpr (CINIT) {
-                if (VECLD && full) {
-                    if constexpr (sizeof(CT) == 8) {
-                        double2 *q = reinterpret_cast<double2 *>(cp);
-                        q[0] = make_double2(acc[a][b][0], acc[a][b][1]);
-                        q[1] = make_double2(acc[a][b][2], acc[a][b][3]);
-                    } else {
+            if constexpr (ROWRUN) {
+                const int64_t col = ccol(b, 0), row = crow(a, 0);
+                if (col >= N) continue;
+                CT *cp = C + row + col * ldc;
+                const bool full = (row + 3 < M) && (!p.upper || row + 3 <= col);
+                if constexpr (CINIT) {
+                    if (VECLD && full) {
                         *reinterpret_cast<float4 *>(cp) =
                             make_float4(acc[a][b][0], acc[a][b][1], acc[a][b][2], acc[a][b][3]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (row + v < M && (!p.upper || row + v <= col)) cp[v] = (CT)acc[a][b][v];
                     }
                 } else {
+                    if (VECLD && full) {
+                        double2 *q = reinterpret_cast<double2 *>(cp);
+                        double2 lo = q[0], hi = q[1];
+                        lo.x -= (double)acc[a][b][0];
+                        lo.y -= (double)acc[a][b][1];
+                        hi.x -= (double)acc[a][b][2];
+                        hi.y -= (double)acc[a][b][3];
+                        q[0] = lo;
+                        q[1] = hi;
+                    } else {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (row + v < M && (!p.upper || row + v <= col)) cp[v] = (CT)acc[a][b][v];
+                        for (int v = 0; v < 4; ++v)
+                            if (row + v < M && (!p.upper || row + v <= col)) cp[v] = cp[v] - (CT)acc[a][b][v];
+                    }
                 }
             } else {
-                if (VECLD && full) {
-                    double2 *q = reinterpret_cast<double2 *>(cp);
-                    double2 lo = q[0], hi = q[1];
-                    lo.x -= (double)acc[a][b][0];
-                    lo.y -= (double)acc[a][b][1];
-                    hi.x -= (double)acc[a][b][2];
-                    hi.y -= (double)acc[a][b][3];
-                    q[0] = lo;
-                    q[1] = hi;
-                } else {
+                const int64_t row = crow(a, 0);
+                if (interior) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (row + v < M && (!p.upper || row + v <= col)) cp[v] = cp[v] - (CT)acc[a][b][v];
+                    for (int v = 0; v < 4; ++v) C[row + ccol(b, v) * ldc] = (CT)acc[a][b][v];
+                } else if (row < M) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t col = ccol(b, v);
+                        if (col < N && (!p.upper || row <= col)) C[row + col * ldc] = (CT)acc[a][b][v];
+                    }
                 }
             }
         }
 }
 
+// ---- LDS-staged variant (K a multiple of the chunk, 16-byte aligned) ------
+// Per k-chunk the workgroup stages the 128 columns of X and of Y it needs
+// (128 bytes of each column: 16 FP64, 32 FP32 or 64 BF16 values) in LDS, so
+// each operand element is read from L2 once per workgroup instead of once per
+// wavefront.  Global -> register -> LDS copies of chunk c + 1 overlap the
+// MFMAs of chunk c (two LDS buffers, one barrier per chunk).  Each column's
+// eight 16-byte units are stored XOR-swizzled by (column mod 8) so that the
+// 16 lanes reading one unit of 16 consecutive columns hit different banks.
+constexpr int kSlabBytes = kTile * 128;  // one operand, one chunk
+
+__device__ __forceinline__ int slab_off(int col, int unit) { return col * 128 + ((unit ^ (col & 7)) << 4); }
+
+template <Prec P, typename CT>
+__global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
+    using TR = Tr<P>;
+    using in_t = typename TR::in_t;
+    using acc_t = typename TR::acc_t;
+    constexpr int VEC = TR::VEC;
+    constexpr int CK = 4 * VEC;  // k per chunk (128 bytes of a column)
+    __shared__ __attribute__((aligned(16))) char lds[2][2][kSlabBytes];  // [buffer][X or Y]
+
+    if (p.info != nullptr && *p.info != 0) return;
+    const int64_t t = xcd_remap((int64_t)blockIdx.x, p.ntiles);
+    int I, J;
+    tile_of(t, p.tm, p.tn, p.upper != 0, I, J);
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int r = lane & 15;
+    const int g = lane >> 4;
+    const int64_t tr0 = (int64_t)I * kTile, tc0 = (int64_t)J * kTile;
+    const int64_t row0 = tr0 + (wave >> 1) * 64;
+    const int64_t col0 = tc0 + (wave & 1) * 64;
+    const int64_t M = p.M, N = p.N, K = p.K, ldc = p.ldc;
+    const bool active = (row0 < M) && (col0 < N) && !(p.upper && row0 > col0 + 63);
+    const char *__restrict__ Xb = static_cast<const char *>(p.X);
+    const char *__restrict__ Yb = static_cast<const char *>(p.Y);
+    const int64_t ldxb = p.ldx * (int64_t)sizeof(in_t), ldyb = p.ldy * (int64_t)sizeof(in_t);
+
+    // copy assignment: thread tid moves units q = tid + 256 j (j < 8) of the
+    // 2 x 1024 units of a chunk.  Unit q belongs to operand q / 1024 (j / 4),
+    // column (q % 1024) / 8 = tid / 8 + 32 (j % 4), 16-byte unit q % 8 = tid % 8.
+    const int unit = tid & 7;
+    const int ccol0 = tid >> 3;
+    const int64_t chunk_bytes = CK * (int64_t)sizeof(in_t);  // 128
+    const int64_t nch = K / CK;
+    // byte offsets (from Xb / Yb) of this thread's four columns of each operand
+    int64_t xoff[4], yoff[4];
+    int dofs[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = ccol0 + 32 * j;
+        xoff[j] = min(tr0 + col, M - 1) * ldxb + unit * 16;
+        yoff[j] = min(tc0 + col, N - 1) * ldyb + unit * 16;
+        dofs[j] = slab_off(col, unit);
+    }
+
+    // C element of accumulator item v of block (a, b) (see mfma_frag)
+#define FLAME_CROW(a, v) ((P == Prec::F64) ? row0 + 16 * (a) + r : row0 + 16 * (a) + 4 * g + (v))
+#define FLAME_CCOL(b, v) ((P == Prec::F64) ? col0 + 16 * (b) + g + 4 * (v) : col0 + 16 * (b) + r)
+    // CINIT: the accumulator starts from the C tile (same precision) and X is
+    // negated; otherwise it starts at zero and C - X^T Y is formed at the end.
+    constexpr bool CINIT = (P == Prec::F64 && sizeof(CT) == 8) || (P == Prec::F32 && sizeof(CT) == 4);
+    CT *__restrict__ C = static_cast<CT *>(p.C);
+    acc_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[a][b][v] = CINIT ? C[min(FLAME_CROW(a, v), M - 1) + min(FLAME_CCOL(b, v), N - 1) * ldc] : 0;
+
+    const int xr = (wave >> 1) * 64 + r, yr = (wave & 1) * 64 + r;
+    u32x4 stx[4], sty[4];
+
+#define FLAME_FETCH1(j, cidx)                                                                         \
+    stx[j] = *reinterpret_cast<const u32x4 *>(Xb + xoff[j] + (cidx) * chunk_bytes);                   \
+    sty[j] = *reinterpret_cast<const u32x4 *>(Yb + yoff[j] + (cidx) * chunk_bytes);
+#define FLAME_FETCH(cidx)                                                                             \
+    {                                                                                                 \
+        FLAME_FETCH1(0, cidx) FLAME_FETCH1(1, cidx) FLAME_FETCH1(2, cidx) FLAME_FETCH1(3, cidx)       \
+    }
+#define FLAME_PUT1(j, buf)                                                                            \
+    *reinterpret_cast<u32x4 *>(&lds[buf][0][0] + dofs[j]) = stx[j];                                   \
+    *reinterpret_cast<u32x4 *>(&lds[buf][1][0] + dofs[j]) = sty[j];
+#define FLAME_PUT(buf)                                                                                \
+    {                                                                                                 \
+        FLAME_PUT1(0, buf) FLAME_PUT1(1, buf) FLAME_PUT1(2, buf) FLAME_PUT1(3, buf)                   \
+    }
+// One chunk from LDS buffer `buf`: the two 16-byte halves of each lane's
+// fragments are read and multiplied in turn (half the operand registers).
+#define FLAME_COMPUTE(buf)                                                                            \
+    {                                                                                                 \
+        const char *xs_ = &lds[buf][0][0];                                                            \
+        const char *ys_ = &lds[buf][1][0];                                                            \
+        _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                               \
+            u32x4 fa_[4], fb_[4];                                                                     \
+            _Pragma("unroll") for (int a = 0; a < 4; ++a) {                                           \
+                fa_[a] = *reinterpret_cast<const u32x4 *>(xs_ + slab_off(xr + 16 * a, 2 * g + h));    \
+                if constexpr (CINIT) fa_[a] = negate_half(P, fa_[a]);                                 \
+            }                                                                                         \
+            _Pragma("unroll") for (int b = 0; b < 4; ++b)                                             \
+                fb_[b] = *reinterpret_cast<const u32x4 *>(ys_ + slab_off(yr + 16 * b, 2 * g + h));    \
+            _Pragma("unroll") for (int a = 0; a < 4; ++a)                                             \
+                _Pragma("unroll") for (int b = 0; b < 4; ++b) mfma_half<P>(acc[a][b], fa_[a], fb_[b]); \
+        }                                                                                             \
+    }
+
+    FLAME_FETCH(0)
+    FLAME_PUT(0)
+    __syncthreads();
+    int64_t c = 0;
+    for (; c + 1 < nch; ++c) {
+        FLAME_FETCH(c + 1)
+        // unconditional (no branch between the loads and the MFMAs, so the
+        // loads stay ahead of them); an inactive wave's product is discarded
+        FLAME_COMPUTE((int)(c & 1))
+        // keep the LDS writes (which wait for the loads) behind the MFMAs
+        __builtin_amdgcn_sched_barrier(0);
+        FLAME_PUT((int)((c + 1) & 1))
+        __syncthreads();
+    }
+#undef FLAME_FETCH
+#undef FLAME_FETCH1
+#undef FLAME_PUT
+#undef FLAME_PUT1
+
+    FLAME_COMPUTE((int)(c & 1))
+    if (active) {
+        const bool interior = (row0 + 64 <= M) && (col0 + 64 <= N) && (!p.upper || row0 + 63 <= col0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = FLAME_CROW(a, v), col = FLAME_CCOL(b, v);
+                    if (interior || (row < M && col < N && (!p.upper || row <= col))) {
+                        CT *cp = C + row + col * ldc;
+                        if constexpr (CINIT)
+                            *cp = (CT)acc[a][b][v];
+                        else
+                            *cp = *cp - (CT)acc[a][b][v];
+                    }
+                }
+    }
+#undef FLAME_COMPUTE
+#undef FLAME_CROW
+#undef FLAME_CCOL
+}
+
 template <Prec P, typename CT>
 static int launch_t(const GemmP &p, bool vec, hipStream_t s) {
+    constexpr int64_t CK = 4 * Tr<P>::VEC;
+    const bool lds_ok = vec && p.K > 0 && (p.K % CK) == 0;
     const unsigned grid = (unsigned)p.ntiles;
     // algorithmic work: 2K flops per updated element; each operand element
     // read once (one panel when X and Y are the same), C read and written
@@ -277,7 +513,9 @@ static int launch_t(const GemmP &p, bool vec, hipStream_t s) {
     const double esz = P == Prec::F64 ? 8.0 : (P == Prec::F32 ? 4.0 : 2.0);
     const double panel = (p.X == p.Y && p.M == p.N) ? K * M : K * (M + N);
     const int tr = trace_begin(FLAME_KC_GEMM, s);
-    if (vec)
+    if (lds_ok)
+        hipLaunchKernelGGL((k_gemm_lds<P, CT>), dim3(grid), dim3(256), 0, s, p);
+    else if (vec)
         hipLaunchKernelGGL((k_gemm_tn<P, CT, true>), dim3(grid), dim3(256), 0, s, p);
     else
         hipLaunchKernelGGL((k_gemm_tn<P, CT, false>), dim3(grid), dim3(256), 0, s, p);
