@@ -3,7 +3,7 @@
 MI355X.
 
 A step is one FP64 factorization of the n = 16384 SPD matrix A = B B^T + n I
-(B ~ N(0,1), PCG64 seed), right-looking loop, block size 128, lookahead.
+(B ~ N(0,1), PCG64 seed), right-looking loop, block size 256, lookahead.
 Each timed step factors its own pre-generated copy already resident in HBM,
 so the timed region holds nothing but the K factorizations.  Prints one JSON
 line with GFLOP/s (potrf flop count n^3/3 + n^2/2 + n/6), the live roofline of
@@ -46,9 +46,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=16384)
-    ap.add_argument("--nb", type=int, default=128)
+    ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--variant", type=int, default=3)
-    ap.add_argument("--lookahead", type=int, default=1)
+    ap.add_argument("--lookahead", type=int, default=2)
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--kappa", type=float, default=1e4)
@@ -151,7 +151,7 @@ def main() -> int:
         "config": {
             "workload": f"dense SPD Cholesky n={n} FP64, A = B B^T + n I (B ~ N(0,1), PCG64 seed {args.seed})",
             "n": n, "nb": args.nb, "variant": {1: "bordered", 2: "left-looking", 3: "right-looking"}[args.variant],
-            "lookahead": bool(args.lookahead), "graph": bool(args.graph),
+            "lookahead": args.lookahead, "graph": bool(args.graph),
         },
         "pct_fp64_mfma_peak": round(100.0 * gflops / (PEAK_F64_TFLOPS * 1e3), 2),
         "beta_F": beta,

@@ -72,12 +72,15 @@ typedef enum { FLAME_TRAIL_NATIVE = 0, FLAME_TRAIL_F32 = 1, FLAME_TRAIL_BF16 = 2
 typedef struct {
     int32_t variant;   /* flame_variant_t; 0 = choose */
     int32_t nb;        /* block size b (A11 is b x b, the last block min(b, n-k));
-                          0 = choose; valid range 1..256 */
+                          0 = choose (selector, else 256); valid range 1..256 */
     int32_t trail;     /* flame_trail_t */
-    int32_t lookahead; /* RIGHT variant: 0 = default (on), 1 = on, -1 = off.
-                          On: the next diagonal block and panel are updated first
+    int32_t lookahead; /* RIGHT variant: 0 = default (2), -1 = off.
+                          1: the next diagonal block and panel are updated first
                           and factored on a second stream while the rest of the
-                          trailing update runs. */
+                          trailing update runs on the caller's stream.
+                          2: the same split, with the rest of the trailing update
+                          on the second stream and the next CHOL and TRSM on
+                          the caller's stream. */
     int32_t graph;     /* 0 = default (off), 1 = capture the loop once per
                           (n, lda, A, info, options, stream) in a HIP graph and
                           replay it on later calls with the same key */

@@ -22,7 +22,7 @@ int normalize_opts(const flame_opts_t *in, int32_t dtype, int64_t n, flame_opts_
     if (o->variant < FLAME_VAR_AUTO || o->variant > FLAME_VAR_RIGHT) return -5;
     if (o->nb < 0 || o->nb > kMaxNb) return -5;
     if (o->trail < FLAME_TRAIL_NATIVE || o->trail > FLAME_TRAIL_BF16) return -5;
-    if (o->lookahead < -1 || o->lookahead > 1) return -5;
+    if (o->lookahead < -1 || o->lookahead > 2) return -5;
     if (o->graph < 0 || o->graph > 1) return -5;
     if (o->variant == FLAME_VAR_AUTO) {
         int32_t v = FLAME_VAR_RIGHT, nb = 0;
@@ -33,7 +33,7 @@ int normalize_opts(const flame_opts_t *in, int32_t dtype, int64_t n, flame_opts_
         o->variant = v;
         if (o->nb == 0) o->nb = nb;
     }
-    if (o->nb == 0) o->nb = 128;
+    if (o->nb == 0) o->nb = 256;
     return 0;
 }
 

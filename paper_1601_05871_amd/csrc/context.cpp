@@ -16,8 +16,8 @@ struct DevCtx {
     int device = -1;
     hipStream_t side = nullptr;
     std::vector<hipEvent_t> events;
-    void *ws[kWsSlots] = {nullptr, nullptr, nullptr, nullptr};
-    size_t ws_bytes[kWsSlots] = {0, 0, 0, 0};
+    void *ws[kWsSlots] = {};
+    size_t ws_bytes[kWsSlots] = {};
     std::mutex mu;
 };
 

@@ -51,8 +51,9 @@ int gemm_tallk(bool upper, int64_t M, int64_t N, int64_t K, const T *X, int64_t 
 
 // ---- right-looking (the paper's loop) ------------------------------------
 template <typename T>
-int factor_right(int64_t n, T *A, int64_t lda, int nb, bool lookahead, flame_trail_t trail, int32_t *info,
+int factor_right(int64_t n, T *A, int64_t lda, int nb, int lookahead, flame_trail_t trail, int32_t *info,
                  hipStream_t s) {
+    const bool rest_on_side = (lookahead == 2 || lookahead == 0);
     Views<T> V{A, lda};
     int rc;
     DevCtx *ctx = ctx_for_current_device();
@@ -86,7 +87,7 @@ int factor_right(int64_t n, T *A, int64_t lda, int nb, bool lookahead, flame_tra
     if (rc) return rc;
     if (n == 0) return FLAME_OK;
 
-    if (!lookahead) {
+    if (lookahead < 0) {
         for (int64_t k = 0; k < n; k += nb) {
             const int64_t bk = std::min<int64_t>(nb, n - k);
             const int64_t m = n - k - bk;
@@ -143,17 +144,33 @@ int factor_right(int64_t n, T *A, int64_t lda, int nb, bool lookahead, flame_tra
             if (rc) return rc;
             continue;
         }
-        FLAME_HIP(hipEventRecord(ev_panel, s));
-        FLAME_HIP(hipStreamWaitEvent(side, ev_panel, 0));
-        rc = launch_chol_block<T>((int)bk2, V.at(k2, k2), lda, info, k2, side);
-        if (rc) return rc;
-        rc = launch_trsm_panel<T>((int)bk2, m2, V.at(k2, k2), lda, V.at(k2, k2 + bk2), lda, info, side);
-        if (rc) return rc;
-        FLAME_HIP(hipEventRecord(ev_ready, side));
-        // the rest of A22: rows and columns [bk2, m)
-        rc = update(k, bk, bk2, m2, bk2, m2, s);
-        if (rc) return rc;
-        FLAME_HIP(hipStreamWaitEvent(s, ev_ready, 0));
+        if (!rest_on_side) {
+            FLAME_HIP(hipEventRecord(ev_panel, s));
+            FLAME_HIP(hipStreamWaitEvent(side, ev_panel, 0));
+            rc = launch_chol_block<T>((int)bk2, V.at(k2, k2), lda, info, k2, side);
+            if (rc) return rc;
+            rc = launch_trsm_panel<T>((int)bk2, m2, V.at(k2, k2), lda, V.at(k2, k2 + bk2), lda, info, side);
+            if (rc) return rc;
+            FLAME_HIP(hipEventRecord(ev_ready, side));
+            // the rest of A22: rows and columns [bk2, m)
+            rc = update(k, bk, bk2, m2, bk2, m2, s);
+            if (rc) return rc;
+            FLAME_HIP(hipStreamWaitEvent(s, ev_ready, 0));
+        } else {
+            // the rest of A22 on the second stream; the next CHOL and TRSM
+            // follow the panel rows on the main stream, which dispatches them
+            // ahead of the remainder's workgroups
+            FLAME_HIP(hipEventRecord(ev_panel, s));
+            FLAME_HIP(hipStreamWaitEvent(side, ev_panel, 0));
+            rc = update(k, bk, bk2, m2, bk2, m2, side);
+            if (rc) return rc;
+            FLAME_HIP(hipEventRecord(ev_ready, side));
+            rc = launch_chol_block<T>((int)bk2, V.at(k2, k2), lda, info, k2, s);
+            if (rc) return rc;
+            rc = launch_trsm_panel<T>((int)bk2, m2, V.at(k2, k2), lda, V.at(k2, k2 + bk2), lda, info, s);
+            if (rc) return rc;
+            FLAME_HIP(hipStreamWaitEvent(s, ev_ready, 0));
+        }
     }
     return FLAME_OK;
 }
@@ -221,7 +238,7 @@ int factor_t(int64_t n, T *A, int64_t lda, const flame_opts_t &o, int32_t *info,
     const int nb = o.nb;
     switch (o.variant) {
         case FLAME_VAR_RIGHT:
-            return factor_right<T>(n, A, lda, nb, o.lookahead >= 0, (flame_trail_t)o.trail, info, s);
+            return factor_right<T>(n, A, lda, nb, o.lookahead, (flame_trail_t)o.trail, info, s);
         case FLAME_VAR_LEFT:
             return factor_left<T>(n, A, lda, nb, info, s);
         case FLAME_VAR_BORDERED:

@@ -105,7 +105,7 @@ int launch_selector(const float *w, const float *feat, int64_t count, float *log
 // ---- per-device context: side stream, events, workspace, graph cache ------
 struct DevCtx;
 DevCtx *ctx_for_current_device();
-// Workspace slot `slot` (0 factor panel, 1 solve, 2 batched, 3 selector) of
+// Workspace slot `slot` (factor panel, solve, batched, selector) of
 // at least `bytes` (grown under a lock, kept until the process ends).
 enum { kWsFactor = 0, kWsSolve = 1, kWsBatched = 2, kWsSelector = 3, kWsSlots = 4 };
 int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out);

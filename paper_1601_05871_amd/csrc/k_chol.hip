@@ -1,19 +1,20 @@
 // CHOL step of the loop body (Fig. "dense-chol"): A11 := Chol(A11) for one
 // diagonal block of order n <= 256, upper triangle, in place.
 //
-// One workgroup of four wavefronts walks the block in SB-column sub-blocks
-// (the same right-looking loop one level down):
-//   (a) wavefront 0 factors the SB x SB diagonal sub-block in registers: lane
-//       c holds column c, the pivot and the row of U are broadcast with
+// One workgroup of four wavefronts holds the block in LDS and walks it in
+// S-column sub-blocks (the same right-looking loop one level down):
+//   (a) wavefront 0 factors the S x S diagonal sub-block in registers: lane c
+//       holds column c, the pivot and the row of U are broadcast with
 //       v_readlane, so the unblocked loop (b = 1 in the figure) runs without a
 //       barrier or an LDS round trip;
 //   (b) every thread solves one column of the sub-block's row panel against the
-//       fresh U (the TRSM step), U staged in LDS;
-//   (c) the trailing block takes the rank-SB update (the HERK step) from the
-//       panel, staged in LDS.
-// SB = 32 keeps the unrolled register code of (a) and (b) small enough to stay
-// in the instruction cache while the loop over sub-blocks repeats it.  The
-// block lives in L2 between the steps (512 KiB at n = 256 in FP64).
+//       fresh U (the TRSM step);
+//   (c) the trailing block takes the rank-S update (the HERK step), 4 x 4
+//       entries per thread.
+// S = 16 keeps the unrolled register code small: the kernel runs as a single
+// workgroup, so its code must stay in the instruction cache.  Blocks of order
+// 129..256 take the same loop one level up (two LDS-resident blocks, the
+// panel TRSM and the trailing update kernels in between).
 #include "flame_internal.h"
 
 namespace flame {
@@ -30,72 +31,112 @@ __device__ __forceinline__ float rdlane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-constexpr int SB = 32;  // sub-block order
+// LDS-resident form for n <= 128: the upper triangle is loaded into LDS once
+// (column-major, leading dimension 129), padded with the identity to a
+// multiple of the sub-block order S (so every sub-block is full and the
+// unrolled register code needs no bounds guards), steps (a)-(c) run on LDS
+// only, and the factor is written back once.  The padding stays the identity:
+// its pivots are 1 and its coupling to the matrix is 0.
+constexpr int kLdsN = 128;
+constexpr int kLdsLd = kLdsN + 1;
 
-// Unblocked right-looking Cholesky of a w x w (w <= SB) upper block held one
-// column per lane: a[i] = A(i, lane) for i <= lane (other entries 0).  On
-// return a[i] = U(i, lane) for i <= lane.  Returns 0, or the 1-based local
-// column of the first pivot that is not > 0 (the rest is then unspecified).
-template <typename T>
-__device__ __forceinline__ int chol_wave_regs(T (&a)[SB], int w, int lane) {
+// 1 / s to full precision: hardware reciprocal estimate and two Newton steps
+// (exact when s is a power of two).
+__device__ __forceinline__ double recip(double s) {
+    double r = __builtin_amdgcn_rcp(s);
+    r = __builtin_fma(__builtin_fma(-s, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-s, r, 1.0), r, r);
+    return r;
+}
+__device__ __forceinline__ float recip(float s) {
+    float r = __builtin_amdgcn_rcpf(s);
+    r = __builtin_fmaf(__builtin_fmaf(-s, r, 1.0f), r, r);
+    return r;
+}
+
+// Unguarded S x S wave factorization (column-per-lane registers, as in
+// chol_wave_regs with w = S) without branches: a pivot that is not > 0 is
+// recorded and the remaining arithmetic runs on (meaningless) values, so the
+// whole sequence is one basic block and the next pivot's square root and
+// reciprocal overlap the previous pivot's row updates.  Returns the first bad
+// local pivot (1-based) or 0; *rinv = 1 / U(lane, lane).
+template <typename T, int S>
+__device__ __forceinline__ int chol_wave_full(T (&a)[S], int lane, T *rinv) {
     int bad = 0;
+    T myinv = T(1);
 #pragma unroll
-    for (int j = 0; j < SB; ++j) {
-        if (j < w && bad == 0) {
-            const T djj = rdlane(a[j], j);  // pivot A(j, j), uniform
-            if (!(djj > T(0))) {
-                bad = j + 1;
-            } else {
-                const T s = sqrt(djj);
-                const T q = a[j] / s;  // U(j, c) = A(j, c) / U(j, j)
-                a[j] = (lane == j) ? s : (lane > j ? q : a[j]);
+    for (int j = 0; j < S; ++j) {
+        const T djj = rdlane(a[j], j);
+        bad = (bad == 0 && !(djj > T(0))) ? j + 1 : bad;
+        const T sq = sqrt(djj);
+        const T inv = recip(sq);
+        myinv = (lane == j) ? inv : myinv;
+        a[j] = (lane == j) ? sq : (lane > j ? a[j] * inv : a[j]);
 #pragma unroll
-                for (int i = j + 1; i < SB; ++i) {
-                    if (i < w) {
-                        const T uji = rdlane(a[j], i);  // U(j, i), uniform
-                        a[i] = a[i] - uji * a[j];       // A(i, c) -= U(j, i) U(j, c)
-                    }
-                }
-            }
+        for (int i = j + 1; i < S; ++i) {
+            const T uji = rdlane(a[j], i);
+            a[i] = a[i] - uji * a[j];
         }
     }
+    *rinv = myinv;
     return bad;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_chol_block(int n, T *__restrict__ A, int64_t lda, int32_t *__restrict__ info,
-                                                    int64_t info_base) {
-    constexpr int RMAX = 256 - SB;  // widest trailing block
-    __shared__ T Us[SB][SB + 1];    // U of the current diagonal sub-block, [row][col]
-    __shared__ T Ps[SB][RMAX + 4];  // the sub-block's row panel after its TRSM, [row][col]
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_chol_lds(int n, T *__restrict__ A, int64_t lda, int32_t *__restrict__ info,
+                                                  int64_t info_base) {
+    constexpr int RMAX = kLdsN - S;       // widest trailing block
+    __shared__ T L[kLdsN * kLdsLd];       // the block, column-major
+    __shared__ T Pt[S][RMAX + 4];         // the current panel rows, row-major
+    __shared__ T rinv[S];                 // 1 / U(j, j) of the current sub-block
     __shared__ int s_bad;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    if (info != nullptr && *info != 0) return;  // an earlier block broke down
+    if (info != nullptr && *info != 0) return;
+    const int np = (n + S - 1) / S * S;
+    // load: all of this thread's loads first, then the LDS stores (lower
+    // positions get a copy of an upper element, never used; padding rows and
+    // columns >= n hold the identity)
+    {
+        constexpr int PER = kLdsN * kLdsN / 256;
+        T v[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + 256 * e;
+            const int col = idx >> 7, row = idx & (kLdsN - 1);
+            v[e] = A[(int64_t)min(min(row, col), n - 1) + (int64_t)min(col, n - 1) * lda];
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + 256 * e;
+            const int col = idx >> 7, row = idx & (kLdsN - 1);
+            if (row < np && col < np)
+                L[col * kLdsLd + row] = (row < n && col < n) ? v[e] : (row == col ? T(1) : T(0));
+        }
+    }
+    __syncthreads();
 
-    for (int r0 = 0; r0 < n; r0 += SB) {
-        const int w = min(SB, n - r0);
-        const int rest = n - r0 - w;
+    for (int r0 = 0; r0 < np; r0 += S) {
+        const int rest = np - r0 - S;
         // (a) diagonal sub-block in the registers of wavefront 0
         if (wave == 0) {
-            T a[SB];
-            T *col = A + r0 + (int64_t)(r0 + (lane < w ? lane : 0)) * lda;
-            // unconditional loads from clamped rows (no branch per element, so
-            // they are all in flight at once); unused entries are zeroed
+            T a[S];
+            const T *colp = L + (r0 + min(lane, S - 1)) * kLdsLd + r0;
 #pragma unroll
-            for (int i = 0; i < SB; ++i) {
-                const T v = col[min(i, w - 1)];
-                a[i] = (lane < w && i <= lane) ? v : T(0);
+            for (int i = 0; i < S; ++i) {
+                const T v = colp[i];
+                a[i] = (i <= lane) ? v : T(0);
             }
-            const int bad = chol_wave_regs(a, w, lane);
+            T ri;
+            const int bad = chol_wave_full<T, S>(a, lane, &ri);
             if (lane == 0) s_bad = bad;
-            if (lane < w) {
+            if (lane < S) {
+                T *colw = L + (r0 + lane) * kLdsLd + r0;
 #pragma unroll
-                for (int i = 0; i < SB; ++i) {
-                    if (i <= lane) col[i] = a[i];
-                    Us[i][lane] = a[i];
-                }
+                for (int i = 0; i < S; ++i)
+                    if (i <= lane) colw[i] = a[i];
+                rinv[lane] = ri;
             }
         }
         __syncthreads();
@@ -103,79 +144,86 @@ __global__ __launch_bounds__(256) void k_chol_block(int n, T *__restrict__ A, in
             if (tid == 0) *info = (int32_t)(info_base + r0 + s_bad);
             return;
         }
-        if (rest > 0) {
-            // (b) row panel: column c = r0 + w + tid, rows r0 .. r0 + w - 1
-            if (tid < rest) {
-                T x[SB];
-                T *colc = A + r0 + (int64_t)(r0 + w + tid) * lda;
+        if (rest == 0) break;
+        // (b) row panel: thread t owns column r0 + S + t
+        if (tid < rest) {
+            T x[S];
+            T *colc = L + (r0 + S + tid) * kLdsLd + r0;
 #pragma unroll
-                for (int i = 0; i < SB; ++i) {
-                    const T v = colc[min(i, w - 1)];
-                    x[i] = (i < w) ? v : T(0);
-                }
+            for (int i = 0; i < S; ++i) x[i] = colc[i];
 #pragma unroll
-                for (int q = 0; q < SB; ++q) {
-                    if (q < w) {
-                        x[q] = x[q] / Us[q][q];
+            for (int q = 0; q < S; ++q) {
+                x[q] = x[q] * rinv[q];
 #pragma unroll
-                        for (int t = q + 1; t < SB; ++t) x[t] = x[t] - Us[q][t] * x[q];
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < SB; ++i) {
-                    if (i < w) colc[i] = x[i];
-                    Ps[i][tid] = (i < w) ? x[i] : T(0);
-                }
+                for (int t = q + 1; t < S; ++t) x[t] = x[t] - L[(r0 + t) * kLdsLd + r0 + q] * x[q];
             }
-            __syncthreads();
-            // (c) trailing rest x rest upper block -= panel^T panel, 4 x 4 per thread
-            const int nb4 = (rest + 3) >> 2;
-            const int cnt = nb4 * (nb4 + 1) / 2;
-            T *T0 = A + (r0 + w) + (int64_t)(r0 + w) * lda;
-            for (int idx = tid; idx < cnt; idx += 256) {
-                int bj = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
-                while (bj * (bj + 1) / 2 > idx) --bj;
-                while ((bj + 1) * (bj + 2) / 2 <= idx) ++bj;
-                const int bi = idx - bj * (bj + 1) / 2;
-                T acc[4][4];
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                colc[i] = x[i];
+                Pt[i][tid] = x[i];
+            }
+        }
+        __syncthreads();
+        // (c) trailing update, 4 x 4 per thread, from the row-major panel
+        const int o = r0 + S;
+        const int nb4 = rest >> 2;
+        const int cnt = nb4 * (nb4 + 1) / 2;
+        for (int idx = tid; idx < cnt; idx += 256) {
+            int bj = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+            while (bj * (bj + 1) / 2 > idx) --bj;
+            while ((bj + 1) * (bj + 2) / 2 <= idx) ++bj;
+            const int bi = idx - bj * (bj + 1) / 2;
+            T acc[4][4];
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) acc[ii][jj] = T(0);
+#pragma unroll 4
+            for (int q = 0; q < S; ++q) {
+                T pi[4], pj[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    pi[e] = Pt[q][4 * bi + e];
+                    pj[e] = Pt[q][4 * bj + e];
+                }
 #pragma unroll
                 for (int ii = 0; ii < 4; ++ii)
 #pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) acc[ii][jj] = T(0);
-                for (int q = 0; q < w; ++q) {
-                    T pi[4], pj[4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        pi[e] = Ps[q][4 * bi + e];
-                        pj[e] = Ps[q][4 * bj + e];
-                    }
-#pragma unroll
-                    for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-                        for (int jj = 0; jj < 4; ++jj) acc[ii][jj] += pi[ii] * pj[jj];
-                }
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int j = 4 * bj + jj;
-                    if (j < rest) {
-#pragma unroll
-                        for (int ii = 0; ii < 4; ++ii) {
-                            const int i = 4 * bi + ii;
-                            if (i <= j) T0[i + (int64_t)j * lda] -= acc[ii][jj];
-                        }
-                    }
-                }
+                    for (int jj = 0; jj < 4; ++jj) acc[ii][jj] += pi[ii] * pj[jj];
             }
-            __syncthreads();
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii)
+                    if (4 * bi + ii <= 4 * bj + jj) L[(o + 4 * bj + jj) * kLdsLd + o + 4 * bi + ii] -= acc[ii][jj];
         }
+        __syncthreads();
     }
+    // store the upper triangle
+    for (int col = wave; col < n; col += 4)
+        for (int row = lane; row <= col; row += 64) A[(int64_t)row + (int64_t)col * lda] = L[col * kLdsLd + row];
 }
 
 template <typename T>
 int launch_chol_block(int n, T *A, int64_t lda, int32_t *info, int64_t info_base, hipStream_t s) {
     if (n <= 0) return FLAME_OK;
+    if (n > kLdsN) {
+        // n in (128, 256]: the same loop one level up, with the LDS kernel on the
+        // two diagonal blocks: Chol(A11); A12 := U11^{-T} A12; A22 -= A12^T A12;
+        // Chol(A22)
+        const int n1 = kLdsN, n2 = n - kLdsN;
+        int rc = launch_chol_block<T>(n1, A, lda, info, info_base, s);
+        if (rc) return rc;
+        rc = launch_trsm_panel<T>(n1, n2, A, lda, A + (int64_t)n1 * lda, lda, info, s);
+        if (rc) return rc;
+        rc = launch_gemm_tn(sizeof(T) == 8 ? Prec::F64 : Prec::F32, sizeof(T) == 8, true, n2, n2, n1,
+                            A + (int64_t)n1 * lda, lda, A + (int64_t)n1 * lda, lda, A + n1 + (int64_t)n1 * lda, lda,
+                            info, s);
+        if (rc) return rc;
+        return launch_chol_block<T>(n2, A + n1 + (int64_t)n1 * lda, lda, info, info_base + n1, s);
+    }
     const int tr = trace_begin(FLAME_KC_CHOL, s);
-    hipLaunchKernelGGL(k_chol_block<T>, dim3(1), dim3(256), 0, s, n, A, lda, info, info_base);
+    hipLaunchKernelGGL((k_chol_lds<T, 16>), dim3(1), dim3(256), 0, s, n, A, lda, info, info_base);
     FLAME_CHECK_LAUNCH();
     const double dn = (double)n;
     trace_end(tr, s, dn * (dn + 1) * (2 * dn + 1) / 6.0, dn * (dn + 1) * (double)sizeof(T));

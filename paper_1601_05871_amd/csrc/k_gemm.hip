@@ -21,6 +21,8 @@
 // Precisions: F64 (v_mfma_f64_16x16x4_f64), F32 (v_mfma_f32_16x16x4_f32) and
 // BF16 inputs (v_mfma_f32_16x16x32_bf16), FP32 accumulation for the latter
 // two; with an FP64 C the FP32 sum is subtracted in FP64 at the end.
+#include <algorithm>
+
 #include "flame_internal.h"
 #include "tile_map.h"
 
@@ -501,9 +503,207 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
 #undef FLAME_CCOL
 }
 
+// ---- 8-wavefront persistent LDS-staged variant --------------------------------
+// One workgroup of eight wavefronts per CU (two per SIMD, so the FP64 MFMA
+// pipe always has a second wavefront to issue from), each wavefront a 64 x 32
+// part of the 128 x 128 tile (wave grid 2 x 4).  The k-chunk is 256 bytes per
+// column (32 FP64 / 64 FP32 / 128 BF16 values) and the two LDS buffers take
+// 128 KiB; 16-byte units are XOR-swizzled by (column mod 16).  The workgroup
+// is persistent: it walks tiles L, L + G, ... (G workgroups, L its
+// XCD-remapped index, so that the 32 workgroups of an XCD work on 32
+// consecutive tiles of the band order) and overlaps each tile's last chunk
+// with the loads of the next tile's first chunk and C tile, so no tile
+// prologue or epilogue is exposed.
+constexpr int kSlab8Bytes = kTile * 256;
+constexpr int64_t kPersistentWgs = 256;  // one per CU
+
+__device__ __forceinline__ int slab8_off(int col, int unit) { return col * 256 + ((unit ^ (col & 15)) << 4); }
+
+template <Prec P, typename CT>
+__global__ __launch_bounds__(512, 1) void k_gemm_p8(GemmP p) {
+    using TR = Tr<P>;
+    using in_t = typename TR::in_t;
+    using acc_t = typename TR::acc_t;
+    constexpr int CK = 256 / (int)sizeof(in_t);  // k per chunk
+    constexpr bool CINIT = (P == Prec::F64 && sizeof(CT) == 8) || (P == Prec::F32 && sizeof(CT) == 4);
+    __shared__ __attribute__((aligned(16))) char lds[2][2][kSlab8Bytes];
+
+    if (p.info != nullptr && *p.info != 0) return;
+    const int64_t G = gridDim.x;
+    int64_t tile = xcd_remap((int64_t)blockIdx.x, G);
+    if (tile >= p.ntiles) return;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int r = lane & 15;
+    const int g = lane >> 4;
+    const int wr = wave >> 2, wc = wave & 3;  // 2 x 4 wave grid
+    const int64_t M = p.M, N = p.N, K = p.K, ldc = p.ldc;
+    const char *__restrict__ Xb = static_cast<const char *>(p.X);
+    const char *__restrict__ Yb = static_cast<const char *>(p.Y);
+    const int64_t ldxb = p.ldx * (int64_t)sizeof(in_t), ldyb = p.ldy * (int64_t)sizeof(in_t);
+    CT *__restrict__ C = static_cast<CT *>(p.C);
+    const int64_t nch = K / CK;
+    constexpr int64_t chunk_bytes = 256;
+    // copy assignment: unit q = tid + 512 j (j < 8) of the 2 x 2048 units of a
+    // chunk: operand j / 4, column tid / 16 + 32 (j % 4), unit tid % 16
+    const int unit = tid & 15;
+    const int ccol0 = tid >> 4;
+    int dofs[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dofs[j] = slab8_off(ccol0 + 32 * j, unit);
+    const int xr = wr * 64 + r, yr = wc * 32 + r;
+
+    // per-tile state
+    int64_t tr0, tc0, row0, col0;
+    int64_t xoff[4], yoff[4];
+    auto set_tile = [&](int64_t tt) {
+        int I, J;
+        tile_of(tt, p.tm, p.tn, p.upper != 0, I, J);
+        tr0 = (int64_t)I * kTile;
+        tc0 = (int64_t)J * kTile;
+        row0 = tr0 + wr * 64;
+        col0 = tc0 + wc * 32;
+    };
+    auto set_offsets = [&]() {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = ccol0 + 32 * j;
+            xoff[j] = min(tr0 + col, M - 1) * ldxb + unit * 16;
+            yoff[j] = min(tc0 + col, N - 1) * ldyb + unit * 16;
+        }
+    };
+
+#define FLAME_CROW(a, v) ((P == Prec::F64) ? row0 + 16 * (a) + r : row0 + 16 * (a) + 4 * g + (v))
+#define FLAME_CCOL(b, v) ((P == Prec::F64) ? col0 + 16 * (b) + g + 4 * (v) : col0 + 16 * (b) + r)
+#define FLAME_LOADC()                                                                                 \
+    _Pragma("unroll") for (int a = 0; a < 4; ++a) _Pragma("unroll") for (int b = 0; b < 2; ++b)      \
+        _Pragma("unroll") for (int v = 0; v < 4; ++v) cpre[a][b][v] =                                 \
+            C[min(FLAME_CROW(a, v), M - 1) + min(FLAME_CCOL(b, v), N - 1) * ldc];
+#define FLAME_FETCH1(j, cidx)                                                                         \
+    stx[j] = *reinterpret_cast<const u32x4 *>(Xb + xoff[j] + (cidx) * chunk_bytes);                   \
+    sty[j] = *reinterpret_cast<const u32x4 *>(Yb + yoff[j] + (cidx) * chunk_bytes);
+#define FLAME_FETCH(cidx)                                                                             \
+    {                                                                                                 \
+        FLAME_FETCH1(0, cidx) FLAME_FETCH1(1, cidx) FLAME_FETCH1(2, cidx) FLAME_FETCH1(3, cidx)       \
+    }
+#define FLAME_PUT1(j, buf)                                                                            \
+    *reinterpret_cast<u32x4 *>(&lds[buf][0][0] + dofs[j]) = stx[j];                                   \
+    *reinterpret_cast<u32x4 *>(&lds[buf][1][0] + dofs[j]) = sty[j];
+#define FLAME_PUT(buf)                                                                                \
+    {                                                                                                 \
+        FLAME_PUT1(0, buf) FLAME_PUT1(1, buf) FLAME_PUT1(2, buf) FLAME_PUT1(3, buf)                   \
+    }
+// lane (r, g) covers 16-byte units 4g .. 4g + 3 of each column, read and
+// multiplied one unit at a time
+#define FLAME_COMPUTE(buf)                                                                            \
+    {                                                                                                 \
+        const char *xs_ = &lds[buf][0][0];                                                            \
+        const char *ys_ = &lds[buf][1][0];                                                            \
+        _Pragma("unroll") for (int h = 0; h < 4; ++h) {                                               \
+            u32x4 fa_[4], fb_[2];                                                                     \
+            _Pragma("unroll") for (int a = 0; a < 4; ++a) {                                           \
+                fa_[a] = *reinterpret_cast<const u32x4 *>(xs_ + slab8_off(xr + 16 * a, 4 * g + h));   \
+                if constexpr (CINIT) fa_[a] = negate_half(P, fa_[a]);                                 \
+            }                                                                                         \
+            _Pragma("unroll") for (int b = 0; b < 2; ++b)                                             \
+                fb_[b] = *reinterpret_cast<const u32x4 *>(ys_ + slab8_off(yr + 16 * b, 4 * g + h));   \
+            _Pragma("unroll") for (int a = 0; a < 4; ++a)                                             \
+                _Pragma("unroll") for (int b = 0; b < 2; ++b) mfma_half<P>(acc[a][b], fa_[a], fb_[b]); \
+        }                                                                                             \
+    }
+
+    CT cpre[4][2][4];  // CINIT: the next tile's C; otherwise this tile's C
+    acc_t acc[4][2];
+    u32x4 stx[4], sty[4];
+
+    set_tile(tile);
+    set_offsets();
+    if constexpr (CINIT) {
+        FLAME_LOADC()
+    }
+    FLAME_FETCH(0)
+    FLAME_PUT(0)
+    __syncthreads();
+    int buf = 0;
+    for (;;) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[a][b][v] = CINIT ? cpre[a][b][v] : 0;
+        const int64_t next = tile + G;
+        const bool has_next = next < p.ntiles;
+        const int64_t crow0 = row0, ccol0t = col0;
+        for (int64_t c = 0; c < nch; ++c) {
+            const bool last = (c + 1 == nch);
+            if (!last) {
+                FLAME_FETCH(c + 1)
+            } else {
+                if constexpr (!CINIT) {
+                    FLAME_LOADC()  // this tile's C, for the epilogue
+                }
+                if (has_next) {
+                    set_tile(next);
+                    set_offsets();
+                    FLAME_FETCH(0)
+                    if constexpr (CINIT) {
+                        FLAME_LOADC()  // the next tile's C, its accumulator start
+                    }
+                }
+            }
+            FLAME_COMPUTE(buf)
+            __builtin_amdgcn_sched_barrier(0);
+            if (!last || has_next) {
+                FLAME_PUT(buf ^ 1)
+            }
+            __syncthreads();
+            buf ^= 1;
+        }
+        // epilogue of the tile just finished (its row0 / col0 were saved)
+        {
+            const int64_t rw0 = crow0, cl0 = ccol0t;
+            const bool active = (rw0 < M) && (cl0 < N) && !(p.upper && rw0 > cl0 + 31);
+            if (active) {
+                const bool interior = (rw0 + 64 <= M) && (cl0 + 32 <= N) && (!p.upper || rw0 + 63 <= cl0);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int64_t row = (P == Prec::F64) ? rw0 + 16 * a + r : rw0 + 16 * a + 4 * g + v;
+                            const int64_t col = (P == Prec::F64) ? cl0 + 16 * b + g + 4 * v : cl0 + 16 * b + r;
+                            if (interior || (row < M && col < N && (!p.upper || row <= col))) {
+                                if constexpr (CINIT)
+                                    C[row + col * ldc] = (CT)acc[a][b][v];
+                                else
+                                    C[row + col * ldc] = cpre[a][b][v] - (CT)acc[a][b][v];
+                            }
+                        }
+            }
+        }
+        if (!has_next) break;
+        tile = next;
+    }
+#undef FLAME_FETCH
+#undef FLAME_FETCH1
+#undef FLAME_PUT
+#undef FLAME_PUT1
+#undef FLAME_COMPUTE
+#undef FLAME_LOADC
+#undef FLAME_CROW
+#undef FLAME_CCOL
+}
+
 template <Prec P, typename CT>
 static int launch_t(const GemmP &p, bool vec, hipStream_t s) {
     constexpr int64_t CK = 4 * Tr<P>::VEC;
+    constexpr int64_t CK8 = 2 * CK;
+    // FP64 runs best as two 4-wavefront workgroups per CU (k_gemm_lds); the
+    // FP32 / BF16 products as one persistent 8-wavefront workgroup (k_gemm_p8)
+    const bool lds8_ok = P != Prec::F64 && vec && p.K > 0 && (p.K % CK8) == 0;
     const bool lds_ok = vec && p.K > 0 && (p.K % CK) == 0;
     const unsigned grid = (unsigned)p.ntiles;
     // algorithmic work: 2K flops per updated element; each operand element
@@ -513,7 +713,10 @@ static int launch_t(const GemmP &p, bool vec, hipStream_t s) {
     const double esz = P == Prec::F64 ? 8.0 : (P == Prec::F32 ? 4.0 : 2.0);
     const double panel = (p.X == p.Y && p.M == p.N) ? K * M : K * (M + N);
     const int tr = trace_begin(FLAME_KC_GEMM, s);
-    if (lds_ok)
+    if (lds8_ok)
+        hipLaunchKernelGGL((k_gemm_p8<P, CT>), dim3((unsigned)std::min<int64_t>(p.ntiles, kPersistentWgs)), dim3(512), 0,
+                           s, p);
+    else if (lds_ok)
         hipLaunchKernelGGL((k_gemm_lds<P, CT>), dim3(grid), dim3(256), 0, s, p);
     else if (vec)
         hipLaunchKernelGGL((k_gemm_tn<P, CT, true>), dim3(grid), dim3(256), 0, s, p);

@@ -55,25 +55,33 @@ __global__ __launch_bounds__(64) void k_trsm_panel(int b, int64_t m, const T *__
     }
 }
 
-// ---- FP64 matrix-core panel solve -----------------------------------------
-// The same solve blocked by 16 rows, each wavefront owning 16 columns of X:
-//   R   = X_s - sum_{q < s} U(q, s)^T X_q   (16 x 16 blocks, MFMA)
-//   X_s = D_s^{-T} R                        (D_s^{-1}: inverse of the 16 x 16
-//                                            diagonal block of U, MFMA)
-// The workgroup inverts the diagonal blocks once (back substitution, one lane
-// per column) into LDS; the solved rows of each wavefront stay in LDS for the
-// later blocks.  MFMA operand/output placement as in the trailing update:
-// lane (r, g) holds row r, columns g + 4v of a 16 x 16 result.
+// ---- FP64 matrix-core panel solve (b <= 128) -------------------------------
+// The solve blocked by 16 rows (U padded with the identity to a multiple of
+// 16).  Each workgroup first forms the inverses D_s = U_ss^{-1} of the 16 x 16
+// diagonal blocks in LDS (16 lanes per block, one lane per column, back
+// substitution).  Then each wavefront owns 16 columns of X, keeps all of its
+// row blocks in registers and runs the right-looking loop
+//   X_s = D_s^T R_s;   R_t -= U(s, t)^T X_s  for t > s
+// on FP64 matrix cores, fully unrolled over the eight row blocks so that the
+// loads of U are independent of the arithmetic and can be issued early.  MFMA
+// placement as in the trailing update: lane (r, g) holds row r, columns
+// g + 4v of a 16 x 16 block.
 typedef double d4v __attribute__((ext_vector_type(4)));
+constexpr int kTrsmNb = 8;  // row blocks of 16: b <= 128
 
-template <int NW, int BMAX>
-__global__ __launch_bounds__(64 * NW) void k_trsm_mfma(int b, int64_t m, const double *__restrict__ U, int64_t ldu,
-                                                      double *__restrict__ X, int64_t ldx,
-                                                      const int32_t *__restrict__ info) {
-    constexpr int P = 17;  // padded row length
-    __shared__ double Xs[NW][BMAX][P];       // solved rows, [row][column] per wavefront
-    __shared__ double Dv[BMAX / 16][16][P];  // D_s^{-1}, [k][i]
-    __shared__ double Rt[NW][16][P];         // R of the current block, [row][column]
+// U(i, j) with rows / columns >= b read as the identity
+__device__ __forceinline__ double u_pad(const double *__restrict__ U, int64_t ldu, int b, int i, int j) {
+    const double v = U[(int64_t)min(i, b - 1) + (int64_t)min(j, b - 1) * ldu];
+    return (i < b && j < b) ? v : (i == j ? 1.0 : 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_trsm_rl(int b, int64_t m, const double *__restrict__ U, int64_t ldu,
+                                                 double *__restrict__ X, int64_t ldx,
+                                                 const int32_t *__restrict__ info) {
+    constexpr int NB = kTrsmNb;
+    __shared__ double Ub[NB][16][17];  // diagonal blocks of U, [block][row][col]
+    __shared__ double Ds[NB][16][17];  // their inverses, [block][k][col]
+    __shared__ double Rt[4][16][17];   // per wavefront: one block in operand layout
     if (info != nullptr && *info != 0) return;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -81,81 +89,78 @@ __global__ __launch_bounds__(64 * NW) void k_trsm_mfma(int b, int64_t m, const d
     const int r = lane & 15;
     const int g = lane >> 4;
     const int nblk = (b + 15) >> 4;
-    // U(i, j) with rows/columns >= b read as the identity
-    auto uat = [&](int i, int j) -> double {
-        const bool in = (i < b) && (j < b);
-        const double v = U[(int64_t)min(i, b - 1) + (int64_t)min(j, b - 1) * ldu];
-        return in ? v : (i == j ? 1.0 : 0.0);
-    };
-
-    // (1) inverses of the diagonal blocks: wavefront w takes blocks w, w + NW, ..;
-    //     lane t < 16 computes column t of D_s^{-1} (U D = I, back substitution)
-    for (int sb = wave; sb < nblk; sb += NW) {
-        const int o = 16 * sb;
-        if (lane < 16) {
-            const int t = lane;
-            double v[16];
+    // (1) diagonal blocks and their inverses
+    for (int idx = tid; idx < NB * 256; idx += 256) {
+        const int sb = idx >> 8, i = (idx >> 4) & 15, j = idx & 15;
+        Ub[sb][i][j] = u_pad(U, ldu, b, 16 * sb + i, 16 * sb + j);
+    }
+    __syncthreads();
+    if (tid < NB * 16) {
+        const int sb = tid >> 4, t = tid & 15;  // column t of D_sb: U_ss D(:, t) = e_t
+        double v[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = 0.0;
+        for (int i = 15; i >= 0; --i) {
+            double acc = (i == t) ? 1.0 : 0.0;
 #pragma unroll
-            for (int i = 15; i >= 0; --i) {
-                if (i <= t) {
-                    double acc = (i == t) ? 1.0 : 0.0;
-#pragma unroll
-                    for (int k = i + 1; k < 16; ++k)
-                        if (k <= t) acc -= uat(o + i, o + k) * v[k];
-                    v[i] = acc / uat(o + i, o + i);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) Dv[sb][i][t] = v[i];  // D(i, t), i.e. [k = i][column t]
+            for (int k = i + 1; k < 16; ++k) acc -= Ub[sb][i][k] * v[k];
+            v[i] = acc / Ub[sb][i][i];  // rows below the diagonal come out 0
         }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Ds[sb][i][t] = v[i];
     }
     __syncthreads();
 
-    const int64_t c0 = ((int64_t)blockIdx.x * NW + wave) * 16;  // this wavefront's first column
-    const bool colok_any = c0 < m;
-    for (int s = 0; s < nblk; ++s) {
-        const int rs = 16 * s;
-        // R = X_s (rows rs + r, columns c0 + g + 4v)
-        d4v acc;
+    // (2) right-looking solve of this wavefront's 16 columns
+    const int64_t c0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    int64_t colc[4];
+    bool colok[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t col = c0 + g + 4 * v;
+        colok[v] = col < m;
+        colc[v] = min(col, m - 1);
+    }
+    d4v acc[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        const int row = 16 * t + r;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t col = c0 + g + 4 * v;
-            const int row = rs + r;
-            const double x = X[(int64_t)min(row, b - 1) + min(col, m - 1) * ldx];
-            acc[v] = (row < b && col < m) ? x : 0.0;
+            const double x = X[(int64_t)min(row, b - 1) + colc[v] * ldx];
+            acc[t][v] = (row < b && colok[v]) ? x : 0.0;
         }
-        // R -= U(q-rows, s-cols)^T X_q for q < s; k slot (g, t) <-> row 16q + 4g + t
-        for (int q = 0; q < s; ++q) {
-            const int kq = 16 * q + 4 * g;
-            double uq[4], xq[4];
+    }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                uq[t] = uat(kq + t, rs + r);       // U(k, rs + i), i = r
-                xq[t] = -Xs[wave][kq + t][r];      // X(k, column r), negated
+    for (int s = 0; s < NB; ++s) {
+        if (s < nblk) {
+            // X_s = D_s^T R_s: R_s through LDS into operand layout
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Rt[wave][r][g + 4 * v] = acc[s][v];
+            d4v xs = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int t4 = 0; t4 < 4; ++t4) {
+                const int k = 4 * g + t4;
+                xs = __builtin_amdgcn_mfma_f64_16x16x4f64(Rt[wave][k][r], Ds[s][k][r], xs, 0, 0, 0);
             }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xq[t], uq[t], acc, 0, 0, 0);
-        }
-        // R to LDS as [row][column]
+            for (int v = 0; v < 4; ++v) {
+                Rt[wave][r][g + 4 * v] = -xs[v];
+                if (16 * s + r < b && colok[v]) X[(int64_t)(16 * s + r) + colc[v] * ldx] = xs[v];
+            }
+            // R_t -= U(s-rows, t-cols)^T X_s
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Rt[wave][r][g + 4 * v] = acc[v];
-        __syncthreads();
-        // X_s = D_s^{-T} R
-        d4v xs = {0.0, 0.0, 0.0, 0.0};
+            for (int t = s + 1; t < NB; ++t) {
+                if (t < nblk) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int k = 4 * g + t;
-            xs = __builtin_amdgcn_mfma_f64_16x16x4f64(Rt[wave][k][r], Dv[s][k][r], xs, 0, 0, 0);
+                    for (int t4 = 0; t4 < 4; ++t4) {
+                        const int k = 4 * g + t4;
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Rt[wave][k][r],
+                                                                      u_pad(U, ldu, b, 16 * s + k, 16 * t + r), acc[t],
+                                                                      0, 0, 0);
+                    }
+                }
+            }
         }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            Xs[wave][rs + r][g + 4 * v] = xs[v];
-            const int64_t col = c0 + g + 4 * v;
-            if (colok_any && rs + r < b && col < m) X[(int64_t)(rs + r) + col * ldx] = xs[v];
-        }
-        __syncthreads();
     }
 }
 
@@ -163,17 +168,23 @@ template <typename T>
 int launch_trsm_panel(int b, int64_t m, const T *U, int64_t ldu, T *X, int64_t ldx, const int32_t *info,
                       hipStream_t s) {
     if (b <= 0 || m <= 0) return FLAME_OK;
+    if constexpr (sizeof(T) == 8) {
+        if (b > 16 * kTrsmNb) {
+            // two row halves: X_top := U_tt^{-T} X_top; X_bot -= U_tb^T X_top;
+            // X_bot := U_bb^{-T} X_bot
+            const int b1 = 16 * kTrsmNb, b2 = b - b1;
+            int rc = launch_trsm_panel<T>(b1, m, U, ldu, X, ldx, info, s);
+            if (rc) return rc;
+            rc = launch_gemm_tn(Prec::F64, true, false, b2, m, b1, U + (int64_t)b1 * ldu, ldu, X, ldx, X + b1, ldx,
+                                info, s);
+            if (rc) return rc;
+            return launch_trsm_panel<T>(b2, m, U + b1 + (int64_t)b1 * ldu, ldu, X + b1, ldx, info, s);
+        }
+    }
     const int tr = trace_begin(FLAME_KC_TRSM, s);
     if constexpr (sizeof(T) == 8) {
-        if (b <= 128) {
-            const int64_t blocks = (m + 63) / 64;
-            hipLaunchKernelGGL((k_trsm_mfma<4, 128>), dim3((unsigned)blocks), dim3(256), 0, s, b, m, U, ldu, X, ldx,
-                               info);
-        } else {
-            const int64_t blocks = (m + 31) / 32;
-            hipLaunchKernelGGL((k_trsm_mfma<2, 256>), dim3((unsigned)blocks), dim3(128), 0, s, b, m, U, ldu, X, ldx,
-                               info);
-        }
+        const int64_t blocks = (m + 63) / 64;
+        hipLaunchKernelGGL(k_trsm_rl, dim3((unsigned)blocks), dim3(256), 0, s, b, m, U, ldu, X, ldx, info);
     } else {
         const int64_t blocks = (m + 63) / 64;
         hipLaunchKernelGGL(k_trsm_panel<T>, dim3((unsigned)blocks), dim3(64), 0, s, b, m, U, ldu, X, ldx, info);

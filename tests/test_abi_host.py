@@ -58,7 +58,7 @@ def test_factor_argument_errors(args, expect):
 
 
 @pytest.mark.parametrize("field,value", [("variant", 9), ("nb", 257), ("nb", -1), ("trail", 3),
-                                         ("lookahead", 2), ("graph", 5)])
+                                         ("lookahead", 3), ("graph", 5)])
 def test_factor_bad_options(field, value):
     o = _opts(**{field: value})
     assert fl.lib().flame_factor(0, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == -5
