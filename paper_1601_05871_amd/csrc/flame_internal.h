@@ -76,6 +76,22 @@ int launch_round_panel(Prec p, int64_t rows, int64_t cols, const double *X, int6
                        const int32_t *info, hipStream_t s);
 
 // ---- solve and residual kernels -------------------------------------------
+// Dt_q = U_qq^{-T} for the diagonal blocks of order bs (<= 128); Dt must hold
+// identity blocks on entry (see launch_identity_blocks).
+int launch_diag_inverse_t(int64_t n, int bs, const double *U, int64_t ldu, double *Dt, hipStream_t s);
+int launch_identity_blocks(int64_t nblk, int bs, double *Dt, hipStream_t s);
+// One right-hand side: U^T y = b (fwd) and U x = y (bwd) in place on x, one
+// persistent launch each, using the block inverses Dt; flags: nblk ints
+// (cleared here), err: one int set to 1 if a wait gave up.
+int launch_trsv1(bool forward, int64_t n, const double *U, int64_t ldu, const double *Dt, double *x, int32_t *flags,
+                 int32_t *err, hipStream_t s);
+// Residual R = B - A0 X (A0 symmetric from its upper triangle), nrhs <= 8,
+// through per-tile partial sums (deterministic); also rowsums of |A0| when
+// rowsums != nullptr.  part: workspace of tiles^2 * 128 * (nrhs + 1) doubles.
+int launch_residual_tiled(int64_t n, int64_t nrhs, const double *A0, int64_t lda0, const double *X, int64_t ldx,
+                          const double *B, int64_t ldb, double *R, int64_t ldr, double *rowsums, double *part,
+                          hipStream_t s);
+size_t residual_workspace_doubles(int64_t n, int64_t nrhs);
 template <typename T>
 int launch_trsv_fwd(int64_t n, int64_t nrhs, const T *U, int64_t ldu, T *B, int64_t ldb, hipStream_t s);
 template <typename T>

@@ -77,7 +77,11 @@ __device__ __forceinline__ double u_pad(const double *__restrict__ U, int64_t ld
 
 __global__ __launch_bounds__(256) void k_trsm_rl(int b, int64_t m, const double *__restrict__ U, int64_t ldu,
                                                  double *__restrict__ X, int64_t ldx,
-                                                 const int32_t *__restrict__ info) {
+                                                 const int32_t *__restrict__ info, int64_t u_step, int64_t x_step) {
+    // blockIdx.y selects one of several independent solves (U and X advanced
+    // by u_step and x_step elements)
+    U += (int64_t)blockIdx.y * u_step;
+    X += (int64_t)blockIdx.y * x_step;
     constexpr int NB = kTrsmNb;
     __shared__ double Ub[NB][16][17];  // diagonal blocks of U, [block][row][col]
     __shared__ double Ds[NB][16][17];  // their inverses, [block][k][col]
@@ -184,7 +188,8 @@ int launch_trsm_panel(int b, int64_t m, const T *U, int64_t ldu, T *X, int64_t l
     const int tr = trace_begin(FLAME_KC_TRSM, s);
     if constexpr (sizeof(T) == 8) {
         const int64_t blocks = (m + 63) / 64;
-        hipLaunchKernelGGL(k_trsm_rl, dim3((unsigned)blocks), dim3(256), 0, s, b, m, U, ldu, X, ldx, info);
+        hipLaunchKernelGGL(k_trsm_rl, dim3((unsigned)blocks), dim3(256), 0, s, b, m, U, ldu, X, ldx, info, (int64_t)0,
+                           (int64_t)0);
     } else {
         const int64_t blocks = (m + 63) / 64;
         hipLaunchKernelGGL(k_trsm_panel<T>, dim3((unsigned)blocks), dim3(64), 0, s, b, m, U, ldu, X, ldx, info);
@@ -192,6 +197,28 @@ int launch_trsm_panel(int b, int64_t m, const T *U, int64_t ldu, T *X, int64_t l
     FLAME_CHECK_LAUNCH();
     const double db = (double)b, dm = (double)m;
     trace_end(tr, s, db * db * dm, (db * (db + 1) / 2 + 2 * db * dm) * (double)sizeof(T));
+    return FLAME_OK;
+}
+
+// Inverses of the diagonal blocks of U (order <= 128 each, `nblk` blocks of
+// order bs starting at U(0, 0), the last one min(bs, n - o)): Dt_q = U_qq^{-T},
+// bs x bs column-major at Dt + q bs^2.  Dt must hold the identity on entry.
+int launch_diag_inverse_t(int64_t n, int bs, const double *U, int64_t ldu, double *Dt, hipStream_t s) {
+    const int64_t nblk = (n + bs - 1) / bs;
+    const int64_t full = n / bs;  // blocks of order bs
+    if (full > 0) {
+        hipLaunchKernelGGL(k_trsm_rl, dim3((unsigned)((bs + 63) / 64), (unsigned)full), dim3(256), 0, s, bs, (int64_t)bs,
+                           U, ldu, Dt, (int64_t)bs, nullptr, (int64_t)bs * (ldu + 1), (int64_t)bs * bs);
+        FLAME_CHECK_LAUNCH();
+    }
+    if (nblk > full) {
+        const int64_t o = full * bs;
+        const int last = (int)(n - o);
+        hipLaunchKernelGGL(k_trsm_rl, dim3((unsigned)((last + 63) / 64), 1u), dim3(256), 0, s, last, (int64_t)last,
+                           U + o + o * ldu, ldu, Dt + full * (int64_t)bs * bs, (int64_t)bs, nullptr, (int64_t)0,
+                           (int64_t)0);
+        FLAME_CHECK_LAUNCH();
+    }
     return FLAME_OK;
 }
 

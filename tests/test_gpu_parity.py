@@ -279,7 +279,10 @@ def test_factor_graph_replays():
 
 # ---- solve and refinement ------------------------------------------------------
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (100, 1), (513, 3), (1000, 64)])
+# n spans single and multiple 128-row blocks with ragged tails; nrhs <= 8
+# takes the single-launch FP64 path, larger nrhs the blocked one
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (100, 1), (127, 1), (128, 2), (129, 1), (513, 3), (1000, 8),
+                                    (1000, 9), (1000, 64), (2500, 1)])
 def test_solve_plain(n, nrhs):
     A = inputs.spd_bbt(n, 8)
     Uo, _ = oracle.potrf(A, threads=8)
@@ -315,6 +318,40 @@ def test_mixed_factor_and_refinement(trail, kappa, nrhs):
     assert rep["eta"] <= 1e-13
     assert oracle.solve_backward_error(A0, X, B) <= 1e-13
     assert np.linalg.norm(X - x_star) / np.linalg.norm(x_star) <= kappa * 1e-13
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 9])
+def test_refinement_eta_matches_oracle(nrhs):
+    """With max_iter = 0 the reported eta is that of the first solve: checks
+    the device residual and norms against the oracle's definition."""
+    n = 700
+    A0 = inputs.spd_kappa(n, 1e4, 3)
+    B = inputs.rhs(n, nrhs, 3)
+    Ad = to_dev(A0)
+    A0d = to_dev(A0, ld=n + 3)
+    fl.factor(Ad, variant=3, nb=128, trail="f32")
+    Bd = to_dev(B, ld=n + 1)
+    rep = fl.solve(Ad, Bd, A0=A0d, tol=0.0, max_iter=0)
+    X = to_host(Bd)
+    assert rep["iters"] == 0 and rep["status"] == fl.FLAME_ERR_NOT_CONVERGED
+    eta_o = oracle.solve_backward_error(A0, X, B)
+    assert eta_o > 1e-12  # the FP32-trailing factor leaves a visible residual
+    assert abs(rep["eta"] - eta_o) <= 1e-3 * eta_o
+
+
+def test_solve_refinement_converges_large():
+    """Multi-block single-launch solves inside refinement (n = 3000)."""
+    n = 3000
+    A0 = inputs.spd_kappa(n, 1e3, 5)
+    B = inputs.rhs(n, 1, 5)
+    Ad = to_dev(A0)
+    A0d = to_dev(A0)
+    fl.factor(Ad, variant=3, nb=256, trail="f32")
+    Bd = to_dev(B)
+    rep = fl.solve(Ad, Bd, A0=A0d, tol=1e-14, max_iter=30)
+    X = to_host(Bd)
+    assert rep["status"] == fl.FLAME_OK and rep["iters"] >= 1, rep
+    assert oracle.solve_backward_error(A0, X, B) <= 1.5e-14
 
 
 def test_mixed_minij_exact():
