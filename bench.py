@@ -56,6 +56,9 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="one plain device copy of this many GiB before the timed region (a reference "
+                         "kernel of known traffic for HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -71,6 +74,14 @@ def main() -> int:
     fl.lib()  # fails loudly if the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe_gib > 0:
+        words = int(args.copy_probe_gib * (1 << 30)) // 8
+        src = torch.ones(words, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)  # a streaming kernel of its own name: reads and writes words * 8 bytes
+        torch.cuda.synchronize()
+        log(f"copy probe (neg kernel): {words * 8} bytes read, {words * 8} bytes written")
+        del src, dst
     n, K, W = args.n, max(1, args.steps), max(0, args.warmup)
     log(f"generating A = B B^T + n I, n={n}, seed={args.seed}")
     P = inputs.spd_bbt_torch(n, args.seed, dev)  # pristine, column-major
@@ -116,13 +127,13 @@ def main() -> int:
     g = trace["gemm"]
     gemm_tflops = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
     roofline = {
-        "kernel": "k_gemm_tn<F64> (trailing SYRK/GEMM)",
+        "kernel": "k_gemm_lds<F64> (trailing SYRK/GEMM)",
         "bound": "mfma",
         "achieved": round(gemm_tflops, 3),
         "peak": PEAK_F64_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(gemm_tflops / PEAK_F64_TFLOPS, 4),
-        "traffic": None,
+        "traffic": gemm_traffic(),
         "launches_per_step": g["launches"] / K,
         "avg_launch_ms": g["ms"] / max(1, g["launches"]),
         "avg_launch_gflop": g["flops"] / max(1, g["launches"]) / 1e9,
@@ -167,6 +178,34 @@ def main() -> int:
         result["cpu_baseline"] = cpu_leg(P, n, args.cpu_seconds)
     print(json.dumps(result), flush=True)
     return 0
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_gemm_lds_f64_n16384_traffic.md")
+
+
+def gemm_traffic():
+    """HBM bytes per trailing-update launch at this workload, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (calibrated against a
+    plain copy); None when that summary is missing or was taken on other
+    kernel sources."""
+    from paper_1601_05871_amd import profile_summary
+
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip("` ")] = v.strip("` ")
+    if fields.get("source_hash") != profile_summary.gemm_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def factor_backward_error_est(A_dev, U_dev, k: int = 8, seed: int = 0) -> float:
