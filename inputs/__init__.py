@@ -167,6 +167,28 @@ def batch(count: int, seed: int = 0, lo: int = 16, hi: int = 512):
     return sizes, _batch_from(g, sizes)
 
 
+def batch_torch(count: int, seed: int, device, lo: int = 16, hi: int = 512, dtype=None):
+    """The matrices of ``batch(count, seed, lo, hi)`` (same sizes, same B_i
+    from the same stream) with each product B_i B_i^T formed by torch on
+    ``device``; returns (sizes, list of column-major device tensors).  The
+    bytes can differ from ``batch`` in the last bit (summation order)."""
+    import torch
+
+    dtype = torch.float64 if dtype is None else dtype
+    g = _rng(seed)
+    sizes = g.integers(lo, hi, endpoint=True, size=count).astype(np.int32)
+    out = []
+    for n in sizes:
+        n = int(n)
+        B = torch.from_numpy(g.standard_normal((n, n), dtype=np.float64)).to(device)
+        A = B @ B.T
+        A.diagonal().add_(float(n))
+        A = torch.triu(A)
+        A = A + torch.triu(A, 1).T
+        out.append(A.to(dtype).T.contiguous().T)
+    return sizes, out
+
+
 def _batch_from(g, sizes):
     out = []
     for n in sizes:

@@ -203,14 +203,31 @@ def solve(U, B, A0=None, tol: float = 1e-13, max_iter: int = 30):
     return {"iters": rep.iters, "eta": rep.eta_max, "status": rc}
 
 
-def batched_factor(ns, ptrs, ldas, info, dtype=F64, opts: Opts | None = None):
-    """Factors len(ns) matrices in one launch.  ``ns``, ``ldas``, ``info``:
-    device int32 tensors; ``ptrs``: device int64 tensor of matrix addresses."""
+def batched_factor(ns, ptrs, ldas, info, dtype=F64, opts: Opts | None = None, graph: int | None = None):
+    """Factors len(ns) matrices in one persistent launch.  ``ns``, ``ldas``,
+    ``info``: device int32 tensors; ``ptrs``: device int64 tensor of matrix
+    addresses.  ``graph``: 1 = capture / replay a HIP graph (the default), 0 =
+    direct launch."""
+    if graph is not None:
+        opts = _opts(VAR_RIGHT, 0, 0, 0, graph)
     rc = lib().flame_batched_factor(int(dtype), int(ns.numel()), ns.data_ptr(), ptrs.data_ptr(), ldas.data_ptr(),
                                     info.data_ptr(), ctypes.byref(opts) if opts is not None else None,
                                     _stream_ptr())
     _check("flame_batched_factor", rc)
     return info
+
+
+def batched_pointers(mats):
+    """(ns, ptrs, ldas) device arrays for a list of square column-major device
+    tensors of one dtype (marshalling for :func:`batched_factor`)."""
+    torch = _torch()
+    if not mats:
+        raise ValueError("empty list")
+    dev = mats[0].device
+    ns = torch.tensor([int(M.shape[0]) for M in mats], dtype=torch.int32, device=dev)
+    ptrs = torch.tensor([int(M.data_ptr()) for M in mats], dtype=torch.int64, device=dev)
+    ldas = torch.tensor([_colmajor_ld(M) for M in mats], dtype=torch.int32, device=dev)
+    return ns, ptrs, ldas
 
 
 def trace_enable(on: bool = True) -> None:

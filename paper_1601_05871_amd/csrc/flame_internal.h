@@ -111,9 +111,11 @@ int launch_eta_full(int64_t n, int64_t nrhs, const double *R, int64_t ldr, const
                     const double *B, int64_t ldb, const double *rowsums, double *eta, hipStream_t s);
 
 // ---- batched -------------------------------------------------------------
+// ws: batched_workspace_ints(batch) ints (order, counter, histogram).
 template <typename T>
-int launch_batched(int32_t batch, const int32_t *n, void *const *A, const int32_t *lda, int32_t *info,
-                   int32_t *order, int32_t *counter, int32_t *hist, hipStream_t s);
+int launch_batched(int32_t batch, const int32_t *n, void *const *A, const int32_t *lda, int32_t *info, int32_t *ws,
+                   hipStream_t s);
+size_t batched_workspace_ints(int32_t batch);
 
 // ---- selector --------------------------------------------------------------
 int launch_selector(const float *w, const float *feat, int64_t count, float *logits, hipStream_t s);

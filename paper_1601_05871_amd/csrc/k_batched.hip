@@ -1,0 +1,314 @@
+// Batched factorization: many independent matrices A_i := Chol(A_i) (upper,
+// in place) of uneven orders in one persistent launch.
+//
+// Work distribution: the matrices are ordered by decreasing order n_i
+// (counting sort on the device: histogram, scan, scatter), and a persistent
+// grid of (CUs x resident workgroups) takes them from an atomic counter in
+// that order, largest first, so the long factorizations start early and the
+// small ones fill the tail (longest-processing-time-first scheduling).
+//
+// One workgroup (4 wavefronts) factors one matrix with the right-looking loop
+// of Fig. "dense-chol" at block size kBB = 32, on the matrix in HBM / L2:
+//   CHOL  wavefront 0 factors the 32 x 32 diagonal block in registers (one
+//         column per lane, the unblocked loop); U11 and 1 / diag go to LDS;
+//   TRSM  one thread per column of the row panel, forward substitution with
+//         U11^T from LDS;
+//   SYRK  the upper 32 x 32 tiles of A22 are spread over the wavefronts; each
+//         tile is a 2 x 2 set of 16 x 16 matrix-core products (FP64 or FP32
+//         MFMA, K = 32) accumulated onto the tile of A22.
+// A breakdown stops that matrix only (info[i] = first bad column, 1-based).
+#include "chol_wave.h"
+#include "flame_internal.h"
+
+namespace flame {
+
+constexpr int kBB = 32;            // block size inside a workgroup
+constexpr int kBatchMaxN = 1024;   // largest order accepted
+constexpr int kBuckets = kBatchMaxN + 2;  // orders 0..1024, plus one for invalid entries
+
+typedef double bd4 __attribute__((ext_vector_type(4)));
+typedef float bf4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct BAcc;
+template <>
+struct BAcc<double> {
+    typedef bd4 type;
+};
+template <>
+struct BAcc<float> {
+    typedef bf4 type;
+};
+
+// acc += x^T y for one k slot.  FP64: lane (r, g) item v of the result is
+// element (r, g + 4v) of the 16 x 16 block; FP32: element (4g + v, r).
+__device__ __forceinline__ bd4 mma(double x, double y, bd4 acc) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(y, x, acc, 0, 0, 0);
+}
+__device__ __forceinline__ bf4 mma(float x, float y, bf4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, acc, 0, 0, 0);
+}
+
+// Row and column (within a 16 x 16 block) of accumulator item v of lane (r, g).
+template <typename T>
+__device__ __forceinline__ int acc_row(int r, int g, int v) {
+    return sizeof(T) == 8 ? r : 4 * g + v;
+}
+template <typename T>
+__device__ __forceinline__ int acc_col(int r, int g, int v) {
+    return sizeof(T) == 8 ? g + 4 * v : r;
+}
+
+// C := C - P^T P on the upper triangle of the m x m matrix C, P is kBB x m.
+// Upper 32 x 32 tiles, column by column, are handed to the wavefronts in turn.
+template <typename T>
+__device__ void syrk_tiles(int m, const T *__restrict__ P, int64_t ldp, T *__restrict__ C, int64_t ldc, int wave,
+                           int lane) {
+    typedef typename BAcc<T>::type acc_t;
+    const int r = lane & 15, g = lane >> 4;
+    const int nt = (m + 31) >> 5;
+    const int ntasks = nt * (nt + 1) / 2;
+    for (int task = wave; task < ntasks; task += 4) {
+        int J = (int)((sqrtf(8.0f * (float)task + 1.0f) - 1.0f) * 0.5f);
+        while (J * (J + 1) / 2 > task) --J;
+        while ((J + 1) * (J + 2) / 2 <= task) ++J;
+        const int I = task - J * (J + 1) / 2;
+        const int rb = 32 * I, cb = 32 * J;
+        acc_t acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = rb + 16 * a + acc_row<T>(r, g, v);
+                    const int j = cb + 16 * b + acc_col<T>(r, g, v);
+                    acc[a][b][v] = C[(int64_t)min(i, m - 1) + (int64_t)min(j, m - 1) * ldc];
+                }
+        // operand columns (clamped; products of clamped columns are never stored)
+        const T *xp[2], *yp[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            xp[a] = P + (int64_t)min(rb + 16 * a + r, m - 1) * ldp;
+            yp[a] = P + (int64_t)min(cb + 16 * a + r, m - 1) * ldp;
+        }
+#pragma unroll
+        for (int kc = 0; kc < kBB; kc += 16) {
+            // lane (r, g) supplies k = kc + 4g + t in MFMA step t for both
+            // operands, so the k slots agree whatever the hardware's order
+            T x[2][4], y[2][4];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    x[a][t] = -xp[a][kc + 4 * g + t];
+                    y[a][t] = yp[a][kc + 4 * g + t];
+                }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) acc[a][b] = mma(x[a][t], y[b][t], acc[a][b]);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = rb + 16 * a + acc_row<T>(r, g, v);
+                    const int j = cb + 16 * b + acc_col<T>(r, g, v);
+                    if (i <= j && j < m) C[(int64_t)i + (int64_t)j * ldc] = acc[a][b][v];
+                }
+    }
+}
+
+// Factors one matrix with the whole workgroup; returns the info value.
+template <typename T>
+__device__ int factor_one(int n, T *__restrict__ A, int64_t lda, T (*Us)[kBB + 1], T *rinv, int *s_bad) {
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int k0 = 0; k0 < n; k0 += kBB) {
+        const int bk = min(kBB, n - k0);
+        const int m = n - k0 - bk;
+        // CHOL: wavefront 0, lane c holds column c of the block (identity
+        // past bk, so the unrolled code needs no guards)
+        if (wave == 0) {
+            T a[kBB];
+            const int c = min(lane, kBB - 1);
+            const T *col = A + k0 + (int64_t)(k0 + min(c, bk - 1)) * lda;
+#pragma unroll
+            for (int i = 0; i < kBB; ++i) {
+                const T v = col[min(i, bk - 1)];
+                a[i] = (c < bk) ? ((i <= c) ? v : T(0)) : (i == c ? T(1) : T(0));
+            }
+            T ri;
+            const int bad = chol_wave_full<T, kBB, true>(a, c, &ri);
+            if (lane == 0) *s_bad = bad;
+            if (lane < bk) {
+                T *colw = A + k0 + (int64_t)(k0 + lane) * lda;
+#pragma unroll
+                for (int i = 0; i < kBB; ++i) {
+                    if (i <= lane) colw[i] = a[i];
+                    Us[lane][i] = a[i];  // [column][row]
+                }
+                rinv[lane] = ri;
+            }
+        }
+        __syncthreads();
+        const int bad = __builtin_amdgcn_readfirstlane(*s_bad);
+        if (bad != 0) return k0 + bad;
+        if (m == 0) break;
+        // TRSM: A12 := U11^{-T} A12, bk == kBB here (m > 0)
+        for (int j = tid; j < m; j += 256) {
+            // keeps the U11 reads inside the loop (hoisted, they would not
+            // fit in registers)
+            asm volatile("" ::: "memory");
+            T *col = A + k0 + (int64_t)(k0 + kBB + j) * lda;
+            T x[kBB];
+#pragma unroll
+            for (int i = 0; i < kBB; ++i) x[i] = col[i];
+#pragma unroll
+            for (int q = 0; q < kBB; ++q) {
+                x[q] = x[q] * rinv[q];
+#pragma unroll
+                for (int t = q + 1; t < kBB; ++t) x[t] = x[t] - Us[t][q] * x[q];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int i = 0; i < kBB; ++i) col[i] = x[i];
+        }
+        __syncthreads();
+        // SYRK: A22 -= A12^T A12 (upper)
+        syrk_tiles<T>(m, A + k0 + (int64_t)(k0 + kBB) * lda, lda, A + (k0 + kBB) + (int64_t)(k0 + kBB) * lda, lda,
+                      wave, lane);
+        __syncthreads();
+    }
+    return 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_batched(int32_t batch, const int32_t *__restrict__ ns, T *const *As,
+                                                 const int32_t *__restrict__ ldas, int32_t *__restrict__ info,
+                                                 const int32_t *__restrict__ order, int32_t *counter) {
+    __shared__ T Us[kBB][kBB + 1];
+    __shared__ T rinv[kBB];
+    __shared__ int s_item, s_bad;
+    const int tid = threadIdx.x;
+    // Every value that steers the loop is made wave-uniform (readfirstlane):
+    // the branches around the barriers are then scalar, and every lane of a
+    // wavefront takes the same path through them.
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (t >= batch) break;  // every wave of the workgroup leaves together
+        const int i = __builtin_amdgcn_readfirstlane(order[t]);
+        const int n = __builtin_amdgcn_readfirstlane(ns[i]);
+        const int lda = __builtin_amdgcn_readfirstlane(ldas[i]);
+        int res = -1;  // order out of range or lda < n: not touched
+        if (n >= 0 && n <= kBatchMaxN && lda >= max(1, n)) res = factor_one<T>(n, As[i], (int64_t)lda, Us, rinv, &s_bad);
+        if (tid == 0) info[i] = res;
+        __syncthreads();
+    }
+}
+
+// ---- ordering: counting sort by decreasing order ------------------------------
+__device__ __forceinline__ int bucket_of(int n, int lda) {
+    return (n < 0 || n > kBatchMaxN || lda < max(1, n)) ? kBatchMaxN + 1 : n;
+}
+
+__global__ void k_batch_hist(int32_t batch, const int32_t *__restrict__ ns, const int32_t *__restrict__ ldas,
+                             int32_t *hist) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < batch) atomicAdd(hist + bucket_of(ns[i], ldas[i]), 1);
+}
+
+// start[b] = number of entries in buckets that come before b: invalid entries
+// first (they finish at once), then orders from kBatchMaxN down to 0.
+__global__ __launch_bounds__(256) void k_batch_scan(int32_t *hist) {
+    constexpr int PER = (kBuckets + 255) / 256;
+    __shared__ int part[256];
+    const int tid = threadIdx.x;
+    // position p in processing order: p = 0 is the invalid bucket, then
+    // p = 1 + (kBatchMaxN - n)
+    int loc[PER];
+    int sum = 0;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int p = tid * PER + e;
+        const int b = (p == 0) ? kBatchMaxN + 1 : kBatchMaxN - (p - 1);
+        loc[e] = (p < kBuckets) ? hist[b] : 0;
+        sum += loc[e];
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int v = (tid >= off) ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - sum;  // exclusive prefix of this thread's range
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int p = tid * PER + e;
+        if (p < kBuckets) {
+            const int b = (p == 0) ? kBatchMaxN + 1 : kBatchMaxN - (p - 1);
+            hist[b] = run;
+            run += loc[e];
+        }
+    }
+}
+
+__global__ void k_batch_scatter(int32_t batch, const int32_t *__restrict__ ns, const int32_t *__restrict__ ldas,
+                                int32_t *start, int32_t *__restrict__ order) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < batch) order[atomicAdd(start + bucket_of(ns[i], ldas[i]), 1)] = i;
+}
+
+size_t batched_workspace_ints(int32_t batch) { return (size_t)batch + kBuckets + 1; }
+
+template <typename T>
+int launch_batched(int32_t batch, const int32_t *n, void *const *A, const int32_t *lda, int32_t *info, int32_t *ws,
+                   hipStream_t s) {
+    if (batch <= 0) return FLAME_OK;
+    int32_t *hist = ws;                  // kBuckets
+    int32_t *counter = ws + kBuckets;    // 1
+    int32_t *order = ws + kBuckets + 1;  // batch
+    static int grid_cache[64] = {};
+    int dev = 0;
+    FLAME_HIP(hipGetDevice(&dev));
+    int grid = (dev < 64) ? grid_cache[dev] : 0;
+    if (grid == 0) {
+        int cus = 0, per = 0;
+        FLAME_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        FLAME_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<T>, 256, 0));
+        grid = std::max(1, cus * std::max(1, per));
+        if (dev < 64) grid_cache[dev] = grid;
+    }
+    int rc = launch_zero_i32(ws, kBuckets + 1, s);
+    if (rc) return rc;
+    const unsigned gb = (unsigned)((batch + 255) / 256);
+    hipLaunchKernelGGL(k_batch_hist, dim3(gb), dim3(256), 0, s, batch, n, lda, hist);
+    FLAME_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(256), 0, s, hist);
+    FLAME_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_batch_scatter, dim3(gb), dim3(256), 0, s, batch, n, lda, hist, order);
+    FLAME_CHECK_LAUNCH();
+    const int tr = trace_begin(FLAME_KC_OTHER, s);
+    hipLaunchKernelGGL(k_batched<T>, dim3((unsigned)std::min<int64_t>(grid, batch)), dim3(256), 0, s, batch, n,
+                       reinterpret_cast<T *const *>(A), lda, info, order, counter);
+    FLAME_CHECK_LAUNCH();
+    trace_end(tr, s, 0.0, 0.0);
+    return FLAME_OK;
+}
+
+template int launch_batched<double>(int32_t, const int32_t *, void *const *, const int32_t *, int32_t *, int32_t *,
+                                    hipStream_t);
+template int launch_batched<float>(int32_t, const int32_t *, void *const *, const int32_t *, int32_t *, int32_t *,
+                                   hipStream_t);
+
+}  // namespace flame

@@ -4,19 +4,6 @@
 
 extern "C" {
 
-int flame_batched_factor(int32_t dtype, int32_t batch, const int32_t *n, void *const *A, const int32_t *lda,
-                         int32_t *info, const flame_opts_t *opts, void *stream) {
-    (void)opts;
-    (void)stream;
-    if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
-    if (batch < 0) return -2;
-    if (batch > 0 && n == nullptr) return -3;
-    if (batch > 0 && A == nullptr) return -4;
-    if (batch > 0 && lda == nullptr) return -5;
-    if (batch > 0 && info == nullptr) return -6;
-    return FLAME_ERR_UNSUPPORTED;
-}
-
 int flame_selector_load(const float *w, int64_t count) {
     if (w == nullptr) return -1;
     if (count != FLAME_SEL_NPARAM) return -2;
