@@ -184,8 +184,9 @@ int flame_op_gemm_tn(int32_t dtype, int32_t trail, int32_t upper, int64_t mr, in
  * is_f64, is_f32, log10 kappa), classes = variant in {1,2,3} x nb in
  * {32,64,128,256} (class c -> variant 1 + c / 4, nb = 32 << (c % 4)).
  * `w` (host) holds W1[64][5], b1[64], W2[64][64], b2[64], W3[12][64], b3[12],
- * row-major, count = FLAME_SEL_NPARAM floats.  Copied to the device.
- * Errors: -1 w, -2 count. */
+ * row-major, count = FLAME_SEL_NPARAM floats.  Copied to each device on first
+ * use.  w == NULL with count == 0 unloads the weights (VAR_AUTO then uses the
+ * autotuner's table).  Errors: -1 w, -2 count. */
 #define FLAME_SEL_FEATURES 5
 #define FLAME_SEL_HIDDEN 64
 #define FLAME_SEL_CLASSES 12

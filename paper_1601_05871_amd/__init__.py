@@ -230,6 +230,53 @@ def batched_pointers(mats):
     return ns, ptrs, ldas
 
 
+# ---- selector and autotuner ---------------------------------------------------
+
+def selector_load(w) -> None:
+    """Loads the selector MLP weights (float32, FLAME_SEL_NPARAM values in the
+    header's order); ``None`` unloads them."""
+    import numpy as np
+
+    if w is None:
+        _check("flame_selector_load", lib().flame_selector_load(None, 0))
+        return
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float32).reshape(-1))
+    rc = lib().flame_selector_load(w.ctypes.data, int(w.size))
+    _check("flame_selector_load", rc)
+
+
+def select(n: int, batch: int = 1, dtype: int = F64, kappa: float = 0.0):
+    """(variant, nb) chosen by the loaded selector (runs its HIP kernel)."""
+    v, b = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = lib().flame_select(int(n), int(batch), int(dtype), float(kappa), ctypes.byref(v), ctypes.byref(b))
+    _check("flame_select", rc)
+    return int(v.value), int(b.value)
+
+
+def select_logits(features):
+    """Class logits of the selector MLP for feature rows (count x 5, float32)."""
+    import numpy as np
+
+    f = np.ascontiguousarray(np.asarray(features, dtype=np.float32).reshape(-1, SEL_FEATURES))
+    out = np.zeros((f.shape[0], SEL_CLASSES), dtype=np.float32)
+    rc = lib().flame_select_logits(f.ctypes.data, int(f.shape[0]), out.ctypes.data)
+    _check("flame_select_logits", rc)
+    return out
+
+
+def autotune(A, reps: int = 2):
+    """Median ms of every (variant, nb) candidate for factoring A (left
+    unchanged); 12 values in class order; records the best for VAR_AUTO."""
+    import numpy as np
+
+    n = A.shape[0]
+    t = np.zeros(SEL_CLASSES, dtype=np.float64)
+    rc = lib().flame_autotune(_dtype_code(A), n, A.data_ptr(), _colmajor_ld(A), int(reps), t.ctypes.data,
+                              _stream_ptr())
+    _check("flame_autotune", rc)
+    return t
+
+
 def trace_enable(on: bool = True) -> None:
     """Per-launch HIP-event timing of the library's kernels (instrumentation)."""
     _check("flame_trace_enable", lib().flame_trace_enable(int(bool(on))))

@@ -26,10 +26,7 @@ int normalize_opts(const flame_opts_t *in, int32_t dtype, int64_t n, flame_opts_
     if (o->graph < 0 || o->graph > 1) return -5;
     if (o->variant == FLAME_VAR_AUTO) {
         int32_t v = FLAME_VAR_RIGHT, nb = 0;
-        if (flame_select(n, 1, dtype, 0.0, &v, &nb) != FLAME_OK) {
-            v = FLAME_VAR_RIGHT;
-            nb = 0;
-        }
+        choose_variant(dtype, n, 1, &v, &nb);
         o->variant = v;
         if (o->nb == 0) o->nb = nb;
     }

@@ -15,6 +15,7 @@ hipError_t last_hip_error() { return g_last_hip; }
 struct DevCtx {
     int device = -1;
     hipStream_t side = nullptr;
+    hipStream_t aux = nullptr;  // selector inference (never captured)
     std::vector<hipEvent_t> events;
     void *ws[kWsSlots] = {};
     size_t ws_bytes[kWsSlots] = {};
@@ -32,7 +33,8 @@ DevCtx *ctx_for_current_device() {
     if (g_ctx[dev] == nullptr) {
         DevCtx *c = new DevCtx();
         c->device = dev;
-        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
             delete c;
             return nullptr;
         }
@@ -49,6 +51,7 @@ DevCtx *ctx_for_current_device() {
 }
 
 hipStream_t ctx_side_stream(DevCtx *c) { return c->side; }
+hipStream_t ctx_aux_stream(DevCtx *c) { return c->aux; }
 hipEvent_t ctx_event(DevCtx *c, int i) { return c->events[i]; }
 
 int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out) {

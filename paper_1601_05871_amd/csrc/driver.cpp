@@ -39,14 +39,18 @@ int gemm(bool upper, int64_t M, int64_t N, int64_t K, const T *X, int64_t ldx, c
 }
 
 // Split-K form of C -= X^T Y for the tall-K products of the left-looking and
-// bordered variants: the K range is cut into `slices` pieces, each applied as
-// its own update in a fixed order on the same stream (deterministic).  The
-// pieces of one update are independent tiles, so a launch covers the GPU when
-// the output alone is too small to.
+// bordered variants (K up to n, output only b rows): the K range is cut into
+// slices computed by one launch, their partial products are then added to C
+// in slice order (deterministic).
 template <typename T>
 int gemm_tallk(bool upper, int64_t M, int64_t N, int64_t K, const T *X, int64_t ldx, const T *Y, int64_t ldy, T *C,
                int64_t ldc, const int32_t *info, hipStream_t s) {
-    return gemm<T>(upper, M, N, K, X, ldx, Y, ldy, C, ldc, info, s);
+    DevCtx *ctx = ctx_for_current_device();
+    if (ctx == nullptr) return FLAME_ERR_HIP;
+    void *w = nullptr;
+    int rc = ctx_workspace(ctx, kWsSplit, splitk_workspace_bytes(), &w);
+    if (rc) return rc;
+    return launch_gemm_splitk<T>(upper, M, N, K, X, ldx, Y, ldy, C, ldc, static_cast<T *>(w), info, s);
 }
 
 // ---- right-looking (the paper's loop) ------------------------------------
@@ -210,10 +214,13 @@ int factor_bordered(int64_t n, T *A, int64_t lda, int nb, int32_t *info, hipStre
     if (rc) return rc;
     for (int64_t k = 0; k < n; k += nb) {
         const int64_t bk = std::min<int64_t>(nb, n - k);
-        // A01 := triu(A00)^{-T} A01: forward substitution over nb-row chunks of
-        // the k x k triangle (TRSM on the chunk, then GEMM on the rows below)
-        for (int64_t r0 = 0; r0 < k; r0 += nb) {
-            const int64_t w = std::min<int64_t>(nb, k - r0);
+        // A01 := triu(A00)^{-T} A01: forward substitution over 256-row chunks
+        // of the k x k triangle (TRSM on the chunk, then GEMM on the rows
+        // below); the chunk is independent of nb, so the chain of dependent
+        // launches is k / 256 long whatever the block size
+        constexpr int64_t kChunk = 256;
+        for (int64_t r0 = 0; r0 < k; r0 += kChunk) {
+            const int64_t w = std::min<int64_t>(kChunk, k - r0);
             rc = launch_trsm_panel<T>((int)w, bk, V.at(r0, r0), lda, V.at(r0, k), lda, info, s);
             if (rc) return rc;
             const int64_t below = k - r0 - w;
@@ -275,6 +282,12 @@ int factor_dispatch(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_
         }
     }
     // Allocate the workspace before capture (no allocation inside a capture).
+    if (o.variant == FLAME_VAR_LEFT || o.variant == FLAME_VAR_BORDERED) {
+        DevCtx *ctx = ctx_for_current_device();
+        void *w = nullptr;
+        int rc = ctx_workspace(ctx, kWsSplit, splitk_workspace_bytes(), &w);
+        if (rc) return rc;
+    }
     if (o.trail != FLAME_TRAIL_NATIVE) {
         DevCtx *ctx = ctx_for_current_device();
         void *w = nullptr;

@@ -72,6 +72,14 @@ int launch_gemm_tn(Prec p, bool c_is_double, bool upper, int64_t M, int64_t N, i
                    hipStream_t s);
 
 // Y (rows x cols, ldy) := round(X) to float / bf16, column by column.
+// C -= X^T Y with the K range split over slices that run as one launch,
+// each writing its partial product to W, then added to C in slice order
+// (deterministic).  Falls back to launch_gemm_tn when a split does not pay
+// or the operands are not 16-byte aligned.  W: splitk_workspace_bytes().
+template <typename CT>
+int launch_gemm_splitk(bool upper, int64_t M, int64_t N, int64_t K, const CT *X, int64_t ldx, const CT *Y,
+                       int64_t ldy, CT *C, int64_t ldc, CT *W, const int32_t *info, hipStream_t s);
+size_t splitk_workspace_bytes();
 int launch_round_panel(Prec p, int64_t rows, int64_t cols, const double *X, int64_t ldx, void *Y, int64_t ldy,
                        const int32_t *info, hipStream_t s);
 
@@ -125,9 +133,13 @@ struct DevCtx;
 DevCtx *ctx_for_current_device();
 // Workspace slot `slot` (factor panel, solve, batched, selector) of
 // at least `bytes` (grown under a lock, kept until the process ends).
-enum { kWsFactor = 0, kWsSolve = 1, kWsBatched = 2, kWsSelector = 3, kWsSlots = 4 };
+enum { kWsFactor = 0, kWsSolve = 1, kWsBatched = 2, kWsSelector = 3, kWsTune = 4, kWsSplit = 5, kWsSlots = 6 };
 int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out);
 hipStream_t ctx_side_stream(DevCtx *c);
+hipStream_t ctx_aux_stream(DevCtx *c);
+// Variant and block size for FLAME_VAR_AUTO: the learned selector when its
+// weights are loaded, else the autotuner's table, else (RIGHT, 256).
+void choose_variant(int32_t dtype, int64_t n, int64_t batch, int32_t *variant, int32_t *nb);
 hipEvent_t ctx_event(DevCtx *c, int i);
 
 // Loop drivers (driver.cpp).

@@ -73,6 +73,13 @@ struct GemmP {
     int tm, tn;
     int64_t ntiles;
     int upper;
+    // split-K (k_gemm_lds only): nslices > 1 runs ntiles * nslices workgroups;
+    // slice s covers k in [s kslice, min(K, (s + 1) kslice)) and writes
+    // -X_s^T Y_s to W + s ldw N (nothing is read from C)
+    int nslices;
+    int64_t kslice;
+    void *W;
+    int64_t ldw;
 };
 
 // One 32-byte fragment of a K x ncols operand: column `col` (already clamped
@@ -373,7 +380,15 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
     __shared__ __attribute__((aligned(16))) char lds[2][2][kSlabBytes];  // [buffer][X or Y]
 
     if (p.info != nullptr && *p.info != 0) return;
-    const int64_t t = xcd_remap((int64_t)blockIdx.x, p.ntiles);
+    int64_t bid = blockIdx.x;
+    int64_t kbeg = 0;
+    const bool split = p.nslices > 1;
+    if (split) {
+        const int64_t slice = bid / p.ntiles;
+        bid -= slice * p.ntiles;
+        kbeg = slice * p.kslice;
+    }
+    const int64_t t = xcd_remap(bid, p.ntiles);
     int I, J;
     tile_of(t, p.tm, p.tn, p.upper != 0, I, J);
     const int tid = threadIdx.x;
@@ -384,10 +399,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
     const int64_t tr0 = (int64_t)I * kTile, tc0 = (int64_t)J * kTile;
     const int64_t row0 = tr0 + (wave >> 1) * 64;
     const int64_t col0 = tc0 + (wave & 1) * 64;
-    const int64_t M = p.M, N = p.N, K = p.K, ldc = p.ldc;
+    const int64_t M = p.M, N = p.N;
+    const int64_t K = split ? min(p.kslice, p.K - kbeg) : p.K;
+    const int64_t ldc = split ? p.ldw : p.ldc;
     const bool active = (row0 < M) && (col0 < N) && !(p.upper && row0 > col0 + 63);
-    const char *__restrict__ Xb = static_cast<const char *>(p.X);
-    const char *__restrict__ Yb = static_cast<const char *>(p.Y);
+    const char *__restrict__ Xb = static_cast<const char *>(p.X) + kbeg * (int64_t)sizeof(in_t);
+    const char *__restrict__ Yb = static_cast<const char *>(p.Y) + kbeg * (int64_t)sizeof(in_t);
     const int64_t ldxb = p.ldx * (int64_t)sizeof(in_t), ldyb = p.ldy * (int64_t)sizeof(in_t);
 
     // copy assignment: thread tid moves units q = tid + 256 j (j < 8) of the
@@ -414,7 +431,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
     // CINIT: the accumulator starts from the C tile (same precision) and X is
     // negated; otherwise it starts at zero and C - X^T Y is formed at the end.
     constexpr bool CINIT = (P == Prec::F64 && sizeof(CT) == 8) || (P == Prec::F32 && sizeof(CT) == 4);
-    CT *__restrict__ C = static_cast<CT *>(p.C);
+    CT *__restrict__ C = split ? static_cast<CT *>(p.W) + (kbeg / p.kslice) * p.ldw * N : static_cast<CT *>(p.C);
     acc_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -422,7 +439,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
         for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                acc[a][b][v] = CINIT ? C[min(FLAME_CROW(a, v), M - 1) + min(FLAME_CCOL(b, v), N - 1) * ldc] : 0;
+                acc[a][b][v] =
+                    (CINIT && !split) ? C[min(FLAME_CROW(a, v), M - 1) + min(FLAME_CCOL(b, v), N - 1) * ldc] : 0;
 
     const int xr = (wave >> 1) * 64 + r, yr = (wave & 1) * 64 + r;
     u32x4 stx[4], sty[4];
@@ -748,6 +766,10 @@ int launch_gemm_tn(Prec prec, bool c_is_double, bool upper, int64_t M, int64_t N
     p.tn = (int)((N + kTile - 1) / kTile);
     p.upper = upper ? 1 : 0;
     p.ntiles = tile_count(p.tm, p.tn, upper);
+    p.nslices = 1;
+    p.kslice = K;
+    p.W = nullptr;
+    p.ldw = 0;
     if (p.ntiles <= 0) return FLAME_OK;
     const size_t esz = prec == Prec::F64 ? 8 : (prec == Prec::F32 ? 4 : 2);
     const int64_t vec_elems = 16 / (int64_t)esz;
@@ -764,6 +786,80 @@ int launch_gemm_tn(Prec prec, bool c_is_double, bool upper, int64_t M, int64_t N
     }
     return FLAME_ERR_UNSUPPORTED;
 }
+
+// ---- split-K for the tall-K products of the left-looking and bordered loops --
+template <typename CT>
+__global__ void k_splitk_reduce(int64_t M, int64_t N, int upper, const CT *__restrict__ W, int64_t ldw, int S,
+                                CT *__restrict__ C, int64_t ldc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = blockIdx.y;
+    if (i >= M || (upper && i > j)) return;
+    CT acc = C[i + j * ldc];
+    for (int s = 0; s < S; ++s) acc += W[i + j * ldw + (int64_t)s * ldw * N];  // fixed order
+    C[i + j * ldc] = acc;
+}
+
+int splitk_slices(bool upper, int64_t M, int64_t N, int64_t K, int64_t *kslice) {
+    constexpr int64_t kTargetWgs = 1024, kMinSliceK = 256;
+    const int tm = (int)((M + kTile - 1) / kTile), tn = (int)((N + kTile - 1) / kTile);
+    const int64_t tiles = tile_count(tm, tn, upper);
+    if (tiles <= 0) return 1;
+    int64_t S = std::min((kTargetWgs + tiles - 1) / tiles, K / kMinSliceK);
+    if (S <= 1) return 1;
+    const int64_t step = 32;  // a multiple of the k chunk of every precision
+    int64_t ks = ((K + S - 1) / S + step - 1) / step * step;
+    S = (K + ks - 1) / ks;
+    *kslice = ks;
+    return (int)S;
+}
+
+size_t splitk_workspace_bytes() { return (size_t)2048 * kTile * kTile * sizeof(double); }
+
+template <typename CT>
+int launch_gemm_splitk(bool upper, int64_t M, int64_t N, int64_t K, const CT *X, int64_t ldx, const CT *Y,
+                       int64_t ldy, CT *C, int64_t ldc, CT *W, const int32_t *info, hipStream_t s) {
+    constexpr Prec P = sizeof(CT) == 8 ? Prec::F64 : Prec::F32;
+    int64_t ks = K;
+    const int S = splitk_slices(upper, M, N, K, &ks);
+    const bool vec = aligned16(X) && aligned16(Y) && (ldx % (16 / (int64_t)sizeof(CT)) == 0) &&
+                     (ldy % (16 / (int64_t)sizeof(CT)) == 0) && (K % 32 == 0);
+    if (S <= 1 || !vec || (size_t)S * M * N * sizeof(CT) > splitk_workspace_bytes())
+        return launch_gemm_tn(P, sizeof(CT) == 8, upper, M, N, K, X, ldx, Y, ldy, C, ldc, info, s);
+    GemmP p;
+    p.M = M;
+    p.N = N;
+    p.K = K;
+    p.X = X;
+    p.ldx = ldx;
+    p.Y = Y;
+    p.ldy = ldy;
+    p.C = C;
+    p.ldc = ldc;
+    p.info = info;
+    p.tm = (int)((M + kTile - 1) / kTile);
+    p.tn = (int)((N + kTile - 1) / kTile);
+    p.upper = upper ? 1 : 0;
+    p.ntiles = tile_count(p.tm, p.tn, upper);
+    p.nslices = S;
+    p.kslice = ks;
+    p.W = W;
+    p.ldw = M;
+    const double dM = (double)M, dN = (double)N, dK = (double)K;
+    const double elems = upper ? (M <= N ? dM * (dM + 1) / 2 + (dN - dM) * dM : dN * (dN + 1) / 2) : dM * dN;
+    const int tr = trace_begin(FLAME_KC_GEMM, s);
+    hipLaunchKernelGGL((k_gemm_lds<P, CT>), dim3((unsigned)(p.ntiles * S)), dim3(256), 0, s, p);
+    FLAME_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_splitk_reduce<CT>, dim3((unsigned)((M + 255) / 256), (unsigned)N), dim3(256), 0, s, M, N,
+                       p.upper, W, M, S, C, ldc);
+    FLAME_CHECK_LAUNCH();
+    trace_end(tr, s, 2.0 * dK * elems, dK * (dM + dN) * sizeof(CT) + (2.0 + S) * elems * sizeof(CT));
+    return FLAME_OK;
+}
+
+template int launch_gemm_splitk<double>(bool, int64_t, int64_t, int64_t, const double *, int64_t, const double *,
+                                        int64_t, double *, int64_t, double *, const int32_t *, hipStream_t);
+template int launch_gemm_splitk<float>(bool, int64_t, int64_t, int64_t, const float *, int64_t, const float *,
+                                       int64_t, float *, int64_t, float *, const int32_t *, hipStream_t);
 
 // ---- low-precision copy of the panel ------------------------------------
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {

@@ -277,6 +277,31 @@ def test_factor_graph_replays():
             assert _rel_max(Ug, Uo) <= TOL_PAR64
 
 
+_ORACLE_CACHE = {}
+
+
+def _oracle_factor(n, seed):
+    if (n, seed) not in _ORACLE_CACHE:
+        A = inputs.spd_bbt(n, seed)
+        _ORACLE_CACHE[(n, seed)] = (A, oracle.potrf(A, threads=8)[0])
+    return _ORACLE_CACHE[(n, seed)]
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("nb", [64, 256])
+def test_tall_k_products_split(variant, nb):
+    """n = 2600: the left-looking and bordered loops' products with K up to
+    ~2500 are split over K slices (partials added in slice order)."""
+    n = 2600
+    A, Uo = _oracle_factor(n, 12)
+    Ad = to_dev(A, ld=n + 8)
+    info = fl.factor(Ad, variant=variant, nb=nb)
+    assert int(info.item()) == 0
+    Ug = to_host(Ad)
+    assert _rel_max(Ug, Uo) <= TOL_PAR64
+    assert oracle.factor_backward_error(A, Ug) <= TOL_BETA64
+
+
 # ---- solve and refinement ------------------------------------------------------
 
 # n spans single and multiple 128-row blocks with ragged tails; nrhs <= 8

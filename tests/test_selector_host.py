@@ -1,0 +1,83 @@
+"""Selector MLP (host side): parameter layout, the numpy forward pass against
+a plain loop, the loss gradient against finite differences, and training on
+a table with a known answer."""
+import math
+
+import numpy as np
+
+import paper_1601_05871_amd as fl
+from paper_1601_05871_amd import selector as sel
+
+
+def test_param_layout_matches_header():
+    assert sel.NPARAM == fl.SEL_NPARAM
+    with open(__file__.replace("tests/test_selector_host.py", "include/flame.h")) as f:
+        text = f.read()
+    assert "#define FLAME_SEL_NPARAM (64 * 5 + 64 + 64 * 64 + 64 + 12 * 64 + 12)" in text
+    p = sel.init_params(3)
+    w = sel.flatten(p)
+    assert w.dtype == np.float32 and w.size == sel.NPARAM
+    q = sel.unflatten(w)
+    for k in p:
+        assert np.allclose(q[k], p[k].astype(np.float32))
+    # W1 row-major first: w[j * 5 + k] = W1[j][k]
+    assert w[7] == np.float32(p["W1"][1][2])
+
+
+def test_class_mapping():
+    assert [sel.class_choice(c) for c in (0, 3, 4, 11)] == [(1, 32), (1, 256), (2, 32), (3, 256)]
+
+
+def test_forward_matches_plain_loops():
+    p = sel.init_params(5)
+    g = np.random.Generator(np.random.PCG64(0))
+    X = g.uniform(0, 10, size=(4, 5))
+    z, _ = sel.forward(p, X)
+    for r in range(4):
+        h1 = [max(0.0, p["b1"][j] + sum(p["W1"][j][k] * X[r][k] for k in range(5))) for j in range(64)]
+        h2 = [max(0.0, p["b2"][j] + sum(p["W2"][j][k] * h1[k] for k in range(64))) for j in range(64)]
+        out = [p["b3"][j] + sum(p["W3"][j][k] * h2[k] for k in range(64)) for j in range(12)]
+        assert np.allclose(z[r], out, rtol=1e-12, atol=1e-12)
+
+
+def test_gradient_matches_finite_differences():
+    p = sel.init_params(1)
+    g = np.random.Generator(np.random.PCG64(1))
+    X = g.uniform(0, 4, size=(6, 5))
+    S = 1.0 + g.uniform(0, 2, size=(6, 12))
+    S[np.arange(6), g.integers(0, 12, 6)] = 1.0
+    _, grad = sel.loss_and_grad(p, X, S)
+    h = 1e-6
+    for k, idx in (("W1", (3, 2)), ("b2", (7,)), ("W3", (5, 11)), ("W2", (10, 40))):
+        p2 = {kk: v.copy() for kk, v in p.items()}
+        p2[k][idx] += h
+        lp, _ = sel.loss_and_grad(p2, X, S)
+        p2[k][idx] -= 2 * h
+        lm, _ = sel.loss_and_grad(p2, X, S)
+        assert abs((lp - lm) / (2 * h) - grad[k][idx]) <= 1e-6 + 1e-4 * abs(grad[k][idx]), k
+
+
+def test_training_learns_a_known_rule():
+    """Times where the fastest class is a step function of log2 n and dtype:
+    the trained model picks it on held-out orders."""
+    def times(n, f64):
+        t = np.full(12, 2.0)
+        t[11 if n >= 2048 else (5 if f64 else 6)] = 1.0
+        return list(t)
+
+    recs = [{"n": n, "dtype": d, "times_ms": times(n, d == "f64")}
+            for n in sel.sample_orders(30, 0) for d in ("f64", "f32")]
+    X, S = sel.expand(recs, reps_per_record=8)
+    p, hist = sel.train(X, S, epochs=3000)
+    assert hist[-1][1] < hist[0][1]
+    held = [{"n": n, "dtype": d, "times_ms": times(n, d == "f64")}
+            for n in (100, 500, 1000, 5000, 20000) for d in ("f64", "f32")]
+    res = sel.regret_table(p, held)
+    assert res["mean_regret"] == 0.0, res
+
+
+def test_features():
+    f = sel.features(1024, 1, True, 0.0)
+    assert f.tolist() == [10.0, 0.0, 1.0, 0.0, 0.0]
+    f = sel.features(64, 10000, False, 1e4)
+    assert math.isclose(f[1], math.log2(10000), rel_tol=1e-6) and f[3] == 1.0 and math.isclose(f[4], 4.0)
