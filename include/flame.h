@@ -84,7 +84,7 @@ typedef struct {
     int32_t graph;     /* 0 = default (off), 1 = capture the loop once per
                           (n, lda, A, info, options, stream) in a HIP graph and
                           replay it on later calls with the same key */
-    int32_t reserved[3];
+    int32_t reserved[3]; /* must be 0 */
 } flame_opts_t;
 
 /* ---- factorization ------------------------------------------------------ */

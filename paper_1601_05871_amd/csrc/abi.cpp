@@ -24,6 +24,7 @@ int normalize_opts(const flame_opts_t *in, int32_t dtype, int64_t n, flame_opts_
     if (o->trail < FLAME_TRAIL_NATIVE || o->trail > FLAME_TRAIL_BF16) return -5;
     if (o->lookahead < -1 || o->lookahead > 2) return -5;
     if (o->graph < 0 || o->graph > 1) return -5;
+    if (o->reserved[0] != 0 || o->reserved[1] != 0 || o->reserved[2] != 0) return -5;
     if (o->variant == FLAME_VAR_AUTO) {
         int32_t v = FLAME_VAR_RIGHT, nb = 0;
         choose_variant(dtype, n, 1, &v, &nb);

@@ -433,14 +433,23 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
     constexpr bool CINIT = (P == Prec::F64 && sizeof(CT) == 8) || (P == Prec::F32 && sizeof(CT) == 4);
     CT *__restrict__ C = split ? static_cast<CT *>(p.W) + (kbeg / p.kslice) * p.ldw * N : static_cast<CT *>(p.C);
     acc_t acc[4][4];
+    // one uniform branch around the whole (unconditional, clamped) tile load
+    if (CINIT && !split) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+            for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                acc[a][b][v] =
-                    (CINIT && !split) ? C[min(FLAME_CROW(a, v), M - 1) + min(FLAME_CCOL(b, v), N - 1) * ldc] : 0;
+                for (int v = 0; v < 4; ++v)
+                    acc[a][b][v] = C[min(FLAME_CROW(a, v), M - 1) + min(FLAME_CCOL(b, v), N - 1) * ldc];
+    } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[a][b][v] = 0;
+    }
 
     const int xr = (wave >> 1) * 64 + r, yr = (wave & 1) * 64 + r;
     u32x4 stx[4], sty[4];

@@ -58,9 +58,15 @@ def test_factor_argument_errors(args, expect):
 
 
 @pytest.mark.parametrize("field,value", [("variant", 9), ("nb", 257), ("nb", -1), ("trail", 3),
-                                         ("lookahead", 3), ("graph", 5)])
+                                         ("lookahead", 3), ("graph", 5), ])
 def test_factor_bad_options(field, value):
     o = _opts(**{field: value})
+    assert fl.lib().flame_factor(0, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == -5
+
+
+def test_factor_reserved_fields_must_be_zero():
+    o = _opts()
+    o.reserved[1] = 1
     assert fl.lib().flame_factor(0, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == -5
 
 
@@ -104,6 +110,9 @@ def test_batched_and_selector_argument_errors():
     assert L.flame_selector_load(FAKE, 3) == -2
     v, nb = ctypes.c_int32(), ctypes.c_int32()
     assert L.flame_select(-1, 1, 0, 1.0, ctypes.byref(v), ctypes.byref(nb)) == -1
+    o = _opts(variant=2)
+    assert L.flame_batched_factor(0, 1, FAKE, FAKE, FAKE, FAKE, ctypes.byref(o), None) == -7
+    assert L.flame_autotune(0, 4, FAKE, 4, 0, FAKE, None) == -5
 
 
 TILE_PROBE = r'''
