@@ -158,6 +158,7 @@ def main() -> int:
         "launches_per_step": g["launches"] / K,
         "avg_launch_ms": g["ms"] / max(1, g["launches"]),
         "avg_launch_gflop": g["flops"] / max(1, g["launches"]) / 1e9,
+        "avg_launch_alg_bytes": g["bytes"] / max(1, g["launches"]),
         "measured_in": "instrumented pass of the same K steps (per-launch HIP events)",
         "instrumented_ms_per_step": None if traced_ms is None else round(traced_ms, 4),
     }

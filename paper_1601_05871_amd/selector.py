@@ -179,8 +179,14 @@ def regret_table(p: dict, records) -> dict:
         rows.append({"n": r["n"], "dtype": r["dtype"], "chosen": class_choice(c), "best": class_choice(int(np.argmin(s))),
                      "regret": float(s[c] - 1.0)})
     reg = np.array([x["regret"] for x in rows])
-    return {"mean_regret": float(reg.mean()), "max_regret": float(reg.max()),
-            "exact_best_fraction": float(np.mean(reg == 0.0)), "rows": rows}
+    # baseline: the single (variant, nb) with the lowest mean regret on these shapes
+    S = np.array([normalized(r["times_ms"]) for r in records]) - 1.0
+    fixed = int(np.argmin(S.mean(axis=0)))
+    return {"mean_regret": float(reg.mean()), "median_regret": float(np.median(reg)),
+            "p95_regret": float(np.percentile(reg, 95)), "max_regret": float(reg.max()),
+            "exact_best_fraction": float(np.mean(reg == 0.0)),
+            "best_fixed_choice": class_choice(fixed), "best_fixed_mean_regret": float(S[:, fixed].mean()),
+            "best_fixed_max_regret": float(S[:, fixed].max()), "rows": rows}
 
 
 # ---- commands ---------------------------------------------------------------------
@@ -272,7 +278,8 @@ def cmd_eval(args) -> int:
         with open(args.out, "w") as f:
             f.write(text)
     print(f"held-out: {len(recs)} shapes, mean regret {res['mean_regret']:.4f}, max {res['max_regret']:.4f}, "
-          f"best chosen {res['exact_best_fraction']:.2f}" + (f", device agrees {res['device_agrees']}"
+          f"best chosen {res['exact_best_fraction']:.2f}; best fixed {tuple(res['best_fixed_choice'])}: mean "
+          f"{res['best_fixed_mean_regret']:.4f}, max {res['best_fixed_max_regret']:.4f}" + (f", device agrees {res['device_agrees']}"
                                                              if args.device else ""))
     return 0
 
