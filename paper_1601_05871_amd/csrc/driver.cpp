@@ -34,9 +34,17 @@ constexpr Prec native_prec() {
 
 template <typename T>
 int gemm(bool upper, int64_t M, int64_t N, int64_t K, const T *X, int64_t ldx, const T *Y, int64_t ldy, T *C,
-         int64_t ldc, const int32_t *info, hipStream_t s) {
-    return launch_gemm_tn(native_prec<T>(), sizeof(T) == 8, upper, M, N, K, X, ldx, Y, ldy, C, ldc, info, s);
+         int64_t ldc, const int32_t *info, hipStream_t s, int reserve_cus = 0) {
+    return launch_gemm_tn(native_prec<T>(), sizeof(T) == 8, upper, M, N, K, X, ldx, Y, ldy, C, ldc, info, s,
+                          reserve_cus);
 }
+
+// Compute units the remainder of the trailing update leaves to the next
+// diagonal block's CHOL and TRSM when the two run concurrently (lookahead 2).
+#ifndef FLAME_CHAIN_CUS
+#define FLAME_CHAIN_CUS 16
+#endif
+constexpr int kChainCus = FLAME_CHAIN_CUS;
 
 // Split-K form of C -= X^T Y for the tall-K products of the left-looking and
 // bordered variants (K up to n, output only b rows): the K range is cut into
@@ -75,16 +83,17 @@ int factor_right(int64_t n, T *A, int64_t lda, int nb, int lookahead, flame_trai
     auto wcol = [&](int64_t j) { return static_cast<char *>(W) + (size_t)j * (size_t)ldw * wesz; };
 
     // trailing update of C (Mr x Nc, at A22 offset (i0, i0)..) from panel columns
-    auto update = [&](int64_t k, int64_t bk, int64_t i0, int64_t Mr, int64_t j0, int64_t Nc, hipStream_t st) -> int {
+    auto update = [&](int64_t k, int64_t bk, int64_t i0, int64_t Mr, int64_t j0, int64_t Nc, hipStream_t st,
+                      int reserve = 0) -> int {
         // C = A22(i0 : i0+Mr, j0 : j0+Nc) with A22 at (k+bk, k+bk); X = A12(:, i0..), Y = A12(:, j0..)
         const int64_t base = k + bk;
         T *C = V.at(base + i0, base + j0);
         if (!mixed) {
             const T *X = V.at(k, base + i0);
             const T *Y = V.at(k, base + j0);
-            return gemm<T>(true, Mr, Nc, bk, X, lda, Y, lda, C, lda, info, st);
+            return gemm<T>(true, Mr, Nc, bk, X, lda, Y, lda, C, lda, info, st, reserve);
         }
-        return launch_gemm_tn(lp, true, true, Mr, Nc, ldw, wcol(i0), ldw, wcol(j0), ldw, C, lda, info, st);
+        return launch_gemm_tn(lp, true, true, Mr, Nc, ldw, wcol(i0), ldw, wcol(j0), ldw, C, lda, info, st, reserve);
     };
 
     rc = launch_zero_i32(info, 1, s);
@@ -166,7 +175,7 @@ int factor_right(int64_t n, T *A, int64_t lda, int nb, int lookahead, flame_trai
             // ahead of the remainder's workgroups
             FLAME_HIP(hipEventRecord(ev_panel, s));
             FLAME_HIP(hipStreamWaitEvent(side, ev_panel, 0));
-            rc = update(k, bk, bk2, m2, bk2, m2, side);
+            rc = update(k, bk, bk2, m2, bk2, m2, side, kChainCus);
             if (rc) return rc;
             FLAME_HIP(hipEventRecord(ev_ready, side));
             rc = launch_chol_block<T>((int)bk2, V.at(k2, k2), lda, info, k2, s);

@@ -67,9 +67,11 @@ enum class Prec { F64, F32, BF16 };
 //   F32:  X, Y float;  C float (cfloat) or double (!cfloat)
 //   BF16: X, Y bf16 (uint16 storage); C double
 // Skips if info && *info.
+// reserve_cus > 0: leave that many compute units free of this launch (for
+// kernels running concurrently on another stream).
 int launch_gemm_tn(Prec p, bool c_is_double, bool upper, int64_t M, int64_t N, int64_t K, const void *X,
                    int64_t ldx, const void *Y, int64_t ldy, void *C, int64_t ldc, const int32_t *info,
-                   hipStream_t s);
+                   hipStream_t s, int reserve_cus = 0);
 
 // Y (rows x cols, ldy) := round(X) to float / bf16, column by column.
 // C -= X^T Y with the K range split over slices that run as one launch,

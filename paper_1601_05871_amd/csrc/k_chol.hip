@@ -21,19 +21,23 @@
 namespace flame {
 
 // LDS-resident form for n <= 128: the upper triangle is loaded into LDS once
-// (column-major, leading dimension 129), padded with the identity to a
+// (packed column by column: 66 KB in FP64, so that the kernel fits on a CU
+// beside one workgroup of the trailing update), padded with the identity to a
 // multiple of the sub-block order S (so every sub-block is full and the
 // unrolled register code needs no bounds guards), steps (a)-(c) run on LDS
 // only, and the factor is written back once.  The padding stays the identity:
 // its pivots are 1 and its coupling to the matrix is 0.
 constexpr int kLdsN = 128;
-constexpr int kLdsLd = kLdsN + 1;
+constexpr int kPacked = kLdsN * (kLdsN + 1) / 2;  // upper triangle, packed by columns
+
+// LDS position of element (i, c), i <= c, of the packed upper triangle
+__device__ __forceinline__ int pk(int i, int c) { return c * (c + 1) / 2 + i; }
 
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_chol_lds(int n, T *__restrict__ A, int64_t lda, int32_t *__restrict__ info,
                                                   int64_t info_base) {
     constexpr int RMAX = kLdsN - S;       // widest trailing block
-    __shared__ T L[kLdsN * kLdsLd];       // the block, column-major
+    __shared__ T L[kPacked];              // the block's upper triangle, packed columns
     __shared__ T Pt[S][RMAX + 4];         // the current panel rows, row-major
     __shared__ T rinv[S];                 // 1 / U(j, j) of the current sub-block
     __shared__ int s_bad;
@@ -58,51 +62,85 @@ __global__ __launch_bounds__(256) void k_chol_lds(int n, T *__restrict__ A, int6
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + 256 * e;
             const int col = idx >> 7, row = idx & (kLdsN - 1);
-            if (row < np && col < np)
-                L[col * kLdsLd + row] = (row < n && col < n) ? v[e] : (row == col ? T(1) : T(0));
+            if (row <= col && col < np)
+                L[pk(row, col)] = (row < n && col < n) ? v[e] : (row == col ? T(1) : T(0));
         }
     }
     __syncthreads();
 
-    for (int r0 = 0; r0 < np; r0 += S) {
-        const int rest = np - r0 - S;
-        // (a) diagonal sub-block in the registers of wavefront 0
-        if (wave == 0) {
-            T a[S];
-            const T *colp = L + (r0 + min(lane, S - 1)) * kLdsLd + r0;
+    // (a) of the first sub-block, then per sub-block: (b), and (c) with the
+    // next diagonal block's share updated first by wavefront 0, which goes on
+    // to factor it (the next (a)) while wavefronts 1-3 finish the update.
+    auto diag = [&](int r0) {
+        T a[S];
+        // column r0 + c from row r0 (the entries read past the column's
+        // diagonal belong to the next columns and are discarded)
+        const T *colp = L + pk(r0, r0 + min(lane, S - 1));
 #pragma unroll
-            for (int i = 0; i < S; ++i) {
-                const T v = colp[i];
-                a[i] = (i <= lane) ? v : T(0);
-            }
-            T ri;
-            const int bad = chol_wave_full<T, S>(a, lane, &ri);
-            if (lane == 0) s_bad = bad;
-            if (lane < S) {
-                T *colw = L + (r0 + lane) * kLdsLd + r0;
+        for (int i = 0; i < S; ++i) a[i] = colp[i];
+        T ri;
+        const int bad = chol_row16<T, S>(a, lane & 15, &ri);
+        if (lane == 0) s_bad = bad;
+        if (lane < S) {
+            T *colw = L + pk(r0, r0 + lane);
 #pragma unroll
-                for (int i = 0; i < S; ++i)
-                    if (i <= lane) colw[i] = a[i];
-                rinv[lane] = ri;
-            }
+            for (int i = 0; i < S; ++i)
+                if (i <= lane) colw[i] = a[i];
+            rinv[lane] = ri;
         }
-        __syncthreads();
-        if (s_bad != 0) {
+    };
+    // 4 x 4 tile idx (upper, column by column) of the trailing block at o
+    auto tile_update = [&](int o, int idx) {
+        int bj = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+        while (bj * (bj + 1) / 2 > idx) --bj;
+        while ((bj + 1) * (bj + 2) / 2 <= idx) ++bj;
+        const int bi = idx - bj * (bj + 1) / 2;
+        T acc[4][4];
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) acc[ii][jj] = T(0);
+#pragma unroll 4
+        for (int q = 0; q < S; ++q) {
+            T pi[4], pj[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                pi[e] = Pt[q][4 * bi + e];
+                pj[e] = Pt[q][4 * bj + e];
+            }
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) acc[ii][jj] += pi[ii] * pj[jj];
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii)
+                if (4 * bi + ii <= 4 * bj + jj) L[pk(o + 4 * bi + ii, o + 4 * bj + jj)] -= acc[ii][jj];
+    };
+    constexpr int kDiagTiles = (S / 4) * (S / 4 + 1) / 2;  // tiles of one S x S diagonal block
+
+    if (wave == 0) diag(0);
+    __syncthreads();
+    for (int r0 = 0;; r0 += S) {
+        if (__builtin_amdgcn_readfirstlane(s_bad) != 0) {  // uniform: a scalar branch
             if (tid == 0) *info = (int32_t)(info_base + r0 + s_bad);
             return;
         }
+        const int rest = np - r0 - S;
         if (rest == 0) break;
         // (b) row panel: thread t owns column r0 + S + t
         if (tid < rest) {
             T x[S];
-            T *colc = L + (r0 + S + tid) * kLdsLd + r0;
+            T *colc = L + pk(r0, r0 + S + tid);
 #pragma unroll
             for (int i = 0; i < S; ++i) x[i] = colc[i];
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 x[q] = x[q] * rinv[q];
 #pragma unroll
-                for (int t = q + 1; t < S; ++t) x[t] = x[t] - L[(r0 + t) * kLdsLd + r0 + q] * x[q];
+                for (int t = q + 1; t < S; ++t) x[t] = x[t] - L[pk(r0 + q, r0 + t)] * x[q];
             }
 #pragma unroll
             for (int i = 0; i < S; ++i) {
@@ -111,44 +149,22 @@ __global__ __launch_bounds__(256) void k_chol_lds(int n, T *__restrict__ A, int6
             }
         }
         __syncthreads();
-        // (c) trailing update, 4 x 4 per thread, from the row-major panel
+        // (c) trailing update of the block at o = r0 + S in 4 x 4 tiles
         const int o = r0 + S;
         const int nb4 = rest >> 2;
         const int cnt = nb4 * (nb4 + 1) / 2;
-        for (int idx = tid; idx < cnt; idx += 256) {
-            int bj = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
-            while (bj * (bj + 1) / 2 > idx) --bj;
-            while ((bj + 1) * (bj + 2) / 2 <= idx) ++bj;
-            const int bi = idx - bj * (bj + 1) / 2;
-            T acc[4][4];
-#pragma unroll
-            for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) acc[ii][jj] = T(0);
-#pragma unroll 4
-            for (int q = 0; q < S; ++q) {
-                T pi[4], pj[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    pi[e] = Pt[q][4 * bi + e];
-                    pj[e] = Pt[q][4 * bj + e];
-                }
-#pragma unroll
-                for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) acc[ii][jj] += pi[ii] * pj[jj];
-            }
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-                for (int ii = 0; ii < 4; ++ii)
-                    if (4 * bi + ii <= 4 * bj + jj) L[(o + 4 * bj + jj) * kLdsLd + o + 4 * bi + ii] -= acc[ii][jj];
+        if (wave == 0) {
+            if (lane < kDiagTiles) tile_update(o, lane);  // the next diagonal block
+            __threadfence_block();                        // its LDS writes before the reads below
+            diag(o);
+        } else {
+            for (int idx = kDiagTiles + tid - 64; idx < cnt; idx += 192) tile_update(o, idx);
         }
         __syncthreads();
     }
     // store the upper triangle
     for (int col = wave; col < n; col += 4)
-        for (int row = lane; row <= col; row += 64) A[(int64_t)row + (int64_t)col * lda] = L[col * kLdsLd + row];
+        for (int row = lane; row <= col; row += 64) A[(int64_t)row + (int64_t)col * lda] = L[pk(row, col)];
 }
 
 template <typename T>

@@ -80,6 +80,11 @@ struct GemmP {
     int64_t kslice;
     void *W;
     int64_t ldw;
+    // compute units to leave free for concurrent kernels (0 = none).  With a
+    // reservation k_gemm_lds launches 2 workgroups per remaining CU and each
+    // walks work items blockIdx.x, + gridDim.x, ... (tiles x slices);
+    // k_gemm_p8 launches one per remaining CU.
+    int reserve_cus;
 };
 
 // One 32-byte fragment of a K x ncols operand: column `col` (already clamped
@@ -380,9 +385,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
     __shared__ __attribute__((aligned(16))) char lds[2][2][kSlabBytes];  // [buffer][X or Y]
 
     if (p.info != nullptr && *p.info != 0) return;
-    int64_t bid = blockIdx.x;
-    int64_t kbeg = 0;
     const bool split = p.nslices > 1;
+    const int64_t items = p.ntiles * (split ? p.nslices : 1);
+    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    int64_t bid = item;
+    int64_t kbeg = 0;
     if (split) {
         const int64_t slice = bid / p.ntiles;
         bid -= slice * p.ntiles;
@@ -528,6 +535,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
 #undef FLAME_COMPUTE
 #undef FLAME_CROW
 #undef FLAME_CCOL
+    __syncthreads();  // the LDS buffers are refilled by the next item
+    }
 }
 
 // ---- 8-wavefront persistent LDS-staged variant --------------------------------
@@ -732,23 +741,38 @@ static int launch_t(const GemmP &p, bool vec, hipStream_t s) {
     // FP32 / BF16 products as one persistent 8-wavefront workgroup (k_gemm_p8)
     const bool lds8_ok = P != Prec::F64 && vec && p.K > 0 && (p.K % CK8) == 0;
     const bool lds_ok = vec && p.K > 0 && (p.K % CK) == 0;
-    const unsigned grid = (unsigned)p.ntiles;
     // algorithmic work: 2K flops per updated element; each operand element
     // read once (one panel when X and Y are the same), C read and written
     const double M = (double)p.M, N = (double)p.N, K = (double)p.K;
     const double elems = p.upper ? (M <= N ? M * (M + 1) / 2 + (N - M) * M : N * (N + 1) / 2) : M * N;
     const double esz = P == Prec::F64 ? 8.0 : (P == Prec::F32 ? 4.0 : 2.0);
     const double panel = (p.X == p.Y && p.M == p.N) ? K * M : K * (M + N);
+    int64_t cus_left = kPersistentWgs;
+    if (p.reserve_cus > 0) {
+        static int cus_cache[64] = {};
+        int dev = 0;
+        FLAME_HIP(hipGetDevice(&dev));
+        int cus = dev < 64 ? cus_cache[dev] : 0;
+        if (cus == 0) {
+            FLAME_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            if (dev < 64) cus_cache[dev] = cus;
+        }
+        // a multiple of the 8 XCDs, so that the persistent walk keeps each
+        // workgroup on its XCD's contiguous tiles
+        cus_left = std::max<int64_t>(8, (cus - p.reserve_cus) / 8 * 8);
+    }
     const int tr = trace_begin(FLAME_KC_GEMM, s);
     if (lds8_ok)
-        hipLaunchKernelGGL((k_gemm_p8<P, CT>), dim3((unsigned)std::min<int64_t>(p.ntiles, kPersistentWgs)), dim3(512), 0,
-                           s, p);
+        hipLaunchKernelGGL((k_gemm_p8<P, CT>), dim3((unsigned)std::min<int64_t>(p.ntiles, cus_left)), dim3(512), 0, s,
+                           p);
     else if (lds_ok)
-        hipLaunchKernelGGL((k_gemm_lds<P, CT>), dim3(grid), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((k_gemm_lds<P, CT>),
+                           dim3((unsigned)(p.reserve_cus > 0 ? std::min<int64_t>(p.ntiles, 2 * cus_left) : p.ntiles)),
+                           dim3(256), 0, s, p);
     else if (vec)
-        hipLaunchKernelGGL((k_gemm_tn<P, CT, true>), dim3(grid), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((k_gemm_tn<P, CT, true>), dim3((unsigned)p.ntiles), dim3(256), 0, s, p);
     else
-        hipLaunchKernelGGL((k_gemm_tn<P, CT, false>), dim3(grid), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((k_gemm_tn<P, CT, false>), dim3((unsigned)p.ntiles), dim3(256), 0, s, p);
     FLAME_CHECK_LAUNCH();
     trace_end(tr, s, 2.0 * K * elems, panel * esz + 2.0 * elems * (double)sizeof(CT));
     return FLAME_OK;
@@ -757,8 +781,8 @@ static int launch_t(const GemmP &p, bool vec, hipStream_t s) {
 static bool aligned16(const void *q) { return ((uintptr_t)q & 15u) == 0; }
 
 int launch_gemm_tn(Prec prec, bool c_is_double, bool upper, int64_t M, int64_t N, int64_t K, const void *X,
-                   int64_t ldx, const void *Y, int64_t ldy, void *C, int64_t ldc, const int32_t *info,
-                   hipStream_t s) {
+                   int64_t ldx, const void *Y, int64_t ldy, void *C, int64_t ldc, const int32_t *info, hipStream_t s,
+                   int reserve_cus) {
     if (M <= 0 || N <= 0) return FLAME_OK;
     GemmP p;
     p.M = M;
@@ -779,6 +803,7 @@ int launch_gemm_tn(Prec prec, bool c_is_double, bool upper, int64_t M, int64_t N
     p.kslice = K;
     p.W = nullptr;
     p.ldw = 0;
+    p.reserve_cus = reserve_cus;
     if (p.ntiles <= 0) return FLAME_OK;
     const size_t esz = prec == Prec::F64 ? 8 : (prec == Prec::F32 ? 4 : 2);
     const int64_t vec_elems = 16 / (int64_t)esz;
@@ -853,6 +878,7 @@ int launch_gemm_splitk(bool upper, int64_t M, int64_t N, int64_t K, const CT *X,
     p.kslice = ks;
     p.W = W;
     p.ldw = M;
+    p.reserve_cus = 0;
     const double dM = (double)M, dN = (double)N, dK = (double)K;
     const double elems = upper ? (M <= N ? dM * (dM + 1) / 2 + (dN - dM) * dM : dN * (dN + 1) / 2) : dM * dN;
     const int tr = trace_begin(FLAME_KC_GEMM, s);
