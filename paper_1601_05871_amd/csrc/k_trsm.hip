@@ -24,7 +24,7 @@ namespace flame {
 // passed in swapped order).
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
-constexpr int kTrsmNb = 8;  // row blocks of 16: b <= 128
+constexpr int kTrsmNb = 8;  // row blocks of 16 per kernel: b <= 128
 
 template <typename T>
 struct TrsmAcc;
@@ -55,7 +55,7 @@ __device__ __forceinline__ f4v mma_rc(float rowop, float colop, f4v acc) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(rowop, colop, acc, 0, 0, 0);
 }
 
-template <typename T>
+template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_trsm_rl(int b, int64_t m, const T *__restrict__ U, int64_t ldu,
                                                  T *__restrict__ X, int64_t ldx, const int32_t *__restrict__ info,
                                                  int64_t u_step, int64_t x_step) {
@@ -65,7 +65,6 @@ __global__ __launch_bounds__(256) void k_trsm_rl(int b, int64_t m, const T *__re
     // by u_step and x_step elements)
     U += (int64_t)blockIdx.y * u_step;
     X += (int64_t)blockIdx.y * x_step;
-    constexpr int NB = kTrsmNb;
     __shared__ T Ds[NB][16][17];  // inverses of the diagonal blocks, [block][k][col]
     __shared__ T Rt[4][16][17];   // per wavefront: one block, [row][col]
     if (info != nullptr && *info != 0) return;
@@ -78,8 +77,8 @@ __global__ __launch_bounds__(256) void k_trsm_rl(int b, int64_t m, const T *__re
     // (1) inverses of the 16 x 16 diagonal blocks (U read from global memory /
     // L2: no LDS copy, so that the kernel fits beside two trailing-update
     // workgroups on one CU)
-    if (tid < NB * 16) {
-        const int sb = tid >> 4, t = tid & 15;  // column t of D_sb: U_ss D(:, t) = e_t
+    for (int ct = tid; ct < NB * 16; ct += 256) {
+        const int sb = ct >> 4, t = ct & 15;  // column t of D_sb: U_ss D(:, t) = e_t
         T v[16];
 #pragma unroll
         for (int i = 15; i >= 0; --i) {
@@ -154,7 +153,9 @@ int launch_trsm_panel(int b, int64_t m, const T *U, int64_t ldu, T *X, int64_t l
     if (b <= 0 || m <= 0) return FLAME_OK;
     if (b > 16 * kTrsmNb) {
         // two row halves: X_top := U_tt^{-T} X_top; X_bot -= U_tb^T X_top;
-        // X_bot := U_bb^{-T} X_bot
+        // X_bot := U_bb^{-T} X_bot.  (One kernel over all sixteen row blocks
+        // needs ~300 registers per lane, which keeps it off the CUs the
+        // concurrent trailing update occupies; the split runs faster there.)
         const int b1 = 16 * kTrsmNb, b2 = b - b1;
         int rc = launch_trsm_panel<T>(b1, m, U, ldu, X, ldx, info, s);
         if (rc) return rc;
@@ -164,11 +165,8 @@ int launch_trsm_panel(int b, int64_t m, const T *U, int64_t ldu, T *X, int64_t l
         return launch_trsm_panel<T>(b2, m, U + b1 + (int64_t)b1 * ldu, ldu, X + b1, ldx, info, s);
     }
     const int tr = trace_begin(FLAME_KC_TRSM, s);
-    {
-        const int64_t blocks = (m + 63) / 64;
-        hipLaunchKernelGGL(k_trsm_rl<T>, dim3((unsigned)blocks), dim3(256), 0, s, b, m, U, ldu, X, ldx, info, (int64_t)0,
-                           (int64_t)0);
-    }
+    hipLaunchKernelGGL((k_trsm_rl<T, kTrsmNb>), dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, b, m, U, ldu, X,
+                       ldx, info, (int64_t)0, (int64_t)0);
     FLAME_CHECK_LAUNCH();
     const double db = (double)b, dm = (double)m;
     trace_end(tr, s, db * db * dm, (db * (db + 1) / 2 + 2 * db * dm) * (double)sizeof(T));
@@ -182,14 +180,14 @@ int launch_diag_inverse_t(int64_t n, int bs, const double *U, int64_t ldu, doubl
     const int64_t nblk = (n + bs - 1) / bs;
     const int64_t full = n / bs;  // blocks of order bs
     if (full > 0) {
-        hipLaunchKernelGGL(k_trsm_rl<double>, dim3((unsigned)((bs + 63) / 64), (unsigned)full), dim3(256), 0, s, bs, (int64_t)bs,
+        hipLaunchKernelGGL((k_trsm_rl<double, kTrsmNb>), dim3((unsigned)((bs + 63) / 64), (unsigned)full), dim3(256), 0, s, bs, (int64_t)bs,
                            U, ldu, Dt, (int64_t)bs, nullptr, (int64_t)bs * (ldu + 1), (int64_t)bs * bs);
         FLAME_CHECK_LAUNCH();
     }
     if (nblk > full) {
         const int64_t o = full * bs;
         const int last = (int)(n - o);
-        hipLaunchKernelGGL(k_trsm_rl<double>, dim3((unsigned)((last + 63) / 64), 1u), dim3(256), 0, s, last, (int64_t)last,
+        hipLaunchKernelGGL((k_trsm_rl<double, kTrsmNb>), dim3((unsigned)((last + 63) / 64), 1u), dim3(256), 0, s, last, (int64_t)last,
                            U + o + o * ldu, ldu, Dt + full * (int64_t)bs * bs, (int64_t)bs, nullptr, (int64_t)0,
                            (int64_t)0);
         FLAME_CHECK_LAUNCH();
