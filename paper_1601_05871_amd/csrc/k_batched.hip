@@ -8,21 +8,23 @@
 // small ones fill the tail (longest-processing-time-first scheduling).
 //
 // One workgroup (4 wavefronts) factors one matrix with the right-looking loop
-// of Fig. "dense-chol" at block size kBB = 32, on the matrix in HBM / L2:
-//   CHOL  wavefront 0 factors the 32 x 32 diagonal block in registers (one
-//         column per lane, the unblocked loop); U11 and 1 / diag go to LDS;
-//   TRSM  one thread per column of the row panel, forward substitution with
-//         U11^T from LDS;
+// of Fig. "dense-chol" at block size kBB = 64, on the matrix in HBM / L2:
+//   CHOL  the 64 x 64 diagonal block in LDS (packed), factored in 16-column
+//         sub-blocks (chol_lds.h), written back;
+//   TRSM  the 64-row panel on matrix cores, 16 columns per wavefront
+//         (trsm_rl.h);
 //   SYRK  the upper 32 x 32 tiles of A22 are spread over the wavefronts; each
 //         tile is a 2 x 2 set of 16 x 16 matrix-core products (FP64 or FP32
-//         MFMA, K = 32) accumulated onto the tile of A22.
+//         MFMA, K = 64) accumulated onto the tile of A22.
 // A breakdown stops that matrix only (info[i] = first bad column, 1-based).
-#include "chol_wave.h"
+#include "chol_lds.h"
 #include "flame_internal.h"
+#include "trsm_rl.h"
 
 namespace flame {
 
-constexpr int kBB = 32;            // block size inside a workgroup
+constexpr int kBB = 64;            // block size inside a workgroup
+constexpr int kSub = 16;           // sub-block of the diagonal factorization
 constexpr int kBatchMaxN = 1024;   // largest order accepted
 constexpr int kBuckets = kBatchMaxN + 2;  // orders 0..1024, plus one for invalid entries
 
@@ -124,65 +126,47 @@ __device__ void syrk_tiles(int m, const T *__restrict__ P, int64_t ldp, T *__res
     }
 }
 
+// Workgroup-shared scratch of factor_one.
+template <typename T>
+struct BatchLds {
+    T L[packed_size<kBB>()];   // diagonal block, packed upper triangle
+    T Pt[kSub][kBB - kSub + 4];  // its sub-block panel rows
+    T rinv[kSub];
+    T Ds[kBB / 16][16][17];    // inverses of the 16 x 16 diagonal blocks of U11
+    T Rt[4][16][17];           // per wavefront TRSM scratch
+    int s_bad;
+};
+
 // Factors one matrix with the whole workgroup; returns the info value.
 template <typename T>
-__device__ int factor_one(int n, T *__restrict__ A, int64_t lda, T (*Us)[kBB + 1], T *rinv, int *s_bad) {
+__device__ int factor_one(int n, T *__restrict__ A, int64_t lda, BatchLds<T> &sh) {
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     for (int k0 = 0; k0 < n; k0 += kBB) {
         const int bk = min(kBB, n - k0);
         const int m = n - k0 - bk;
-        // CHOL: wavefront 0, lane c holds column c of the block (identity
-        // past bk, so the unrolled code needs no guards)
-        if (wave == 0) {
-            T a[kBB];
-            const int c = min(lane, kBB - 1);
-            const T *col = A + k0 + (int64_t)(k0 + min(c, bk - 1)) * lda;
-#pragma unroll
-            for (int i = 0; i < kBB; ++i) {
-                const T v = col[min(i, bk - 1)];
-                a[i] = (c < bk) ? ((i <= c) ? v : T(0)) : (i == c ? T(1) : T(0));
-            }
-            T ri;
-            const int bad = chol_wave_full<T, kBB, true>(a, c, &ri);
-            if (lane == 0) *s_bad = bad;
-            if (lane < bk) {
-                T *colw = A + k0 + (int64_t)(k0 + lane) * lda;
-#pragma unroll
-                for (int i = 0; i < kBB; ++i) {
-                    if (i <= lane) colw[i] = a[i];
-                    Us[lane][i] = a[i];  // [column][row]
-                }
-                rinv[lane] = ri;
-            }
-        }
+        T *A11 = A + k0 + (int64_t)k0 * lda;
+        // CHOL
+        chol_lds_load<T, kBB, kSub>(bk, A11, lda, sh.L);
         __syncthreads();
-        const int bad = __builtin_amdgcn_readfirstlane(*s_bad);
+        const int bad = chol_lds_core<T, kSub, kBB>((bk + kSub - 1) / kSub * kSub, sh.L, sh.Pt, sh.rinv, &sh.s_bad);
         if (bad != 0) return k0 + bad;
+        chol_lds_store<T>(bk, A11, lda, sh.L);
+        __syncthreads();  // U11 in memory for every wavefront; L free again
         if (m == 0) break;
-        // TRSM: A12 := U11^{-T} A12, bk == kBB here (m > 0)
-        for (int j = tid; j < m; j += 256) {
-            // keeps the U11 reads inside the loop (hoisted, they would not
-            // fit in registers)
+        // TRSM: A12 := U11^{-T} A12 (bk == kBB here)
+        T *A12 = A + k0 + (int64_t)(k0 + kBB) * lda;
+        trsm_inverses<T, kBB / 16>(kBB, A11, lda, sh.Ds);
+        __syncthreads();
+        for (int c0 = 16 * wave; c0 < m; c0 += 64) {
+            // keeps the U11 loads inside the loop (hoisted, they would not fit
+            // in registers)
             asm volatile("" ::: "memory");
-            T *col = A + k0 + (int64_t)(k0 + kBB + j) * lda;
-            T x[kBB];
-#pragma unroll
-            for (int i = 0; i < kBB; ++i) x[i] = col[i];
-#pragma unroll
-            for (int q = 0; q < kBB; ++q) {
-                x[q] = x[q] * rinv[q];
-#pragma unroll
-                for (int t = q + 1; t < kBB; ++t) x[t] = x[t] - Us[t][q] * x[q];
-                __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int i = 0; i < kBB; ++i) col[i] = x[i];
+            trsm_cols<T, kBB / 16>(kBB, m, A11, lda, A12, lda, c0, sh.Ds, sh.Rt[wave]);
         }
         __syncthreads();
         // SYRK: A22 -= A12^T A12 (upper)
-        syrk_tiles<T>(m, A + k0 + (int64_t)(k0 + kBB) * lda, lda, A + (k0 + kBB) + (int64_t)(k0 + kBB) * lda, lda,
-                      wave, lane);
+        syrk_tiles<T>(m, A12, lda, A + (k0 + kBB) + (int64_t)(k0 + kBB) * lda, lda, wave, lane);
         __syncthreads();
     }
     return 0;
@@ -190,11 +174,10 @@ __device__ int factor_one(int n, T *__restrict__ A, int64_t lda, T (*Us)[kBB + 1
 
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_batched(int32_t batch, const int32_t *__restrict__ ns, T *const *As,
-                                                 const int32_t *__restrict__ ldas, int32_t *__restrict__ info,
-                                                 const int32_t *__restrict__ order, int32_t *counter) {
-    __shared__ T Us[kBB][kBB + 1];
-    __shared__ T rinv[kBB];
-    __shared__ int s_item, s_bad;
+                                                    const int32_t *__restrict__ ldas, int32_t *__restrict__ info,
+                                                    const int32_t *__restrict__ order, int32_t *counter) {
+    __shared__ BatchLds<T> sh;
+    __shared__ int s_item;
     const int tid = threadIdx.x;
     // Every value that steers the loop is made wave-uniform (readfirstlane):
     // the branches around the barriers are then scalar, and every lane of a
@@ -209,7 +192,7 @@ __global__ __launch_bounds__(256, 2) void k_batched(int32_t batch, const int32_t
         const int n = __builtin_amdgcn_readfirstlane(ns[i]);
         const int lda = __builtin_amdgcn_readfirstlane(ldas[i]);
         int res = -1;  // order out of range or lda < n: not touched
-        if (n >= 0 && n <= kBatchMaxN && lda >= max(1, n)) res = factor_one<T>(n, As[i], (int64_t)lda, Us, rinv, &s_bad);
+        if (n >= 0 && n <= kBatchMaxN && lda >= max(1, n)) res = factor_one<T>(n, As[i], (int64_t)lda, sh);
         if (tid == 0) info[i] = res;
         __syncthreads();
     }
