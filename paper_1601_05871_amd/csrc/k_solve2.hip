@@ -195,11 +195,26 @@ __global__ __launch_bounds__(256) void k_symv_tiles(int64_t n, int tn, int nrhs,
     tile_of((int64_t)blockIdx.x, tn, tn, true, I, J);
     const int tid = threadIdx.x;
     const int64_t ri0 = (int64_t)I * kTb, cj0 = (int64_t)J * kTb;
-    for (int idx = tid; idx < kTb * kTb; idx += 256) {
-        const int c = idx >> 7, r = idx & (kTb - 1);
-        const int64_t gr = ri0 + r, gc = cj0 + c;
-        const double v = A[min(gr, n - 1) + min(gc, n - 1) * lda];
-        As[c][r] = (gr < n && gc < n && gr <= gc) ? v : 0.0;
+    // the tile in two halves of 32 loads per thread, all issued before their
+    // LDS stores (one load in flight at a time would leave the kernel
+    // latency-bound)
+    constexpr int kHalf = kTb * kTb / 512;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        double v[kHalf];
+#pragma unroll
+        for (int e = 0; e < kHalf; ++e) {
+            const int idx = tid + 256 * (h * kHalf + e);
+            const int c = idx >> 7, r = idx & (kTb - 1);
+            v[e] = A[min(ri0 + r, n - 1) + min(cj0 + c, n - 1) * lda];
+        }
+#pragma unroll
+        for (int e = 0; e < kHalf; ++e) {
+            const int idx = tid + 256 * (h * kHalf + e);
+            const int c = idx >> 7, r = idx & (kTb - 1);
+            const int64_t gr = ri0 + r, gc = cj0 + c;
+            As[c][r] = (gr < n && gc < n && gr <= gc) ? v[e] : 0.0;
+        }
     }
     for (int idx = tid; idx < nrhs * kTb; idx += 256) {
         const int k = idx >> 7, r = idx & (kTb - 1);
