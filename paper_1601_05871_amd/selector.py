@@ -13,8 +13,8 @@ Pipeline (each step a subcommand):
          FP64 and FP32, on A = B B^T + n I; writes the timing table.
   train  (CPU) fits the MLP to the table.  The loss is the expected
          slowdown  sum_c softmax(z)_c t_c / t_best  (cost-sensitive, so
-         near-ties cost little), plus a small cross-entropy term on the
-         fastest class; full-batch Adam.  The looped factorization's
+         near-ties cost little), optionally plus a cross-entropy term on the
+         fastest class (--ce-weight); full-batch Adam.  The looped factorization's
          per-matrix time does not depend on the batch size or on kappa, so
          every timed order is replicated over seeded batch sizes
          (log-uniform in [1, 10000]) and kappa values (10^U[0, 8]).
@@ -244,7 +244,7 @@ def _load_records(path, split):
 def cmd_train(args) -> int:
     recs = _load_records(args.sweep, "train")
     X, S = expand(recs, seed=args.seed)
-    p, hist = train(X, S, epochs=args.epochs, lr=args.lr, seed=args.seed)
+    p, hist = train(X, S, epochs=args.epochs, lr=args.lr, seed=args.seed, ce_weight=args.ce_weight)
     w = flatten(p)
     res = regret_table(p, recs)
     with open(args.out, "w") as f:
@@ -307,9 +307,10 @@ def main() -> int:
     b = sub.add_parser("train")
     b.add_argument("--sweep", required=True)
     b.add_argument("--out", required=True)
-    b.add_argument("--epochs", type=int, default=4000)
-    b.add_argument("--lr", type=float, default=3e-3)
+    b.add_argument("--epochs", type=int, default=12000)
+    b.add_argument("--lr", type=float, default=1e-3)
     b.add_argument("--seed", type=int, default=0)
+    b.add_argument("--ce-weight", type=float, default=0.0)
     c = sub.add_parser("eval")
     c.add_argument("--sweep", required=True)
     c.add_argument("--weights", required=True)

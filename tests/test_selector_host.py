@@ -81,3 +81,21 @@ def test_features():
     assert f.tolist() == [10.0, 0.0, 1.0, 0.0, 0.0]
     f = sel.features(64, 10000, False, 1e4)
     assert math.isclose(f[1], math.log2(10000), rel_tol=1e-6) and f[3] == 1.0 and math.isclose(f[4], 4.0)
+
+
+def test_committed_weights_and_evaluation():
+    """The committed selector weights have the library's layout and give
+    finite logits; the committed held-out evaluation reports its regret."""
+    import json
+    import os
+
+    with open(sel.DEFAULT_WEIGHTS) as f:
+        w = np.array(json.load(f)["weights"], dtype=np.float32)
+    assert w.size == fl.SEL_NPARAM
+    z, _ = sel.forward(sel.unflatten(w), np.stack([sel.features(n, 1, d, 0.0) for n in (100, 5000) for d in (1, 0)]))
+    assert np.all(np.isfinite(z))
+    ev = os.path.join(os.path.dirname(sel.DEFAULT_WEIGHTS), "eval_heldout.json")
+    with open(ev) as f:
+        res = json.load(f)
+    assert 0.0 <= res["mean_regret"] <= res["max_regret"]
+    assert len(res["rows"]) >= 8
