@@ -72,7 +72,10 @@ typedef enum { FLAME_TRAIL_NATIVE = 0, FLAME_TRAIL_F32 = 1, FLAME_TRAIL_BF16 = 2
 typedef struct {
     int32_t variant;   /* flame_variant_t; 0 = choose */
     int32_t nb;        /* block size b (A11 is b x b, the last block min(b, n-k));
-                          0 = choose (selector, else 256); valid range 1..256 */
+                          0 = choose (selector, else 256); valid range 1..512.
+                          RIGHT with lookahead: the last 8192 columns use
+                          min(b, 256) and the last 6144 (4096 with FP32/BF16
+                          trailing products) min(b, 128) */
     int32_t trail;     /* flame_trail_t */
     int32_t lookahead; /* RIGHT variant: 0 = default (2), -1 = off.
                           1: the next diagonal block and panel are updated first

@@ -9,7 +9,8 @@ using namespace flame;
 
 namespace {
 
-constexpr int kMaxNb = 256;
+constexpr int kMaxNb = 512;     // block size of the factorization loops
+constexpr int kMaxBlockOp = 256;  // order of the exposed block operations
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
@@ -56,7 +57,7 @@ int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opt
 
 int flame_op_chol(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, int64_t info_base, void *stream) {
     if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
-    if (n < 0 || n > kMaxNb) return -2;
+    if (n < 0 || n > kMaxBlockOp) return -2;
     if (A == nullptr && n > 0) return -3;
     if (lda < (n > 1 ? n : 1)) return -4;
     if (info == nullptr) return -5;
@@ -68,7 +69,7 @@ int flame_op_chol(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info,
 int flame_op_trsm(int32_t dtype, int64_t b, int64_t m, const void *U, int64_t ldu, void *X, int64_t ldx,
                   void *stream) {
     if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
-    if (b < 0 || b > kMaxNb) return -2;
+    if (b < 0 || b > kMaxBlockOp) return -2;
     if (m < 0) return -3;
     if (U == nullptr && b > 0) return -4;
     if (ldu < (b > 1 ? b : 1)) return -5;

@@ -56,6 +56,13 @@ constexpr int kChainCus = FLAME_CHAIN_CUS;
 constexpr int64_t kTailN = FLAME_TAIL_N;
 constexpr int64_t kTailNMixed = 4096;
 constexpr int64_t kTailNb = 128;
+// Blocks above 256 (a trailing update with K = 512 runs at 61 TF/s against
+// 53 at K = 256) drop to 256 for the last kMidN columns.
+#ifndef FLAME_MID_N
+#define FLAME_MID_N 8192
+#endif
+constexpr int64_t kMidN = FLAME_MID_N;
+constexpr int64_t kMidNb = 256;
 
 // Split-K form of C -= X^T Y for the tall-K products of the left-looking and
 // bordered variants (K up to n, output only b rows): the K range is cut into
@@ -140,11 +147,16 @@ int factor_right(int64_t n, T *A, int64_t lda, int nb, int lookahead, flame_trai
     hipEvent_t ev_panel = ctx_event(ctx, 0);  // next panel rows updated (main)
     hipEvent_t ev_ready = ctx_event(ctx, 1);  // next CHOL + TRSM done (side)
     // Block size by position: nb while the trailing matrix is large (the
-    // trailing update dominates), kTailNb once at most kTailN columns remain
-    // (the serial CHOL + TRSM chain dominates there and costs less per column
-    // at the smaller block).
+    // trailing update dominates), at most kMidNb once kMidN columns remain and
+    // kTailNb once kTailN remain (the serial CHOL + TRSM chain dominates there
+    // and costs less per column at the smaller block).
     const int64_t tail_n = mixed ? kTailNMixed : kTailN;
-    auto nb_at = [&](int64_t k) -> int64_t { return (nb > kTailNb && n - k <= tail_n) ? kTailNb : nb; };
+    auto nb_at = [&](int64_t k) -> int64_t {
+        const int64_t rest = n - k;
+        if (rest <= tail_n) return std::min<int64_t>(nb, kTailNb);
+        if (rest <= kMidN) return std::min<int64_t>(nb, kMidNb);
+        return nb;
+    };
     {
         const int64_t bk = std::min<int64_t>(nb_at(0), n);
         rc = launch_chol_block<T>((int)bk, V.at(0, 0), lda, info, 0, s);

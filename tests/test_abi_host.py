@@ -57,7 +57,7 @@ def test_factor_argument_errors(args, expect):
     assert fl.lib().flame_factor(*args) == expect
 
 
-@pytest.mark.parametrize("field,value", [("variant", 9), ("nb", 257), ("nb", -1), ("trail", 3),
+@pytest.mark.parametrize("field,value", [("variant", 9), ("nb", 513), ("nb", -1), ("trail", 3),
                                          ("lookahead", 3), ("graph", 5), ])
 def test_factor_bad_options(field, value):
     o = _opts(**{field: value})

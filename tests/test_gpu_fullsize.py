@@ -1,5 +1,5 @@
 """Full-size checks at n = 16384 in the benchmark's launch configuration
-(right-looking, nb = 256, lookahead 2): an exact
+(right-looking, nb = 512, lookahead 2): an exact
 input checked everywhere, a random input checked through properties that hold
 at any size and on the rows the oracle can afford, and the mixed-precision
 path with refinement."""
@@ -18,7 +18,7 @@ DEV = "cuda:0"
 
 
 def _bench_factor(A, trail="native"):
-    return fl.factor(A, variant=fl.VAR_RIGHT, nb=256, lookahead=2, trail=trail)
+    return fl.factor(A, variant=fl.VAR_RIGHT, nb=512, lookahead=2, trail=trail)
 
 
 def _minij_device(n):

@@ -287,11 +287,12 @@ def _oracle_factor(n, seed):
     return _ORACLE_CACHE[(n, seed)]
 
 
-@pytest.mark.parametrize("variant", [1, 2])
-@pytest.mark.parametrize("nb", [64, 256])
+@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("nb", [64, 256, 512])
 def test_tall_k_products_split(variant, nb):
     """n = 2600: the left-looking and bordered loops' products with K up to
-    ~2500 are split over K slices (partials added in slice order)."""
+    ~2500 are split over K slices (partials added in slice order); nb = 512
+    takes the diagonal factorization and the panel solve three levels deep."""
     n = 2600
     A, Uo = _oracle_factor(n, 12)
     Ad = to_dev(A, ld=n + 8)
