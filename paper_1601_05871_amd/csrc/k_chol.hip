@@ -1,12 +1,14 @@
 // CHOL step of the loop body (Fig. "dense-chol"): A11 := Chol(A11) for one
 // diagonal block of order n <= 256, upper triangle, in place.
 //
-// Orders up to 128: one workgroup holds the block in LDS (packed upper
-// triangle, 66 KB in FP64, so that the kernel fits on a CU beside one
-// workgroup of the trailing update) and factors it with the sub-blocked loop
-// of chol_lds.h; the factor is written back once.  Orders 129..256 take the
-// same loop one level up (two LDS-resident blocks, the panel TRSM and the
-// trailing update kernels in between).
+// Orders up to 128: one workgroup holds the block's upper triangle in LDS as
+// 16 x 16 tiles (72 KB in FP64, so that the kernel fits on a CU beside one
+// workgroup of the trailing update) and factors it with the band loop of
+// chol_lds.h (per 16-row band: one elimination pass over diagonal block and
+// row panel, then a matrix-core rank-16 update); U goes to A straight from
+// registers.  Orders 129..256 take the same loop one level up (two
+// LDS-resident blocks, the panel TRSM and the trailing update kernels in
+// between).
 #include "chol_lds.h"
 #include "flame_internal.h"
 
@@ -17,19 +19,13 @@ constexpr int kLdsN = 128;
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_chol_lds(int n, T *__restrict__ A, int64_t lda, int32_t *__restrict__ info,
                                                   int64_t info_base) {
-    __shared__ T L[packed_size<kLdsN>()];  // the block's upper triangle, packed columns
-    __shared__ T Pt[S][kLdsN - S + 4];     // the current panel rows, row-major
-    __shared__ T rinv[S];                  // 1 / U(j, j) of the current sub-block
+    __shared__ T L[band_lds_size<kLdsN>()];              // the block's upper triangle in 16 x 16 tiles
     __shared__ int s_bad;
     if (info != nullptr && *info != 0) return;
-    chol_lds_load<T, kLdsN, S>(n, A, lda, L);
+    band_load<T, kLdsN>(n, A, lda, L);
     __syncthreads();
-    const int bad = chol_lds_core<T, S, kLdsN>((n + S - 1) / S * S, L, Pt, rinv, &s_bad);
-    if (bad != 0) {
-        if (threadIdx.x == 0) *info = (int32_t)(info_base + bad);
-        return;
-    }
-    chol_lds_store<T>(n, A, lda, L);
+    const int bad = chol_lds_core2<T, kLdsN>(n, L, &s_bad, A, lda);
+    if (bad != 0 && threadIdx.x == 0) *info = (int32_t)(info_base + bad);
 }
 
 template <typename T>
