@@ -63,6 +63,16 @@ constexpr int64_t kTailNb = 128;
 #endif
 constexpr int64_t kMidN = FLAME_MID_N;
 constexpr int64_t kMidNb = 256;
+// While more than kEarlyN rows remain below the next panel, the remainder of
+// the trailing update is launched before the update of the next panel rows
+// (the two write disjoint rows and read only the current panel): the panel
+// update then overlaps the long remainder instead of running alone.  Below
+// that the chain of the next CHOL and TRSM is critical and the panel update
+// keeps the whole GPU.
+#ifndef FLAME_EARLY_N
+#define FLAME_EARLY_N 8192
+#endif
+constexpr int64_t kEarlyN = FLAME_EARLY_N;
 
 // Split-K form of C -= X^T Y for the tall-K products of the left-looking and
 // bordered variants (K up to n, output only b rows): the K range is cut into
@@ -178,6 +188,16 @@ int factor_right(int64_t n, T *A, int64_t lda, int nb, int lookahead, flame_trai
         const int64_t k2 = k + bk;
         const int64_t bk2 = std::min<int64_t>(nb_at(k2), m);
         const int64_t m2 = m - bk2;
+        const bool early = rest_on_side && m2 > kEarlyN;
+        if (early) {
+            // the rest of A22 (rows and columns [bk2, m)) first, on the second
+            // stream, beside the panel-row update below
+            FLAME_HIP(hipEventRecord(ev_panel, s));
+            FLAME_HIP(hipStreamWaitEvent(side, ev_panel, 0));
+            rc = update(k, bk, bk2, m2, bk2, m2, side, kChainCus);
+            if (rc) return rc;
+            FLAME_HIP(hipEventRecord(ev_ready, side));
+        }
         // rows [0, bk2) of A22: the next A11 and A12
         rc = update(k, bk, 0, bk2, 0, m, s);
         if (rc) return rc;
@@ -199,14 +219,16 @@ int factor_right(int64_t n, T *A, int64_t lda, int nb, int lookahead, flame_trai
             if (rc) return rc;
             FLAME_HIP(hipStreamWaitEvent(s, ev_ready, 0));
         } else {
-            // the rest of A22 on the second stream; the next CHOL and TRSM
-            // follow the panel rows on the main stream, which dispatches them
-            // ahead of the remainder's workgroups
-            FLAME_HIP(hipEventRecord(ev_panel, s));
-            FLAME_HIP(hipStreamWaitEvent(side, ev_panel, 0));
-            rc = update(k, bk, bk2, m2, bk2, m2, side, kChainCus);
-            if (rc) return rc;
-            FLAME_HIP(hipEventRecord(ev_ready, side));
+            // the rest of A22 on the second stream (unless already launched);
+            // the next CHOL and TRSM follow the panel rows on the main stream,
+            // which dispatches them ahead of the remainder's workgroups
+            if (!early) {
+                FLAME_HIP(hipEventRecord(ev_panel, s));
+                FLAME_HIP(hipStreamWaitEvent(side, ev_panel, 0));
+                rc = update(k, bk, bk2, m2, bk2, m2, side, kChainCus);
+                if (rc) return rc;
+                FLAME_HIP(hipEventRecord(ev_ready, side));
+            }
             rc = launch_chol_block<T>((int)bk2, V.at(k2, k2), lda, info, k2, s);
             if (rc) return rc;
             rc = launch_trsm_panel<T>((int)bk2, m2, V.at(k2, k2), lda, V.at(k2, k2 + bk2), lda, info, s);
