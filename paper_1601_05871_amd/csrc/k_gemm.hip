@@ -738,8 +738,11 @@ static int launch_t(const GemmP &p, bool vec, hipStream_t s) {
     constexpr int64_t CK = 4 * Tr<P>::VEC;
     constexpr int64_t CK8 = 2 * CK;
     // FP64 runs best as two 4-wavefront workgroups per CU (k_gemm_lds); the
-    // FP32 / BF16 products as one persistent 8-wavefront workgroup (k_gemm_p8)
-    const bool lds8_ok = P != Prec::F64 && vec && p.K > 0 && (p.K % CK8) == 0;
+    // FP32 / BF16 products alone as one persistent 8-wavefront workgroup
+    // (k_gemm_p8).  Beside the CHOL/TRSM chain (a CU reservation) they also
+    // take k_gemm_lds: k_gemm_p8 fills whole CUs and leaves the chain's panel
+    // TRSM only the reserved ones
+    const bool lds8_ok = P != Prec::F64 && p.reserve_cus == 0 && vec && p.K > 0 && (p.K % CK8) == 0;
     const bool lds_ok = vec && p.K > 0 && (p.K % CK) == 0;
     // algorithmic work: 2K flops per updated element; each operand element
     // read once (one panel when X and Y are the same), C read and written
