@@ -371,18 +371,24 @@ __global__ __launch_bounds__(256, 1) void k_gemm_tn(GemmP p) {
 // MFMAs of chunk c (two LDS buffers, one barrier per chunk).  Each column's
 // eight 16-byte units are stored XOR-swizzled by (column mod 8) so that the
 // 16 lanes reading one unit of 16 consecutive columns hit different banks.
-constexpr int kSlabBytes = kTile * 128;  // one operand, one chunk
 
 __device__ __forceinline__ int slab_off(int col, int unit) { return col * 128 + ((unit ^ (col & 7)) << 4); }
 
-template <Prec P, typename CT>
+// TM: tile order, 128 (wavefront blocks of 64 x 64) or 64 (32 x 32: four
+// times the workgroups for launches with few tiles, a quarter of the serial
+// MFMA chain per tile).
+template <Prec P, typename CT, int TM>
 __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
     using TR = Tr<P>;
     using in_t = typename TR::in_t;
     using acc_t = typename TR::acc_t;
     constexpr int VEC = TR::VEC;
     constexpr int CK = 4 * VEC;  // k per chunk (128 bytes of a column)
-    __shared__ __attribute__((aligned(16))) char lds[2][2][kSlabBytes];  // [buffer][X or Y]
+    constexpr int WT = TM / 2;   // a wavefront's block of the tile: WT x WT
+    constexpr int WB = WT / 16;  // 16 x 16 MFMA blocks per wavefront side
+    constexpr int NJ = TM / 32;  // operand columns copied per thread and chunk
+    static_assert(TM == 128 || TM == 64, "tile order");
+    __shared__ __attribute__((aligned(16))) char lds[2][2][TM * 128];  // [buffer][X or Y]
 
     if (p.info != nullptr && *p.info != 0) return;
     const bool split = p.nslices > 1;
@@ -403,29 +409,29 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
     const int lane = tid & 63;
     const int r = lane & 15;
     const int g = lane >> 4;
-    const int64_t tr0 = (int64_t)I * kTile, tc0 = (int64_t)J * kTile;
-    const int64_t row0 = tr0 + (wave >> 1) * 64;
-    const int64_t col0 = tc0 + (wave & 1) * 64;
+    const int64_t tr0 = (int64_t)I * TM, tc0 = (int64_t)J * TM;
+    const int64_t row0 = tr0 + (wave >> 1) * WT;
+    const int64_t col0 = tc0 + (wave & 1) * WT;
     const int64_t M = p.M, N = p.N;
     const int64_t K = split ? min(p.kslice, p.K - kbeg) : p.K;
     const int64_t ldc = split ? p.ldw : p.ldc;
-    const bool active = (row0 < M) && (col0 < N) && !(p.upper && row0 > col0 + 63);
+    const bool active = (row0 < M) && (col0 < N) && !(p.upper && row0 > col0 + WT - 1);
     const char *__restrict__ Xb = static_cast<const char *>(p.X) + kbeg * (int64_t)sizeof(in_t);
     const char *__restrict__ Yb = static_cast<const char *>(p.Y) + kbeg * (int64_t)sizeof(in_t);
     const int64_t ldxb = p.ldx * (int64_t)sizeof(in_t), ldyb = p.ldy * (int64_t)sizeof(in_t);
 
-    // copy assignment: thread tid moves units q = tid + 256 j (j < 8) of the
-    // 2 x 1024 units of a chunk.  Unit q belongs to operand q / 1024 (j / 4),
-    // column (q % 1024) / 8 = tid / 8 + 32 (j % 4), 16-byte unit q % 8 = tid % 8.
+    // copy assignment: thread tid moves units q = tid + 256 j (j < 2 NJ) of the
+    // 2 x 8 TM units of a chunk.  Unit q belongs to operand q / (8 TM) (j / NJ),
+    // column (q % (8 TM)) / 8 = tid / 8 + 32 (j % NJ), 16-byte unit q % 8 = tid % 8.
     const int unit = tid & 7;
     const int ccol0 = tid >> 3;
     const int64_t chunk_bytes = CK * (int64_t)sizeof(in_t);  // 128
     const int64_t nch = K / CK;
-    // byte offsets (from Xb / Yb) of this thread's four columns of each operand
-    int64_t xoff[4], yoff[4];
-    int dofs[4];
+    // byte offsets (from Xb / Yb) of this thread's NJ columns of each operand
+    int64_t xoff[NJ], yoff[NJ];
+    int dofs[NJ];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         const int col = ccol0 + 32 * j;
         xoff[j] = min(tr0 + col, M - 1) * ldxb + unit * 16;
         yoff[j] = min(tc0 + col, N - 1) * ldyb + unit * 16;
@@ -439,41 +445,41 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
     // negated; otherwise it starts at zero and C - X^T Y is formed at the end.
     constexpr bool CINIT = (P == Prec::F64 && sizeof(CT) == 8) || (P == Prec::F32 && sizeof(CT) == 4);
     CT *__restrict__ C = split ? static_cast<CT *>(p.W) + (kbeg / p.kslice) * p.ldw * N : static_cast<CT *>(p.C);
-    acc_t acc[4][4];
+    acc_t acc[WB][WB];
     // one uniform branch around the whole (unconditional, clamped) tile load
     if (CINIT && !split) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < WB; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+            for (int b = 0; b < WB; ++b)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     acc[a][b][v] = C[min(FLAME_CROW(a, v), M - 1) + min(FLAME_CCOL(b, v), N - 1) * ldc];
     } else {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < WB; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+            for (int b = 0; b < WB; ++b)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[a][b][v] = 0;
     }
 
-    const int xr = (wave >> 1) * 64 + r, yr = (wave & 1) * 64 + r;
-    u32x4 stx[4], sty[4];
+    const int xr = (wave >> 1) * WT + r, yr = (wave & 1) * WT + r;
+    u32x4 stx[NJ], sty[NJ];
 
 #define FLAME_FETCH1(j, cidx)                                                                         \
     stx[j] = *reinterpret_cast<const u32x4 *>(Xb + xoff[j] + (cidx) * chunk_bytes);                   \
     sty[j] = *reinterpret_cast<const u32x4 *>(Yb + yoff[j] + (cidx) * chunk_bytes);
 #define FLAME_FETCH(cidx)                                                                             \
     {                                                                                                 \
-        FLAME_FETCH1(0, cidx) FLAME_FETCH1(1, cidx) FLAME_FETCH1(2, cidx) FLAME_FETCH1(3, cidx)       \
+        _Pragma("unroll") for (int j_ = 0; j_ < NJ; ++j_) { FLAME_FETCH1(j_, cidx) }                  \
     }
 #define FLAME_PUT1(j, buf)                                                                            \
     *reinterpret_cast<u32x4 *>(&lds[buf][0][0] + dofs[j]) = stx[j];                                   \
     *reinterpret_cast<u32x4 *>(&lds[buf][1][0] + dofs[j]) = sty[j];
 #define FLAME_PUT(buf)                                                                                \
     {                                                                                                 \
-        FLAME_PUT1(0, buf) FLAME_PUT1(1, buf) FLAME_PUT1(2, buf) FLAME_PUT1(3, buf)                   \
+        _Pragma("unroll") for (int j_ = 0; j_ < NJ; ++j_) { FLAME_PUT1(j_, buf) }                     \
     }
 // One chunk from LDS buffer `buf`: the two 16-byte halves of each lane's
 // fragments are read and multiplied in turn (half the operand registers).
@@ -482,15 +488,15 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
         const char *xs_ = &lds[buf][0][0];                                                            \
         const char *ys_ = &lds[buf][1][0];                                                            \
         _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                               \
-            u32x4 fa_[4], fb_[4];                                                                     \
-            _Pragma("unroll") for (int a = 0; a < 4; ++a) {                                           \
+            u32x4 fa_[WB], fb_[WB];                                                                   \
+            _Pragma("unroll") for (int a = 0; a < WB; ++a) {                                          \
                 fa_[a] = *reinterpret_cast<const u32x4 *>(xs_ + slab_off(xr + 16 * a, 2 * g + h));    \
                 if constexpr (CINIT) fa_[a] = negate_half(P, fa_[a]);                                 \
             }                                                                                         \
-            _Pragma("unroll") for (int b = 0; b < 4; ++b)                                             \
+            _Pragma("unroll") for (int b = 0; b < WB; ++b)                                            \
                 fb_[b] = *reinterpret_cast<const u32x4 *>(ys_ + slab_off(yr + 16 * b, 2 * g + h));    \
-            _Pragma("unroll") for (int a = 0; a < 4; ++a)                                             \
-                _Pragma("unroll") for (int b = 0; b < 4; ++b) mfma_half<P>(acc[a][b], fa_[a], fb_[b]); \
+            _Pragma("unroll") for (int a = 0; a < WB; ++a)                                            \
+                _Pragma("unroll") for (int b = 0; b < WB; ++b) mfma_half<P>(acc[a][b], fa_[a], fb_[b]); \
         }                                                                                             \
     }
 
@@ -515,11 +521,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
 
     FLAME_COMPUTE((int)(c & 1))
     if (active) {
-        const bool interior = (row0 + 64 <= M) && (col0 + 64 <= N) && (!p.upper || row0 + 63 <= col0);
+        const bool interior = (row0 + WT <= M) && (col0 + WT <= N) && (!p.upper || row0 + WT - 1 <= col0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < WB; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+            for (int b = 0; b < WB; ++b)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int64_t row = FLAME_CROW(a, v), col = FLAME_CCOL(b, v);
@@ -733,6 +739,16 @@ __global__ __launch_bounds__(512, 1) void k_gemm_p8(GemmP p) {
 #undef FLAME_CCOL
 }
 
+// Launches with at most this many 128-tiles (about one per CU; no CU
+// reservation, no split) run on 64-tiles: the products inside the 256- and
+// 512-wide CHOL and TRSM steps and the panel-row updates of the tail
+// (n = 16384: 35.5 -> 33.0 ms; at 512 and above the large panel-row updates
+// lose more than the small ones gain: 38.7 ms)
+#ifndef FLAME_SMALL_TILES
+#define FLAME_SMALL_TILES 256
+#endif
+constexpr int64_t kSmallTiles = FLAME_SMALL_TILES;
+
 template <Prec P, typename CT>
 static int launch_t(const GemmP &p, bool vec, hipStream_t s) {
     constexpr int64_t CK = 4 * Tr<P>::VEC;
@@ -768,8 +784,15 @@ static int launch_t(const GemmP &p, bool vec, hipStream_t s) {
     if (lds8_ok)
         hipLaunchKernelGGL((k_gemm_p8<P, CT>), dim3((unsigned)std::min<int64_t>(p.ntiles, cus_left)), dim3(512), 0, s,
                            p);
-    else if (lds_ok)
-        hipLaunchKernelGGL((k_gemm_lds<P, CT>),
+    else if (lds_ok && p.reserve_cus == 0 && p.nslices <= 1 && p.ntiles <= kSmallTiles) {
+        // few 128-tiles: 64-tiles, four times the workgroups
+        GemmP q = p;
+        q.tm = (int)((p.M + 63) / 64);
+        q.tn = (int)((p.N + 63) / 64);
+        q.ntiles = tile_count(q.tm, q.tn, p.upper != 0);
+        hipLaunchKernelGGL((k_gemm_lds<P, CT, 64>), dim3((unsigned)q.ntiles), dim3(256), 0, s, q);
+    } else if (lds_ok)
+        hipLaunchKernelGGL((k_gemm_lds<P, CT, 128>),
                            dim3((unsigned)(p.reserve_cus > 0 ? std::min<int64_t>(p.ntiles, 2 * cus_left) : p.ntiles)),
                            dim3(256), 0, s, p);
     else if (vec)
@@ -885,7 +908,7 @@ int launch_gemm_splitk(bool upper, int64_t M, int64_t N, int64_t K, const CT *X,
     const double dM = (double)M, dN = (double)N, dK = (double)K;
     const double elems = upper ? (M <= N ? dM * (dM + 1) / 2 + (dN - dM) * dM : dN * (dN + 1) / 2) : dM * dN;
     const int tr = trace_begin(FLAME_KC_GEMM, s);
-    hipLaunchKernelGGL((k_gemm_lds<P, CT>), dim3((unsigned)(p.ntiles * S)), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_gemm_lds<P, CT, 128>), dim3((unsigned)(p.ntiles * S)), dim3(256), 0, s, p);
     FLAME_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_splitk_reduce<CT>, dim3((unsigned)((M + 255) / 256), (unsigned)N), dim3(256), 0, s, M, N,
                        p.upper, W, M, S, C, ldc);
