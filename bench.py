@@ -149,7 +149,7 @@ def main() -> int:
     g = trace["gemm"]
     gemm_tflops = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
     roofline = {
-        "kernel": "k_gemm_lds<F64> (trailing SYRK/GEMM)",
+        "kernel": "k_gemm_lds<F64> (trailing SYRK/GEMM, 128- and 64-tiles)",
         "bound": "mfma",
         "achieved": round(gemm_tflops, 3),
         "peak": PEAK_F64_TFLOPS,
