@@ -98,14 +98,22 @@ __device__ __forceinline__ void trsm_cols(int b, int64_t m, const T *__restrict_
         colok[v] = col < m;
         colc[v] = min(col, m - 1);
     }
+    // all loads first (clamped addresses, unconditional): the barrier keeps
+    // the compiler from sinking each load into the masking select below,
+    // which would give one branch and one full memory wait per load
+    T xin[NB][4];
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xin[t][v] = X[(int64_t)min(16 * t + arow(v), b - 1) + colc[v] * ldx];
+    asm volatile("" ::: "memory");
     acc_t acc[NB];
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * t + arow(v);
-            const T x = X[(int64_t)min(row, b - 1) + colc[v] * ldx];
-            acc[t][v] = (row < b && colok[v]) ? x : T(0);
+            acc[t][v] = (row < b && colok[v]) ? xin[t][v] : T(0);
         }
     }
 #pragma unroll
