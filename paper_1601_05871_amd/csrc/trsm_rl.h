@@ -54,22 +54,47 @@ __device__ __forceinline__ f4v mma_rc(float rowop, float colop, f4v acc) {
 }
 
 // (1) D_s = U_ss^{-1} for the NB diagonal 16 x 16 blocks into Ds (all threads
-// of the workgroup; U read from global memory / L2).
+// of the workgroup).  The blocks are first copied into Ds with coalesced
+// loads (eight per thread, all issued before the LDS stores), then each of
+// NB * 16 threads solves one column U_ss D(:, t) = e_t by back substitution
+// from LDS into registers, and the columns replace the blocks in Ds.
 template <typename T, int NB>
 __device__ __forceinline__ void trsm_inverses(int b, const T *__restrict__ U, int64_t ldu, T (*Ds)[16][17]) {
     const int tid = threadIdx.x;
-    for (int ct = tid; ct < NB * 16; ct += 256) {
-        const int sb = ct >> 4, t = ct & 15;  // column t of D_sb: U_ss D(:, t) = e_t
-        T v[16];
+    constexpr int PER = (NB * 256 + 255) / 256;
+    T v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;  // element (i, j) of block sb, i fastest
+        const int sb = min(e >> 8, NB - 1), i = e & 15, j = (e >> 4) & 15;
+        v[q] = U[(int64_t)min(16 * sb + i, b - 1) + (int64_t)min(16 * sb + j, b - 1) * ldu];
+    }
+    asm volatile("" ::: "memory");  // the loads stay ahead of the stores below
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        const int sb = e >> 8, i = e & 15, j = (e >> 4) & 15;
+        if (sb < NB) {
+            const int gi = 16 * sb + i, gj = 16 * sb + j;
+            Ds[sb][i][j] = (gi < b && gj < b) ? v[q] : (gi == gj ? T(1) : T(0));
+        }
+    }
+    __syncthreads();
+    T d[16];
+    const int sb = tid >> 4, t = tid & 15;  // column t of D_sb
+    if (sb < NB) {
 #pragma unroll
         for (int i = 15; i >= 0; --i) {
             T acc = (i == t) ? T(1) : T(0);
 #pragma unroll
-            for (int k = i + 1; k < 16; ++k) acc -= u_pad(U, ldu, b, 16 * sb + i, 16 * sb + k) * v[k];
-            v[i] = acc / u_pad(U, ldu, b, 16 * sb + i, 16 * sb + i);  // rows below the diagonal come out 0
+            for (int k = i + 1; k < 16; ++k) acc -= Ds[sb][i][k] * d[k];
+            d[i] = acc / Ds[sb][i][i];  // rows below the diagonal come out 0
         }
+    }
+    __syncthreads();
+    if (sb < NB) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) Ds[sb][i][t] = v[i];
+        for (int i = 0; i < 16; ++i) Ds[sb][i][t] = d[i];
     }
 }
 
