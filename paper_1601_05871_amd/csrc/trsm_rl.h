@@ -141,8 +141,28 @@ __device__ __forceinline__ void trsm_cols(int b, int64_t m, const T *__restrict_
             acc[t][v] = (row < b && colok[v]) ? xin[t][v] : T(0);
         }
     }
+    // U(s, t) operands of row block s (all t > s), loaded one row block ahead
+    // of their use: the barrier keeps each set of loads at its issue point,
+    // so their latency overlaps the previous block's products
+    T un[NB][4];
+#pragma unroll
+    for (int t = 1; t < NB; ++t)
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4) un[t][t4] = u_pad(U, ldu, b, 4 * g + t4, 16 * t + r);
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
+        T uc[NB][4];
+#pragma unroll
+        for (int t = s + 1; t < NB; ++t)
+#pragma unroll
+            for (int t4 = 0; t4 < 4; ++t4) uc[t][t4] = un[t][t4];
+        if (s + 1 < NB) {
+#pragma unroll
+            for (int t = s + 2; t < NB; ++t)
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4) un[t][t4] = u_pad(U, ldu, b, 16 * (s + 1) + 4 * g + t4, 16 * t + r);
+        }
+        asm volatile("" ::: "memory");
         if (s < nblk) {
             // X_s = D_s^T R_s: R_s through LDS into operand layout
 #pragma unroll
@@ -165,7 +185,7 @@ __device__ __forceinline__ void trsm_cols(int b, int64_t m, const T *__restrict_
 #pragma unroll
                     for (int t4 = 0; t4 < 4; ++t4) {
                         const int k = 4 * g + t4;
-                        acc[t] = mma_rc(u_pad(U, ldu, b, 16 * s + k, 16 * t + r), Rt[k][r], acc[t]);
+                        acc[t] = mma_rc(uc[t][t4], Rt[k][r], acc[t]);
                     }
                 }
             }
