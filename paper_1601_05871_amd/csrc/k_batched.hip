@@ -8,14 +8,18 @@
 // small ones fill the tail (longest-processing-time-first scheduling).
 //
 // One workgroup (4 wavefronts) factors one matrix with the right-looking loop
-// of Fig. "dense-chol" at block size kBB = 64, on the matrix in HBM / L2:
-//   CHOL  the 64 x 64 diagonal block in LDS (packed), factored in 16-column
-//         sub-blocks (chol_lds.h), written back;
-//   TRSM  the 64-row panel on matrix cores, 16 columns per wavefront
+// of Fig. "dense-chol" at block size kBB = 128, on the matrix in HBM / L2:
+//   CHOL  the 128 x 128 diagonal block in LDS as 16 x 16 tiles, factored
+//         band by band with matrix-core trailing updates (chol_lds.h), U11
+//         stored as each band is done;
+//   TRSM  the 128-row panel on matrix cores, 16 columns per wavefront
 //         (trsm_rl.h);
 //   SYRK  the upper 32 x 32 tiles of A22 are spread over the wavefronts; each
 //         tile is a 2 x 2 set of 16 x 16 matrix-core products (FP64 or FP32
-//         MFMA, K = 64) accumulated onto the tile of A22.
+//         MFMA, K = 128) accumulated onto the tile of A22.
+// The diagonal block's LDS tiles and the TRSM scratch share one union (73.7 KB
+// in FP64), so two workgroups fit on a CU.  A matrix of order <= 128 is one
+// CHOL step.
 // A breakdown stops that matrix only (info[i] = first bad column, 1-based).
 #include "chol_lds.h"
 #include "flame_internal.h"
@@ -23,8 +27,10 @@
 
 namespace flame {
 
-constexpr int kBB = 64;            // block size inside a workgroup
-constexpr int kSub = 16;           // sub-block of the diagonal factorization
+#ifndef FLAME_BATCH_BB
+#define FLAME_BATCH_BB 128
+#endif
+constexpr int kBB = FLAME_BATCH_BB;  // block size inside a workgroup (64 or 128; 128 measured faster)
 constexpr int kBatchMaxN = 1024;   // largest order accepted
 constexpr int kBuckets = kBatchMaxN + 2;  // orders 0..1024, plus one for invalid entries
 
@@ -126,14 +132,17 @@ __device__ void syrk_tiles(int m, const T *__restrict__ P, int64_t ldp, T *__res
     }
 }
 
-// Workgroup-shared scratch of factor_one.
+// Workgroup-shared scratch of factor_one: the diagonal block's tiles during
+// CHOL, the TRSM inverses and per-wavefront staging afterwards.
 template <typename T>
 struct BatchLds {
-    T L[packed_size<kBB>()];   // diagonal block, packed upper triangle
-    T Pt[kSub][kBB - kSub + 4];  // its sub-block panel rows
-    T rinv[kSub];
-    T Ds[kBB / 16][16][17];    // inverses of the 16 x 16 diagonal blocks of U11
-    T Rt[4][16][17];           // per wavefront TRSM scratch
+    union {
+        T L[band_lds_size<kBB>()];  // diagonal block, upper 16 x 16 tiles
+        struct {
+            T Ds[kBB / 16][16][17];  // inverses of the 16 x 16 diagonal blocks of U11
+            T Rt[4][16][17];         // per wavefront TRSM scratch
+        } t;
+    };
     int s_bad;
 };
 
@@ -146,23 +155,22 @@ __device__ int factor_one(int n, T *__restrict__ A, int64_t lda, BatchLds<T> &sh
         const int bk = min(kBB, n - k0);
         const int m = n - k0 - bk;
         T *A11 = A + k0 + (int64_t)k0 * lda;
-        // CHOL
-        chol_lds_load<T, kBB, kSub>(bk, A11, lda, sh.L);
+        // CHOL: the block's tiles in LDS, U11 stored to A11 band by band
+        band_load<T, kBB>(bk, A11, lda, sh.L);
         __syncthreads();
-        const int bad = chol_lds_core<T, kSub, kBB>((bk + kSub - 1) / kSub * kSub, sh.L, sh.Pt, sh.rinv, &sh.s_bad);
+        const int bad = chol_lds_core2<T, kBB>(bk, sh.L, &sh.s_bad, A11, lda);
         if (bad != 0) return k0 + bad;
-        chol_lds_store<T>(bk, A11, lda, sh.L);
         __syncthreads();  // U11 in memory for every wavefront; L free again
         if (m == 0) break;
         // TRSM: A12 := U11^{-T} A12 (bk == kBB here)
         T *A12 = A + k0 + (int64_t)(k0 + kBB) * lda;
-        trsm_inverses<T, kBB / 16>(kBB, A11, lda, sh.Ds);
+        trsm_inverses<T, kBB / 16, true>(kBB, A11, lda, sh.t.Ds);
         __syncthreads();
         for (int c0 = 16 * wave; c0 < m; c0 += 64) {
             // keeps the U11 loads inside the loop (hoisted, they would not fit
             // in registers)
             asm volatile("" ::: "memory");
-            trsm_cols<T, kBB / 16>(kBB, m, A11, lda, A12, lda, c0, sh.Ds, sh.Rt[wave]);
+            trsm_cols<T, kBB / 16, true>(kBB, m, A11, lda, A12, lda, c0, sh.t.Ds, sh.t.Rt[wave]);
         }
         __syncthreads();
         // SYRK: A22 -= A12^T A12 (upper)

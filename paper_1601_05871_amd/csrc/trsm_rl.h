@@ -58,9 +58,14 @@ __device__ __forceinline__ f4v mma_rc(float rowop, float colop, f4v acc) {
 // loads (eight per thread, all issued before the LDS stores), then each of
 // NB * 16 threads solves one column U_ss D(:, t) = e_t by back substitution
 // from LDS into registers, and the columns replace the blocks in Ds.
-template <typename T, int NB>
+// Opaque (for callers inside a loop, like the batched kernel): the lane
+// indices are hidden from the compiler, so that the addresses and the unit
+// vectors are formed at each call, not hoisted out of the caller's loop into
+// registers that stay live (and spill) across it.
+template <typename T, int NB, bool Opaque = false>
 __device__ __forceinline__ void trsm_inverses(int b, const T *__restrict__ U, int64_t ldu, T (*Ds)[16][17]) {
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    if constexpr (Opaque) asm volatile("" : "+v"(tid));
     constexpr int PER = (NB * 256 + 255) / 256;
     T v[PER];
 #pragma unroll
@@ -81,7 +86,9 @@ __device__ __forceinline__ void trsm_inverses(int b, const T *__restrict__ U, in
     }
     __syncthreads();
     T d[16];
-    const int sb = tid >> 4, t = tid & 15;  // column t of D_sb
+    const int sb = tid >> 4;
+    int t = tid & 15;  // column t of D_sb
+    if constexpr (Opaque) asm volatile("" : "+v"(t));
     if (sb < NB) {
 #pragma unroll
         for (int i = 15; i >= 0; --i) {
@@ -101,14 +108,15 @@ __device__ __forceinline__ void trsm_inverses(int b, const T *__restrict__ U, in
 // (2) One wavefront solves the 16 columns c0 .. c0 + 15 of X (b x m; columns
 // >= m are skipped) with the inverses in Ds; Rt: this wavefront's 16 x 17
 // LDS scratch.
-template <typename T, int NB>
+template <typename T, int NB, bool Opaque = false>
 __device__ __forceinline__ void trsm_cols(int b, int64_t m, const T *__restrict__ U, int64_t ldu,
                                           T *__restrict__ X, int64_t ldx, int64_t c0, T (*Ds)[16][17],
                                           T (*Rt)[17]) {
     typedef typename TrsmAcc<T>::type acc_t;
     constexpr bool F64 = sizeof(T) == 8;
     const int lane = threadIdx.x & 63;
-    const int r = lane & 15;
+    int r = lane & 15;
+    if constexpr (Opaque) asm volatile("" : "+v"(r));
     const int g = lane >> 4;
     const int nblk = (b + 15) >> 4;
     // (2) right-looking solve of this wavefront's 16 columns.  Accumulator
