@@ -235,6 +235,26 @@ def test_factor_breakdown_info(variant, bad):
     assert int(info.item()) == bad + 1
 
 
+def test_factor_after_breakdown_leaves_no_state():
+    """Nothing a failed call leaves behind (its launches after the breakdown
+    turn into no-ops on both streams of lookahead 2) may affect the next
+    calls: an early breakdown, then two good factorizations of other orders,
+    each equal to the oracle's factor."""
+    A = inputs.spd_bbt(1500, 7)
+    A[100, 100] = -1.0
+    Ad = to_dev(A)
+    assert int(fl.factor(Ad, variant=3, nb=128).item()) == 101
+    for n, seed in ((1300, 8), (2100, 9)):
+        A = inputs.spd_bbt(n, seed)
+        Uo, io = oracle.potrf(A, threads=8)
+        Ad = to_dev(A)
+        info = fl.factor(Ad, variant=3, nb=128)
+        Ug = to_host(Ad)
+        assert int(info.item()) == io == 0
+        assert _rel_max(Ug, Uo) <= TOL_PAR64
+        assert oracle.factor_backward_error(A, Ug) <= TOL_BETA64
+
+
 def test_factor_nan_info():
     n = 300
     A = inputs.spd_bbt(n, 5)
