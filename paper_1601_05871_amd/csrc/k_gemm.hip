@@ -367,10 +367,20 @@ __global__ __launch_bounds__(256, 1) void k_gemm_tn(GemmP p) {
 // Per k-chunk the workgroup stages the 128 columns of X and of Y it needs
 // (128 bytes of each column: 16 FP64, 32 FP32 or 64 BF16 values) in LDS, so
 // each operand element is read from L2 once per workgroup instead of once per
-// wavefront.  Global -> register -> LDS copies of chunk c + 1 overlap the
-// MFMAs of chunk c (two LDS buffers, one barrier per chunk).  Each column's
-// eight 16-byte units are stored XOR-swizzled by (column mod 8) so that the
-// 16 lanes reading one unit of 16 consecutive columns hit different banks.
+// wavefront.  The copies go from global memory straight into LDS
+// (global_load_lds_dwordx4: 16 bytes per lane, no registers in between), and
+// those of chunk c + 1 overlap the MFMAs of chunk c (two LDS buffers, one
+// barrier per chunk).  Each column's eight 16-byte units are stored
+// XOR-swizzled by (column mod 8) so that the 16 lanes reading one unit of 16
+// consecutive columns hit different banks.  (Against copies staged through
+// registers: n = 16384 FP64 factorization 32.0 -> 30.6 ms; the 32 registers
+// the staging held had left the fragment reads of each chunk one at a time.)
+
+// 16 bytes per lane from global memory straight into LDS: lane l's bytes land
+// at lds + 16 l (lds wavefront-uniform).
+__device__ __forceinline__ void copy16_to_lds(const char *g, char *lds) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
 
 __device__ __forceinline__ int slab_off(int col, int unit) { return col * 128 + ((unit ^ (col & 7)) << 4); }
 
@@ -420,22 +430,21 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
     const char *__restrict__ Yb = static_cast<const char *>(p.Y) + kbeg * (int64_t)sizeof(in_t);
     const int64_t ldxb = p.ldx * (int64_t)sizeof(in_t), ldyb = p.ldy * (int64_t)sizeof(in_t);
 
-    // copy assignment: thread tid moves units q = tid + 256 j (j < 2 NJ) of the
-    // 2 x 8 TM units of a chunk.  Unit q belongs to operand q / (8 TM) (j / NJ),
-    // column (q % (8 TM)) / 8 = tid / 8 + 32 (j % NJ), 16-byte unit q % 8 = tid % 8.
-    const int unit = tid & 7;
+    // copy assignment: wavefront w copies columns 8 w + 32 j .. 8 w + 32 j + 7
+    // (j < NJ) of each operand, 1 KB per copy instruction; lane l's 16 bytes
+    // land in slot l % 8 of column 8 w + 32 j + l / 8, so the lane fetches the
+    // unit that the swizzle puts there: unit (l % 8) ^ (l / 8).
+    const int unit = (tid & 7) ^ ((tid >> 3) & 7);
     const int ccol0 = tid >> 3;
     const int64_t chunk_bytes = CK * (int64_t)sizeof(in_t);  // 128
     const int64_t nch = K / CK;
-    // byte offsets (from Xb / Yb) of this thread's NJ columns of each operand
+    // byte offsets (from Xb / Yb) of this lane's NJ units of each operand
     int64_t xoff[NJ], yoff[NJ];
-    int dofs[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const int col = ccol0 + 32 * j;
         xoff[j] = min(tr0 + col, M - 1) * ldxb + unit * 16;
         yoff[j] = min(tc0 + col, N - 1) * ldyb + unit * 16;
-        dofs[j] = slab_off(col, unit);
     }
 
     // C element of accumulator item v of block (a, b) (see mfma_frag)
@@ -465,22 +474,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
     }
 
     const int xr = (wave >> 1) * WT + r, yr = (wave & 1) * WT + r;
-    u32x4 stx[NJ], sty[NJ];
 
-#define FLAME_FETCH1(j, cidx)                                                                         \
-    stx[j] = *reinterpret_cast<const u32x4 *>(Xb + xoff[j] + (cidx) * chunk_bytes);                   \
-    sty[j] = *reinterpret_cast<const u32x4 *>(Yb + yoff[j] + (cidx) * chunk_bytes);
-#define FLAME_FETCH(cidx)                                                                             \
-    {                                                                                                 \
-        _Pragma("unroll") for (int j_ = 0; j_ < NJ; ++j_) { FLAME_FETCH1(j_, cidx) }                  \
-    }
-#define FLAME_PUT1(j, buf)                                                                            \
-    *reinterpret_cast<u32x4 *>(&lds[buf][0][0] + dofs[j]) = stx[j];                                   \
-    *reinterpret_cast<u32x4 *>(&lds[buf][1][0] + dofs[j]) = sty[j];
-#define FLAME_PUT(buf)                                                                                \
-    {                                                                                                 \
-        _Pragma("unroll") for (int j_ = 0; j_ < NJ; ++j_) { FLAME_PUT1(j_, buf) }                     \
-    }
 // One chunk from LDS buffer `buf`: the two 16-byte halves of each lane's
 // fragments are read and multiplied in turn (half the operand registers).
 #define FLAME_COMPUTE(buf)                                                                            \
@@ -500,24 +494,28 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmP p) {
         }                                                                                             \
     }
 
-    FLAME_FETCH(0)
-    FLAME_PUT(0)
+    // the wait for this wavefront's copies of chunk c + 1 and the barrier
+    // come after the MFMAs of chunk c; the copies are unconditional (an
+    // inactive wavefront's product is discarded)
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+#define FLAME_COPY(cidx, buf)                                                                             \
+    {                                                                                                     \
+        _Pragma("unroll") for (int j_ = 0; j_ < NJ; ++j_) {                                               \
+            copy16_to_lds(Xb + xoff[j_] + (cidx) * chunk_bytes, &lds[buf][0][0] + (8 * wv + 32 * j_) * 128); \
+            copy16_to_lds(Yb + yoff[j_] + (cidx) * chunk_bytes, &lds[buf][1][0] + (8 * wv + 32 * j_) * 128); \
+        }                                                                                                 \
+    }
+    FLAME_COPY(0, 0)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     int64_t c = 0;
     for (; c + 1 < nch; ++c) {
-        FLAME_FETCH(c + 1)
-        // unconditional (no branch between the loads and the MFMAs, so the
-        // loads stay ahead of them); an inactive wave's product is discarded
+        FLAME_COPY(c + 1, (int)((c + 1) & 1))
         FLAME_COMPUTE((int)(c & 1))
-        // keep the LDS writes (which wait for the loads) behind the MFMAs
-        __builtin_amdgcn_sched_barrier(0);
-        FLAME_PUT((int)((c + 1) & 1))
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
-#undef FLAME_FETCH
-#undef FLAME_FETCH1
-#undef FLAME_PUT
-#undef FLAME_PUT1
+#undef FLAME_COPY
 
     FLAME_COMPUTE((int)(c & 1))
     if (active) {
