@@ -42,6 +42,7 @@ extern "C" {
 #define FLAME_ERR_NOMEM 2         /* device workspace allocation failed */
 #define FLAME_ERR_NOT_CONVERGED 3 /* refinement reached max_iter above tol */
 #define FLAME_ERR_UNSUPPORTED 4   /* valid but unsupported combination */
+#define FLAME_ERR_BREAKDOWN 5     /* flame_solve_mixed: no factorization attempt succeeded */
 
 /* ---- enumerations ------------------------------------------------------- */
 typedef enum { FLAME_F64 = 0, FLAME_F32 = 1 } flame_dtype_t;
@@ -72,8 +73,9 @@ typedef enum { FLAME_TRAIL_NATIVE = 0, FLAME_TRAIL_F32 = 1, FLAME_TRAIL_BF16 = 2
 typedef struct {
     int32_t variant;   /* flame_variant_t; 0 = choose */
     int32_t nb;        /* block size b (A11 is b x b, the last block min(b, n-k));
-                          0 = choose (selector, else 256); valid range 1..512.
-                          RIGHT with lookahead: the last 8192 columns use
+                          0 = choose (selector, else 512); valid range 1..512.
+                          RIGHT with lookahead, unless flags has
+                          FLAME_OPT_FIXED_NB: the last 8192 columns use
                           min(b, 256) and the last 6144 (4096 with FP32/BF16
                           trailing products) min(b, 128) */
     int32_t trail;     /* flame_trail_t */
@@ -87,8 +89,13 @@ typedef struct {
     int32_t graph;     /* 0 = default (off), 1 = capture the loop once per
                           (n, lda, A, info, options, stream) in a HIP graph and
                           replay it on later calls with the same key */
-    int32_t reserved[3]; /* must be 0 */
+    int32_t flags;     /* bit set of FLAME_OPT_* (0 = none) */
+    int32_t reserved[2]; /* must be 0 */
 } flame_opts_t;
+
+/* opts.flags: FLAME_OPT_FIXED_NB runs every block of the RIGHT loop at
+ * min(nb, n - k), without the smaller blocks of the last columns. */
+#define FLAME_OPT_FIXED_NB 1
 
 /* ---- factorization ------------------------------------------------------ */
 
@@ -108,36 +115,92 @@ int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opt
 
 /* ---- solve and iterative refinement ----------------------------------- */
 
+/* Refinement methods (flame_refine_t.method).  The paper uses the factor to
+ * solve SPD systems, as a preconditioner; how a low-precision factor is
+ * corrected is not in the paper.  All three run in FP64 on the device.
+ *   IR   classical iterative refinement: x += (U^T U)^{-1} (b - A0 x); converges
+ *        while kappa(A0) times the factor's working precision is well below 1.
+ *   CG   conjugate gradients on A0 x = b preconditioned by M = U^T U, from the
+ *        current x; when the recursive residual's eta reaches tol the true
+ *        residual b - A0 x is formed, and the iteration restarts from it if its
+ *        eta is still above tol.
+ *   AUTO IR while eta at least halves per step, then CG from the current x. */
+#define FLAME_REFINE_IR 0
+#define FLAME_REFINE_CG 1
+#define FLAME_REFINE_AUTO 2
+
 typedef struct {
     const double *A0; /* device, the original FP64 matrix (upper triangle read), lda0 x n */
     int64_t lda0;     /* >= max(1, n) */
     double tol;       /* stop when eta <= tol (e.g. 1e-13) */
-    int32_t max_iter; /* correction steps allowed (>= 0) */
-    int32_t reserved;
+    int32_t max_iter; /* refinement steps allowed (IR corrections + CG iterations), >= 0 */
+    int32_t method;   /* FLAME_REFINE_* */
 } flame_refine_t;
 
 typedef struct {
-    int32_t iters;  /* correction steps taken */
-    int32_t reserved;
-    double eta_max; /* final normwise backward error, max over the columns:
-                       ||b - A0 x||_inf / (||A0||_inf ||x||_inf + ||b||_inf) */
+    int32_t iters;       /* refinement steps taken */
+    int32_t method;      /* FLAME_REFINE_IR or FLAME_REFINE_CG: the method of the last step */
+    double eta_max;      /* final normwise backward error, max over the columns:
+                            ||b - A0 x||_inf / (||A0||_inf ||x||_inf + ||b||_inf) */
+    double shift;        /* flame_solve_mixed: the shift mu of the factorization used (0 = none) */
+    int32_t factor_info; /* flame_solve_mixed: info of the last factorization attempt */
+    int32_t attempts;    /* flame_solve_mixed: factorizations run (1 + shifted retries) */
 } flame_solve_report_t;
 
 /* Solves A X = B with A = U^T U from flame_factor: U^T Y = B, then U X = Y.
+ * The paper is silent on the solve: this is the use of the factor it names
+ * (solving SPD systems), written as two triangular solves.
  *   dtype  FLAME_F64 or FLAME_F32 (U and B of that type); refinement needs F64
- *   n      order, >= 0;  nrhs  number of right-hand sides, >= 0
+ *   n      order, >= 0;  nrhs  number of right-hand sides, 0 <= nrhs <= 524280
  *   U      device, the factor (upper triangle), ldu x n
  *   B      device, n x nrhs, ldb >= max(1, n); overwritten with X
- *   refine host, NULL = one plain solve.  Otherwise: x = solve(U, b); then
- *          repeat { r = b - A0 x (FP64); eta = ...; stop if eta <= tol;
- *          d = solve(U, r); x = x + d } at most max_iter corrections.  Each
+ *   refine host, NULL = one plain solve.  Otherwise x = solve(U, b), then the
+ *          method's steps against A0 until eta <= tol or max_iter steps.  Each
  *          step reads eta back to the host, so this call synchronizes the
  *          stream.  Returns FLAME_ERR_NOT_CONVERGED (X holds the last iterate,
- *          report the last eta) if eta > tol after max_iter corrections.
+ *          report the last eta) if eta > tol after max_iter steps.
  *   report host, may be NULL; filled when refine is given.
- * Errors: -1 dtype, -2 n, -3 nrhs, -4 U, -5 ldu, -6 B, -7 ldb, -8 refine. */
+ * Errors: -1 dtype, -2 n, -3 nrhs, -4 U, -5 ldu, -6 B, -7 ldb, -8 refine;
+ * FLAME_ERR_UNSUPPORTED for refinement with dtype F32. */
 int flame_solve(int32_t dtype, int64_t n, int64_t nrhs, const void *U, int64_t ldu, void *B, int64_t ldb,
                 const flame_refine_t *refine, flame_solve_report_t *report, void *stream);
+
+/* Options of flame_solve_mixed. */
+typedef struct {
+    int32_t trail;      /* flame_trail_t of the factorization (F32 or BF16; NATIVE = FP64) */
+    int32_t nb;         /* block size (0 = default) */
+    int32_t method;     /* refinement method, FLAME_REFINE_* */
+    int32_t max_iter;   /* refinement steps allowed */
+    double tol;         /* target eta, e.g. 1e-13 */
+    int32_t scale;      /* 1: factor D A0 D, D = diag(A0)^{-1/2} (unit diagonal); 0: A0 */
+    int32_t max_shifts; /* retries after a breakdown, each with a larger shift (0..64) */
+    double shift;       /* first shift mu added to the (scaled) diagonal; 0 = 2 u_trail */
+    int32_t reserved;   /* must be 0 */
+    int32_t reserved2;
+} flame_mixed_opts_t;
+
+/* Solves A0 X = B to FP64 backward error with a low-precision factor (the
+ * mixed-precision use of Fig. "dense-chol"; the paper is silent on mixed
+ * precision).  Steps, all on the device:
+ *   1. D = diag(A0)^{-1/2} (scale = 1) or D = I;
+ *   2. W := D A0 D + mu I (upper triangle; mu = 0 first), W := Chol(W) with
+ *      flame_factor (RIGHT, opts.trail); on breakdown retry with mu = shift,
+ *      then 4x larger each time, at most max_shifts retries (the scaling and
+ *      shift of Higham & Pranesh for low-precision SPD factorizations);
+ *   3. W := W D^{-1}, a factor of A0 + mu D^{-2};
+ *   4. X from flame_solve with refinement against A0 (method, tol, max_iter).
+ *   n, nrhs   order and right-hand sides (>= 0)
+ *   A0        device, FP64, lda0 x n, upper triangle read, never written
+ *   W         device, FP64, ldw x n: receives the factor (upper triangle)
+ *   B         device, n x nrhs, ldb: in the right-hand sides, out X
+ *   opts      host, required;  report  host, may be NULL
+ * Synchronizes the stream (info and eta are read back).  Returns
+ * FLAME_ERR_BREAKDOWN if A0 has a diagonal entry that is not positive or every
+ * attempt broke down (report->factor_info holds the column),
+ * FLAME_ERR_NOT_CONVERGED as flame_solve.
+ * Errors: -1 n, -2 nrhs, -3 A0, -4 lda0, -5 W, -6 ldw, -7 B, -8 ldb, -9 opts. */
+int flame_solve_mixed(int64_t n, int64_t nrhs, const double *A0, int64_t lda0, double *W, int64_t ldw, double *B,
+                      int64_t ldb, const flame_mixed_opts_t *opts, flame_solve_report_t *report, void *stream);
 
 /* ---- batched factorization ---------------------------------------------- */
 
@@ -240,6 +303,15 @@ int flame_trace_enable(int32_t on);
  * arrays of FLAME_KC_COUNT entries each; any may be NULL).
  * Errors: FLAME_ERR_HIP if an event query fails. */
 int flame_trace_collect(int64_t *launches, double *ms, double *flops, double *bytes);
+
+/* ---- teardown -------------------------------------------------------------- */
+
+/* Waits for every device the library has used, then releases its state there:
+ * cached HIP graphs, streams, events and workspaces.  Call it before the HIP
+ * runtime is torn down (the Python binding registers it with atexit).  Later
+ * calls re-create the state on demand.  Returns FLAME_ERR_HIP if a device
+ * could not be synchronized (the state is released anyway). */
+int flame_shutdown(void);
 
 /* ---- status -------------------------------------------------------------- */
 const char *flame_status_string(int status);

@@ -14,6 +14,7 @@ and ``A.stride(1) == lda >= n`` (for a contiguous row-major tensor pass
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -21,9 +22,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libflame.so")
 
 F64, F32 = 0, 1
+OPT_FIXED_NB = 1
 VAR_AUTO, VAR_BORDERED, VAR_LEFT, VAR_RIGHT = 0, 1, 2, 3
 TRAIL = {"native": 0, "f32": 1, "bf16": 2}
 FLAME_OK, FLAME_ERR_HIP, FLAME_ERR_NOMEM, FLAME_ERR_NOT_CONVERGED, FLAME_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+FLAME_ERR_BREAKDOWN = 5
+REFINE = {"ir": 0, "cg": 1, "auto": 2}
 
 SEL_FEATURES, SEL_HIDDEN, SEL_CLASSES = 5, 64, 12
 SEL_NPARAM = 64 * 5 + 64 + 64 * 64 + 64 + 12 * 64 + 12
@@ -33,6 +37,7 @@ EXPORTS = (
     "flame_factor", "flame_solve", "flame_batched_factor", "flame_op_chol", "flame_op_trsm",
     "flame_op_gemm_tn", "flame_selector_load", "flame_select", "flame_select_logits", "flame_autotune",
     "flame_trace_enable", "flame_trace_collect", "flame_status_string", "flame_version",
+    "flame_solve_mixed", "flame_shutdown",
 )
 KC_CHOL, KC_TRSM, KC_GEMM, KC_OTHER = 0, 1, 2, 3
 
@@ -45,16 +50,25 @@ class FlameError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("nb", ctypes.c_int32), ("trail", ctypes.c_int32),
-                ("lookahead", ctypes.c_int32), ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("lookahead", ctypes.c_int32), ("graph", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Refine(ctypes.Structure):
     _fields_ = [("A0", ctypes.c_void_p), ("lda0", ctypes.c_int64), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class SolveReport(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int32), ("reserved", ctypes.c_int32), ("eta_max", ctypes.c_double)]
+    _fields_ = [("iters", ctypes.c_int32), ("method", ctypes.c_int32), ("eta_max", ctypes.c_double),
+                ("shift", ctypes.c_double), ("factor_info", ctypes.c_int32), ("attempts", ctypes.c_int32)]
+
+
+class MixedOpts(ctypes.Structure):
+    _fields_ = [("trail", ctypes.c_int32), ("nb", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("scale", ctypes.c_int32),
+                ("max_shifts", ctypes.c_int32), ("shift", ctypes.c_double), ("reserved", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
 
 _lib = None
@@ -83,6 +97,9 @@ def lib() -> ctypes.CDLL:
     L.flame_autotune.argtypes = [i32, i64, vp, i64, i32, vp, vp]
     L.flame_trace_enable.argtypes = [i32]
     L.flame_trace_collect.argtypes = [vp, vp, vp, vp]
+    L.flame_solve_mixed.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, ctypes.POINTER(MixedOpts),
+                                    ctypes.POINTER(SolveReport), vp]
+    L.flame_shutdown.argtypes = []
     L.flame_status_string.argtypes = [ctypes.c_int]
     L.flame_status_string.restype = ctypes.c_char_p
     L.flame_version.argtypes = []
@@ -91,7 +108,16 @@ def lib() -> ctypes.CDLL:
         if name not in ("flame_status_string", "flame_version"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
+    # release graphs, streams and workspaces while the HIP runtime is still up
+    # (atexit handlers run before the interpreter tears torch down)
+    atexit.register(L.flame_shutdown)
     return L
+
+
+def shutdown() -> None:
+    """Waits for the devices and releases the library's cached graphs,
+    streams, events and workspaces (re-created on the next call)."""
+    _check("flame_shutdown", lib().flame_shutdown())
 
 
 def status_string(status: int) -> str:
@@ -147,46 +173,78 @@ def colmajor(t):
     return t.mT.contiguous().mT
 
 
-def _opts(variant, nb, trail, lookahead, graph) -> Opts:
+def _opts(variant, nb, trail, lookahead, graph, fixed_nb=False) -> Opts:
     o = Opts()
     o.variant = int(variant)
     o.nb = int(nb)
     o.trail = TRAIL[trail] if isinstance(trail, str) else int(trail)
     o.lookahead = int(lookahead)
     o.graph = int(graph)
+    o.flags = OPT_FIXED_NB if fixed_nb else 0
     return o
 
 
 def factor(A, variant: int = VAR_RIGHT, nb: int = 128, trail="native", lookahead: int = 0, graph: int = 0,
-           info=None):
+           info=None, fixed_nb: bool = False):
     """A := Chol(A) in place (upper triangle).  Returns the device int32
     ``info`` tensor (0, or the 1-based column of the first non-positive pivot).
-    Asynchronous on the current stream."""
+    Asynchronous on the current stream.  ``fixed_nb``: the right-looking loop
+    runs every block at ``nb`` (no smaller blocks in the last columns)."""
     torch = _torch()
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a square 2-D tensor")
     n = A.shape[0]
-    if A.shape[1] != n:
-        raise ValueError("A must be square")
     lda = _colmajor_ld(A)
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
-    o = _opts(variant, nb, trail, lookahead, graph)
+    elif info.dtype != torch.int32 or info.numel() < 1 or not info.is_cuda:
+        raise ValueError("info must be a device int32 tensor with at least one element")
+    o = _opts(variant, nb, trail, lookahead, graph, fixed_nb)
     rc = lib().flame_factor(_dtype_code(A), n, A.data_ptr(), lda, ctypes.byref(o), info.data_ptr(), _stream_ptr())
     _check("flame_factor", rc)
     return info
 
 
-def solve(U, B, A0=None, tol: float = 1e-13, max_iter: int = 30):
+def _report(rep: SolveReport, rc: int) -> dict:
+    return {"iters": rep.iters, "eta": rep.eta_max, "status": rc,
+            "method": {v: k for k, v in REFINE.items()}.get(rep.method, rep.method),
+            "shift": rep.shift, "factor_info": rep.factor_info, "attempts": rep.attempts}
+
+
+def _square(name: str, t) -> int:
+    if t.dim() != 2 or t.shape[0] != t.shape[1]:
+        raise ValueError(f"{name} must be a square 2-D tensor")
+    return int(t.shape[0])
+
+
+def _rows(name: str, t, n: int) -> int:
+    if t.dim() != 2 or t.shape[0] != n:
+        raise ValueError(f"{name} must be a 2-D tensor with {n} rows")
+    return int(t.shape[1])
+
+
+def solve(U, B, A0=None, tol: float = 1e-13, max_iter: int = 30, method: str = "ir"):
     """Solves A X = B in place on B (column-major, n x nrhs) with A = U^T U.
-    With ``A0`` (the original FP64 matrix) runs FP64 iterative refinement and
-    returns the report (iters, eta_max) and the status; otherwise returns
-    None.  Refinement synchronizes the stream."""
-    n = U.shape[0]
-    nrhs = B.shape[1]
+    With ``A0`` (the original FP64 matrix) refines in FP64 with ``method``
+    ('ir', 'cg' or 'auto', see flame.h) and returns the report (iters, eta,
+    status, method); otherwise returns None.  Refinement synchronizes the
+    stream."""
+    torch = _torch()
+    n = _square("U", U)
+    nrhs = _rows("B", B, n)
+    if B.dtype != U.dtype:
+        raise TypeError("U and B must have the same dtype")
+    if A0 is not None:
+        _square("A0", A0)
+        if A0.shape[0] != n:
+            raise ValueError("A0 must be n x n")
+        if A0.dtype != torch.float64 or U.dtype != torch.float64:
+            raise TypeError("refinement needs float64 U, B and A0")
+        if method not in REFINE:
+            raise ValueError(f"method must be one of {sorted(REFINE)}")
     ldu = _colmajor_ld(U)
     ldb = _colmajor_ld(B)
     dt = _dtype_code(U)
-    if B.dtype != U.dtype:
-        raise TypeError("U and B must have the same dtype")
     if A0 is None:
         rc = lib().flame_solve(dt, n, nrhs, U.data_ptr(), ldu, B.data_ptr(), ldb, None, None, _stream_ptr())
         _check("flame_solve", rc)
@@ -196,11 +254,49 @@ def solve(U, B, A0=None, tol: float = 1e-13, max_iter: int = 30):
     ref.lda0 = _colmajor_ld(A0)
     ref.tol = float(tol)
     ref.max_iter = int(max_iter)
+    ref.method = REFINE[method]
     rep = SolveReport()
     rc = lib().flame_solve(dt, n, nrhs, U.data_ptr(), ldu, B.data_ptr(), ldb, ctypes.byref(ref), ctypes.byref(rep),
                            _stream_ptr())
     _check("flame_solve", rc, ok=(FLAME_OK, FLAME_ERR_NOT_CONVERGED))
-    return {"iters": rep.iters, "eta": rep.eta_max, "status": rc}
+    return _report(rep, rc)
+
+
+def solve_mixed(A0, B, W=None, trail="bf16", nb: int = 0, tol: float = 1e-13, max_iter: int = 1000,
+                method: str = "auto", scale: bool = True, max_shifts: int = 8, shift: float = 0.0):
+    """Solves A0 X = B (in place on B) to FP64 backward error ``tol`` with a
+    factor computed with ``trail`` trailing products (flame_solve_mixed):
+    unit-diagonal scaling, shifted retries on breakdown, FP64 refinement.
+    ``W`` (n x n float64, column-major) receives the factor; allocated when
+    None.  Returns the report dict; raises on argument errors and on a
+    breakdown of every attempt (FlameError with status FLAME_ERR_BREAKDOWN)."""
+    torch = _torch()
+    n = _square("A0", A0)
+    nrhs = _rows("B", B, n)
+    if A0.dtype != torch.float64 or B.dtype != torch.float64:
+        raise TypeError("A0 and B must be float64")
+    if W is None:
+        W = torch.empty((n, n), dtype=torch.float64, device=A0.device).mT
+    elif _square("W", W) != n or W.dtype != torch.float64:
+        raise ValueError("W must be an n x n float64 tensor")
+    if method not in REFINE:
+        raise ValueError(f"method must be one of {sorted(REFINE)}")
+    o = MixedOpts()
+    o.trail = TRAIL[trail] if isinstance(trail, str) else int(trail)
+    o.nb = int(nb)
+    o.method = REFINE[method]
+    o.max_iter = int(max_iter)
+    o.tol = float(tol)
+    o.scale = int(bool(scale))
+    o.max_shifts = int(max_shifts)
+    o.shift = float(shift)
+    rep = SolveReport()
+    rc = lib().flame_solve_mixed(n, nrhs, A0.data_ptr(), _colmajor_ld(A0), W.data_ptr(), _colmajor_ld(W),
+                                 B.data_ptr(), _colmajor_ld(B), ctypes.byref(o), ctypes.byref(rep), _stream_ptr())
+    _check("flame_solve_mixed", rc, ok=(FLAME_OK, FLAME_ERR_NOT_CONVERGED))
+    out = _report(rep, rc)
+    out["W"] = W
+    return out
 
 
 def batched_factor(ns, ptrs, ldas, info, dtype=F64, opts: Opts | None = None, graph: int | None = None):
@@ -300,6 +396,10 @@ def op_chol(A, info, info_base: int = 0):
 
 
 def op_trsm(U, X):
+    b = _square("U", U)
+    _rows("X", X, b)
+    if X.dtype != U.dtype:
+        raise TypeError("U and X must have the same dtype")
     rc = lib().flame_op_trsm(_dtype_code(U), X.shape[0], X.shape[1], U.data_ptr(), _colmajor_ld(U), X.data_ptr(),
                              _colmajor_ld(X), _stream_ptr())
     _check("flame_op_trsm", rc)
@@ -309,7 +409,13 @@ def op_gemm_tn(C, X, Y, upper: bool, trail="native", dtype=None):
     """C := C - X^T Y (upper triangle only if ``upper``).  For trail 'f32' /
     'bf16' X and Y are float32 / bfloat16 tensors and C is float64."""
     torch = _torch()
+    if X.dim() != 2 or Y.dim() != 2 or C.dim() != 2:
+        raise ValueError("C, X and Y must be 2-D tensors")
     k = X.shape[0]
+    if Y.shape[0] != k:
+        raise ValueError("X and Y must have the same number of rows (the inner dimension)")
+    if C.shape[0] != X.shape[1] or C.shape[1] != Y.shape[1]:
+        raise ValueError("C must be X.shape[1] x Y.shape[1]")
     if dtype is None:
         dtype = F32 if (C.dtype == torch.float32) else F64
     tr = TRAIL[trail] if isinstance(trail, str) else int(trail)

@@ -11,6 +11,10 @@ namespace {
 
 constexpr int kMaxNb = 512;     // block size of the factorization loops
 constexpr int kMaxBlockOp = 256;  // order of the exposed block operations
+// Block size when neither the caller nor the selector names one: the RIGHT
+// loop then runs 512 while more than 8192 columns remain, 256 down to 6144
+// and 128 in the tail (the schedule measured fastest at n = 16384).
+constexpr int kDefaultNb = 512;
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
@@ -25,14 +29,15 @@ int normalize_opts(const flame_opts_t *in, int32_t dtype, int64_t n, flame_opts_
     if (o->trail < FLAME_TRAIL_NATIVE || o->trail > FLAME_TRAIL_BF16) return -5;
     if (o->lookahead < -1 || o->lookahead > 2) return -5;
     if (o->graph < 0 || o->graph > 1) return -5;
-    if (o->reserved[0] != 0 || o->reserved[1] != 0 || o->reserved[2] != 0) return -5;
+    if ((o->flags & ~FLAME_OPT_FIXED_NB) != 0) return -5;
+    if (o->reserved[0] != 0 || o->reserved[1] != 0) return -5;
     if (o->variant == FLAME_VAR_AUTO) {
         int32_t v = FLAME_VAR_RIGHT, nb = 0;
         choose_variant(dtype, n, 1, &v, &nb);
         o->variant = v;
         if (o->nb == 0) o->nb = nb;
     }
-    if (o->nb == 0) o->nb = 256;
+    if (o->nb == 0) o->nb = kDefaultNb;
     return 0;
 }
 
@@ -124,6 +129,8 @@ const char *flame_status_string(int status) {
             return "iterative refinement did not reach the tolerance";
         case FLAME_ERR_UNSUPPORTED:
             return "unsupported combination of arguments";
+        case FLAME_ERR_BREAKDOWN:
+            return "the factorization broke down (not positive definite at the precision used)";
         default:
             return "unknown status";
     }

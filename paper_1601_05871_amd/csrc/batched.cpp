@@ -22,6 +22,14 @@ int run_batched(int32_t dtype, int32_t batch, const int32_t *n, void *const *A, 
 
 }  // namespace
 
+namespace flame {
+void drop_batched_graphs() {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    for (auto &kv : g_bgraphs) (void)hipGraphExecDestroy(kv.second);
+    g_bgraphs.clear();
+}
+}  // namespace flame
+
 extern "C" int flame_batched_factor(int32_t dtype, int32_t batch, const int32_t *n, void *const *A,
                                     const int32_t *lda, int32_t *info, const flame_opts_t *opts, void *stream) {
     if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;

@@ -19,6 +19,7 @@ struct DevCtx {
     std::vector<hipEvent_t> events;
     void *ws[kWsSlots] = {};
     size_t ws_bytes[kWsSlots] = {};
+    uint64_t ws_gen[kWsSlots] = {};  // bumped whenever a slot's buffer is replaced
     std::mutex mu;
 };
 
@@ -76,9 +77,51 @@ int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out) {
             return FLAME_ERR_NOMEM;
         }
         c->ws_bytes[slot] = want;
+        c->ws_gen[slot] += 1;
     }
     *out = c->ws[slot];
     return FLAME_OK;
 }
 
+uint64_t ctx_workspace_gen(DevCtx *c, int slot) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    return c->ws_gen[slot];
+}
+
+// Releases every device's state: waits for the device, then destroys the
+// cached graphs, streams and events and frees the workspaces.  Contexts are
+// re-created lazily by the next call.
+int shutdown_all() {
+    {
+        // nothing to release (and no HIP call) if no device was ever used
+        std::lock_guard<std::mutex> lk(g_mu);
+        bool any = false;
+        for (DevCtx *c : g_ctx) any = any || (c != nullptr);
+        if (!any) return FLAME_OK;
+    }
+    int rc = FLAME_OK;
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    drop_factor_graphs();
+    drop_batched_graphs();
+    selector_forget_devices();
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (DevCtx *c : g_ctx) {
+        if (c == nullptr) continue;
+        if (hipSetDevice(c->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) rc = FLAME_ERR_HIP;
+        for (auto &e : c->events)
+            if (e) (void)hipEventDestroy(e);
+        if (c->side) (void)hipStreamDestroy(c->side);
+        if (c->aux) (void)hipStreamDestroy(c->aux);
+        for (int k = 0; k < kWsSlots; ++k)
+            if (c->ws[k]) (void)hipFree(c->ws[k]);
+        delete c;
+    }
+    g_ctx.clear();
+    if (have_cur) (void)hipSetDevice(cur);
+    return rc;
+}
+
 }  // namespace flame
+
+extern "C" int flame_shutdown(void) { return flame::shutdown_all(); }

@@ -91,8 +91,8 @@ int gemm_tallk(bool upper, int64_t M, int64_t N, int64_t K, const T *X, int64_t 
 
 // ---- right-looking (the paper's loop) ------------------------------------
 template <typename T>
-int factor_right(int64_t n, T *A, int64_t lda, int nb, int lookahead, flame_trail_t trail, int32_t *info,
-                 hipStream_t s) {
+int factor_right(int64_t n, T *A, int64_t lda, int nb, int lookahead, flame_trail_t trail, bool fixed_nb,
+                 int32_t *info, hipStream_t s) {
     const bool rest_on_side = (lookahead == 2 || lookahead == 0);
     Views<T> V{A, lda};
     int rc;
@@ -162,6 +162,7 @@ int factor_right(int64_t n, T *A, int64_t lda, int nb, int lookahead, flame_trai
     // and costs less per column at the smaller block).
     const int64_t tail_n = mixed ? kTailNMixed : kTailN;
     auto nb_at = [&](int64_t k) -> int64_t {
+        if (fixed_nb) return nb;
         const int64_t rest = n - k;
         if (rest <= tail_n) return std::min<int64_t>(nb, kTailNb);
         if (rest <= kMidN) return std::min<int64_t>(nb, kMidNb);
@@ -305,7 +306,8 @@ int factor_t(int64_t n, T *A, int64_t lda, const flame_opts_t &o, int32_t *info,
     const int nb = o.nb;
     switch (o.variant) {
         case FLAME_VAR_RIGHT:
-            return factor_right<T>(n, A, lda, nb, o.lookahead, (flame_trail_t)o.trail, info, s);
+            return factor_right<T>(n, A, lda, nb, o.lookahead, (flame_trail_t)o.trail,
+                                   (o.flags & FLAME_OPT_FIXED_NB) != 0, info, s);
         case FLAME_VAR_LEFT:
             return factor_left<T>(n, A, lda, nb, info, s);
         case FLAME_VAR_BORDERED:
@@ -316,11 +318,24 @@ int factor_t(int64_t n, T *A, int64_t lda, const flame_opts_t &o, int32_t *info,
 }
 
 // ---- graph cache -----------------------------------------------------------
-using GraphKey = std::tuple<int, int64_t, void *, int64_t, int32_t *, int, int, int, int, hipStream_t, int>;
+// The key holds every pointer a captured loop uses: the caller's (A, info,
+// stream) and the library workspace the loop reads and writes (the rounded
+// panel of the FP32/BF16 products, the split-K partials) with the generation
+// of that buffer, so a graph is never replayed into a workspace that has been
+// freed and replaced since its capture.
+using GraphKey = std::tuple<int, int64_t, void *, int64_t, int32_t *, int, int, int, int, int, hipStream_t, int,
+                            int, void *, uint64_t>;
+constexpr int kKeyDev = 11, kKeySlot = 12, kKeyGen = 14;
 std::mutex g_graph_mu;
 std::map<GraphKey, hipGraphExec_t> g_graphs;
 
 }  // namespace
+
+void drop_factor_graphs() {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto &kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+}
 
 int factor_dispatch(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opts_t &o, int32_t *info,
                     hipStream_t s) {
@@ -332,7 +347,25 @@ int factor_dispatch(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_
 
     int dev = 0;
     FLAME_HIP(hipGetDevice(&dev));
-    GraphKey key{dtype, n, A, lda, info, o.variant, o.nb, o.trail, o.lookahead, s, dev};
+    // The workspace is allocated (or grown) before the lookup and the capture:
+    // no allocation happens inside a capture, and the key sees the buffer the
+    // loop will use.
+    DevCtx *ctx = ctx_for_current_device();
+    if (ctx == nullptr) return FLAME_ERR_HIP;
+    void *ws = nullptr;
+    int slot = -1;
+    if (o.variant == FLAME_VAR_LEFT || o.variant == FLAME_VAR_BORDERED) {
+        slot = kWsSplit;
+        int rc = ctx_workspace(ctx, slot, splitk_workspace_bytes(), &ws);
+        if (rc) return rc;
+    } else if (o.trail != FLAME_TRAIL_NATIVE) {
+        slot = kWsFactor;
+        const int64_t ldw = ((int64_t)o.nb + 15) / 16 * 16;
+        int rc = ctx_workspace(ctx, slot, (size_t)ldw * (size_t)std::max<int64_t>(n, 1) * 4, &ws);
+        if (rc) return rc;
+    }
+    const uint64_t ws_gen = slot >= 0 ? ctx_workspace_gen(ctx, slot) : 0;
+    GraphKey key{dtype, n, A, lda, info, o.variant, o.nb, o.trail, o.lookahead, o.flags, s, dev, slot, ws, ws_gen};
     {
         std::lock_guard<std::mutex> lk(g_graph_mu);
         auto it = g_graphs.find(key);
@@ -340,20 +373,19 @@ int factor_dispatch(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_
             FLAME_HIP(hipGraphLaunch(it->second, s));
             return FLAME_OK;
         }
-    }
-    // Allocate the workspace before capture (no allocation inside a capture).
-    if (o.variant == FLAME_VAR_LEFT || o.variant == FLAME_VAR_BORDERED) {
-        DevCtx *ctx = ctx_for_current_device();
-        void *w = nullptr;
-        int rc = ctx_workspace(ctx, kWsSplit, splitk_workspace_bytes(), &w);
-        if (rc) return rc;
-    }
-    if (o.trail != FLAME_TRAIL_NATIVE) {
-        DevCtx *ctx = ctx_for_current_device();
-        void *w = nullptr;
-        const int64_t ldw = ((int64_t)o.nb + 15) / 16 * 16;
-        int rc = ctx_workspace(ctx, kWsFactor, (size_t)ldw * (size_t)std::max<int64_t>(n, 1) * 4, &w);
-        if (rc) return rc;
+        // graphs of this device whose workspace has been replaced can never
+        // be replayed again
+        for (auto g = g_graphs.begin(); g != g_graphs.end();) {
+            const int gslot = std::get<kKeySlot>(g->first);
+            const bool stale = std::get<kKeyDev>(g->first) == dev && gslot >= 0 &&
+                               std::get<kKeyGen>(g->first) != ctx_workspace_gen(ctx, gslot);
+            if (stale) {
+                (void)hipGraphExecDestroy(g->second);
+                g = g_graphs.erase(g);
+            } else {
+                ++g;
+            }
+        }
     }
     FLAME_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     int rc = run(s);

@@ -95,7 +95,8 @@ int launch_identity_blocks(int64_t nblk, int bs, double *Dt, hipStream_t s);
 // (cleared here), err: one int set to 1 if a wait gave up.
 int launch_trsv1(bool forward, int64_t n, const double *U, int64_t ldu, const double *Dt, double *x, int32_t *flags,
                  int32_t *err, hipStream_t s);
-// Residual R = B - A0 X (A0 symmetric from its upper triangle), nrhs <= 8,
+// Residual R = B - A0 X (A0 symmetric from its upper triangle; B == nullptr:
+// the product R = A0 X), nrhs <= 8,
 // through per-tile partial sums (deterministic); also rowsums of |A0| when
 // rowsums != nullptr.  part: workspace of tiles^2 * 128 * (nrhs + 1) doubles.
 int launch_residual_tiled(int64_t n, int64_t nrhs, const double *A0, int64_t lda0, const double *X, int64_t ldx,
@@ -112,6 +113,27 @@ int launch_trsv_bwd(int64_t n, int64_t nrhs, const T *U, int64_t ldu, T *B, int6
 int launch_residual(int64_t n, int64_t nrhs, const double *A0, int64_t lda0, const double *X, int64_t ldx,
                     const double *B, int64_t ldb, double *R, int64_t ldr, double *rowsums, bool want_rowsums,
                     hipStream_t s);
+// R := beta B + alpha A0 X (A0 symmetric from its upper triangle; B may be
+// nullptr when beta is unused), any nrhs, with |A0| row sums when rowsums !=
+// nullptr.  Deterministic.
+int launch_symm(int64_t n, int64_t nrhs, double alpha, const double *A0, int64_t lda0, const double *X, int64_t ldx,
+                double beta, const double *B, int64_t ldb, double *R, int64_t ldr, double *rowsums, hipStream_t s);
+// out[c] = X(:, c) . Y(:, c), deterministic.
+int launch_dot_cols(int64_t n, int64_t nrhs, const double *X, int64_t ldx, const double *Y, int64_t ldy, double *out,
+                    hipStream_t s);
+// Conjugate-gradient updates per column: P := Z + (rho / rho_old) P (P := Z
+// when first); X += alpha P, R -= alpha Q with alpha = rho / pq.
+int launch_cg_direction(int64_t n, int64_t nrhs, const double *Z, int64_t ldz, double *P, int64_t ldp,
+                        const double *rho, const double *rho_old, bool first, hipStream_t s);
+int launch_cg_step(int64_t n, int64_t nrhs, double *X, int64_t ldx, double *R, int64_t ldr, const double *P,
+                   int64_t ldp, const double *Q, int64_t ldq, const double *rho, const double *pq, hipStream_t s);
+// Diagonal scaling: d = 1 / sqrt(diag(A0)), *bad = first 1-based column whose
+// diagonal is not > 0 (0x7fffffff if none); W := D A0 D + mu I (upper; d ==
+// nullptr: no scaling); U := U D^{-1} (columns).
+int launch_diag_scale(int64_t n, const double *A0, int64_t lda0, double *d, int32_t *bad, hipStream_t s);
+int launch_scale_copy_upper(int64_t n, const double *A0, int64_t lda0, double *W, int64_t ldw, const double *d,
+                            double mu, hipStream_t s);
+int launch_unscale_cols(int64_t n, double *U, int64_t ldu, const double *d, hipStream_t s);
 int launch_axpy_cols(int64_t n, int64_t nrhs, const double *D, int64_t ldd, double *X, int64_t ldx,
                      hipStream_t s);
 int launch_copy_cols(int64_t n, int64_t nrhs, const double *S, int64_t lds, double *D, int64_t ldd,
@@ -135,8 +157,15 @@ struct DevCtx;
 DevCtx *ctx_for_current_device();
 // Workspace slot `slot` (factor panel, solve, batched, selector) of
 // at least `bytes` (grown under a lock, kept until the process ends).
-enum { kWsFactor = 0, kWsSolve = 1, kWsBatched = 2, kWsSelector = 3, kWsTune = 4, kWsSplit = 5, kWsSlots = 6 };
+enum { kWsFactor = 0, kWsSolve = 1, kWsBatched = 2, kWsSelector = 3, kWsTune = 4, kWsSplit = 5, kWsMixed = 6, kWsSlots = 7 };
 int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out);
+// Generation of a slot's buffer: changes every time ctx_workspace replaces it
+// (a graph that captured the old pointer must not be replayed).
+uint64_t ctx_workspace_gen(DevCtx *c, int slot);
+// Teardown helpers of flame_shutdown: each drops its module's device state.
+void drop_factor_graphs();
+void drop_batched_graphs();
+void selector_forget_devices();
 hipStream_t ctx_side_stream(DevCtx *c);
 hipStream_t ctx_aux_stream(DevCtx *c);
 // Variant and block size for FLAME_VAR_AUTO: the learned selector when its

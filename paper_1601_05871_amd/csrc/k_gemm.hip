@@ -928,6 +928,23 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
     return (uint16_t)(u >> 16);
 }
 
+// FP64 -> BF16, one rounding to nearest even.  (float)x rounds once already,
+// so rounding its result again to BF16 could round twice; instead x is first
+// rounded to odd at FP32 precision (truncated toward zero, last bit set when
+// inexact), which keeps the information the second rounding needs: with
+// FP32's 24 bits >= BF16's 8 + 2, round-to-odd followed by
+// round-to-nearest-even equals a direct round-to-nearest-even (Boldo and
+// Melquiond, "When double rounding is odd").
+__device__ __forceinline__ uint16_t f64_to_bf16_rne(double x) {
+    float f = (float)x;
+    if (!__builtin_isnan(x) && (double)f != x) {
+        uint32_t u = __float_as_uint(f);
+        if (fabs((double)f) > fabs(x)) u -= 1u;  // one FP32 step toward zero (f != 0 here)
+        f = __uint_as_float(u | 1u);
+    }
+    return f32_to_bf16_rne(f);
+}
+
 template <Prec P>
 __global__ void k_round_panel(int64_t rows, int64_t cols, const double *__restrict__ X, int64_t ldx,
                               void *__restrict__ Yv, int64_t ldy, const int32_t *__restrict__ info) {
@@ -938,7 +955,7 @@ __global__ void k_round_panel(int64_t rows, int64_t cols, const double *__restri
         if constexpr (P == Prec::F32) {
             static_cast<float *>(Yv)[i + c * ldy] = (float)v;
         } else {
-            static_cast<uint16_t *>(Yv)[i + c * ldy] = f32_to_bf16_rne((float)v);
+            static_cast<uint16_t *>(Yv)[i + c * ldy] = f64_to_bf16_rne(v);
         }
     }
 }

@@ -88,48 +88,12 @@ template int launch_trsv_bwd<double>(int64_t, int64_t, const double *, int64_t, 
 template int launch_trsv_bwd<float>(int64_t, int64_t, const float *, int64_t, float *, int64_t, hipStream_t);
 
 // ---- residual R = B - A0 X, A0 symmetric from its upper triangle ------------
-// One thread per row i: the row of the symmetric matrix is column i of the
-// upper triangle above the diagonal (rows j < i) followed by row i from the
-// diagonal on (columns j >= i).  Up to kResRhs right-hand sides share one pass
-// over A0 (x(j, c) is wave-uniform and comes in through scalar loads).  Also
-// |A0| row sums for ||A0||_inf.
-constexpr int kResRhs = 8;
-
-__global__ __launch_bounds__(256) void k_residual(int64_t n, int64_t nrhs, const double *__restrict__ A0,
-                                                  int64_t lda0, const double *__restrict__ X, int64_t ldx,
-                                                  const double *__restrict__ B, int64_t ldb, double *__restrict__ R,
-                                                  int64_t ldr, double *__restrict__ rowsums, int want_rowsums) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.y * kResRhs;
-    const int nc = (int)((nrhs - c0) < kResRhs ? (nrhs - c0) : kResRhs);
-    if (i >= n) return;
-    double acc[kResRhs];
-#pragma unroll
-    for (int c = 0; c < kResRhs; ++c) acc[c] = 0.0;
-    double asum = 0.0;
-    const double *coli = A0 + i * lda0;
-    for (int64_t j = 0; j < n; ++j) {
-        const double a = (j < i) ? coli[j] : A0[i + j * lda0];
-        asum += fabs(a);
-#pragma unroll
-        for (int c = 0; c < kResRhs; ++c)
-            if (c < nc) acc[c] += a * X[j + (c0 + c) * ldx];
-    }
-#pragma unroll
-    for (int c = 0; c < kResRhs; ++c)
-        if (c < nc) R[i + (c0 + c) * ldr] = B[i + (c0 + c) * ldb] - acc[c];
-    if (want_rowsums && blockIdx.y == 0) rowsums[i] = asum;
-}
-
+// The row-block symmetric product of k_refine.hip (R = B - A0 X, |A0| row
+// sums with it when asked for).
 int launch_residual(int64_t n, int64_t nrhs, const double *A0, int64_t lda0, const double *X, int64_t ldx,
                     const double *B, int64_t ldb, double *R, int64_t ldr, double *rowsums, bool want_rowsums,
                     hipStream_t s) {
-    if (n <= 0 || nrhs <= 0) return FLAME_OK;
-    const unsigned gy = (unsigned)((nrhs + kResRhs - 1) / kResRhs);
-    hipLaunchKernelGGL(k_residual, dim3((unsigned)((n + 255) / 256), gy), dim3(256), 0, s, n, nrhs, A0, lda0, X, ldx,
-                       B, ldb, R, ldr, rowsums, want_rowsums ? 1 : 0);
-    FLAME_CHECK_LAUNCH();
-    return FLAME_OK;
+    return launch_symm(n, nrhs, -1.0, A0, lda0, X, ldx, 1.0, B, ldb, R, ldr, want_rowsums ? rowsums : nullptr, s);
 }
 
 // eta[c] = ||r_c||_inf / (||A0||_inf ||x_c||_inf + ||b_c||_inf); eta[nrhs] =

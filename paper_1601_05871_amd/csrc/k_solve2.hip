@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256) void k_residual_reduce(int64_t n, int tn, int 
         double y = 0.0;
         for (int J = 0; J < tn; ++J) y += P[(((int64_t)I * tn + J) * nk + k) * kTb + r];
         if (k < nrhs)
-            R[gi + k * ldr] = B[gi + k * ldb] - y;
+            R[gi + k * ldr] = (B != nullptr) ? B[gi + k * ldb] - y : y;
         else if (rowsums != nullptr)
             rowsums[gi] = y;
     }

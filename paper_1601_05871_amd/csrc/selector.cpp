@@ -22,6 +22,7 @@ struct SelState {
     std::mutex mu;
     std::vector<float> weights;  // host copy; empty = not loaded
     std::map<int, bool> on_device;  // device -> weights uploaded to its workspace
+    std::map<int, uint64_t> gen;    // device -> generation of the workspace holding them
     std::map<std::tuple<int32_t, int64_t, int64_t>, std::pair<int32_t, int32_t>> memo;  // (dtype, n, batch)
     std::map<std::pair<int32_t, int64_t>, int32_t> table;  // autotuner: (dtype, n) -> class
 };
@@ -49,17 +50,12 @@ int sel_buffers(int64_t count, float **w, float **feat, float **logits, hipStrea
     FLAME_HIP(hipGetDevice(&dev));
     const size_t need = ((size_t)FLAME_SEL_NPARAM + (size_t)count * (kF + kC)) * sizeof(float);
     void *base = nullptr;
-    void *old = nullptr;
-    {
-        // a grown workspace loses the uploaded weights
-        void *probe = nullptr;
-        int rc0 = ctx_workspace(ctx, kWsSelector, 1, &probe);
-        if (rc0) return rc0;
-        old = probe;
-    }
     int rc = ctx_workspace(ctx, kWsSelector, need, &base);
     if (rc) return rc;
-    if (base != old) g_sel.on_device[dev] = false;
+    // a replaced workspace has lost the uploaded weights
+    const uint64_t gen = ctx_workspace_gen(ctx, kWsSelector);
+    if (g_sel.gen[dev] != gen) g_sel.on_device[dev] = false;
+    g_sel.gen[dev] = gen;
     *s = ctx_aux_stream(ctx);
     *w = static_cast<float *>(base);
     *feat = *w + FLAME_SEL_NPARAM;
@@ -95,6 +91,12 @@ int argmax(const float *l) {
 }  // namespace
 
 namespace flame {
+
+void selector_forget_devices() {
+    std::lock_guard<std::mutex> lk(g_sel.mu);
+    g_sel.on_device.clear();
+    g_sel.gen.clear();
+}
 
 void choose_variant(int32_t dtype, int64_t n, int64_t batch, int32_t *variant, int32_t *nb) {
     if (flame_select(n, batch, dtype, 0.0, variant, nb) == FLAME_OK) return;

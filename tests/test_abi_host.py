@@ -153,3 +153,82 @@ def test_tile_enumeration_is_a_bijection(tmp_path):
                     str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout
+
+
+def test_factor_unknown_flag_bits():
+    o = _opts(flags=2)
+    assert fl.lib().flame_factor(0, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == -5
+
+
+def test_refine_method_must_be_known():
+    r = fl.Refine()
+    r.A0, r.lda0, r.tol, r.max_iter, r.method = 0x1000, 4, 1e-13, 3, 7
+    assert fl.lib().flame_solve(0, 4, 1, FAKE, 4, FAKE, 4, ctypes.byref(r), None, None) == -8
+
+
+def _mixed_opts(**kw):
+    o = fl.MixedOpts()
+    o.trail, o.method, o.max_iter, o.tol, o.scale, o.max_shifts = 2, 2, 10, 1e-13, 1, 4
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_solve_mixed_argument_errors():
+    L = fl.lib()
+    o = _mixed_opts()
+    ok = ctypes.byref(o)
+    assert L.flame_solve_mixed(-1, 1, FAKE, 4, FAKE, 4, FAKE, 4, ok, None, None) == -1
+    assert L.flame_solve_mixed(4, -1, FAKE, 4, FAKE, 4, FAKE, 4, ok, None, None) == -2
+    assert L.flame_solve_mixed(4, 1, None, 4, FAKE, 4, FAKE, 4, ok, None, None) == -3
+    assert L.flame_solve_mixed(4, 1, FAKE, 3, FAKE, 4, FAKE, 4, ok, None, None) == -4
+    assert L.flame_solve_mixed(4, 1, FAKE, 4, None, 4, FAKE, 4, ok, None, None) == -5
+    assert L.flame_solve_mixed(4, 1, FAKE, 4, FAKE, 3, FAKE, 4, ok, None, None) == -6
+    assert L.flame_solve_mixed(4, 1, FAKE, 4, FAKE, 4, None, 4, ok, None, None) == -7
+    assert L.flame_solve_mixed(4, 1, FAKE, 4, FAKE, 4, FAKE, 3, ok, None, None) == -8
+    assert L.flame_solve_mixed(4, 1, FAKE, 4, FAKE, 4, FAKE, 4, None, None, None) == -9
+    for field, value in [("trail", 3), ("nb", 513), ("method", 3), ("max_iter", -1), ("tol", -1.0),
+                         ("scale", 2), ("max_shifts", 65), ("shift", -1.0), ("reserved", 1)]:
+        bad = _mixed_opts(**{field: value})
+        assert L.flame_solve_mixed(4, 1, FAKE, 4, FAKE, 4, FAKE, 4, ctypes.byref(bad), None, None) == -9, field
+
+
+def test_breakdown_status_string():
+    assert "broke down" in fl.status_string(fl.FLAME_ERR_BREAKDOWN)
+
+
+def test_shutdown_without_devices_is_a_no_op():
+    assert fl.lib().flame_shutdown() == fl.FLAME_OK
+
+
+# ---- the Python wrapper validates shapes before it touches the device --------
+
+def test_wrapper_shape_checks():
+    import torch
+
+    z = torch.zeros
+    with pytest.raises(ValueError):
+        fl.solve(z(3, 4, dtype=torch.float64), z(3, 1, dtype=torch.float64))  # U not square
+    with pytest.raises(ValueError):
+        fl.solve(z(3, 3, dtype=torch.float64), z(4, 1, dtype=torch.float64))  # B rows != n
+    with pytest.raises(TypeError):
+        fl.solve(z(3, 3, dtype=torch.float64), z(3, 1, dtype=torch.float32))  # dtype mismatch
+    with pytest.raises(ValueError):
+        fl.solve(z(3, 3, dtype=torch.float64), z(3, 1, dtype=torch.float64), A0=z(4, 4, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        fl.solve(z(3, 3, dtype=torch.float64), z(3, 1, dtype=torch.float64), A0=z(3, 3, dtype=torch.float32))
+    with pytest.raises(ValueError):
+        fl.solve(z(3, 3, dtype=torch.float64), z(3, 1, dtype=torch.float64), A0=z(3, 3, dtype=torch.float64),
+                 method="gmres")
+    with pytest.raises(ValueError):
+        fl.op_trsm(z(3, 3), z(4, 2))  # X rows != b
+    with pytest.raises(ValueError):
+        fl.op_gemm_tn(z(4, 5), z(3, 4), z(2, 5), upper=False)  # inner dimensions differ
+    with pytest.raises(ValueError):
+        fl.op_gemm_tn(z(4, 4), z(3, 4), z(3, 5), upper=False)  # C not X.shape[1] x Y.shape[1]
+    with pytest.raises(ValueError):
+        fl.factor(z(3, 4, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        fl.solve_mixed(z(3, 3, dtype=torch.float64), z(4, 1, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        fl.solve_mixed(z(3, 3, dtype=torch.float32), z(3, 1, dtype=torch.float64))

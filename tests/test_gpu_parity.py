@@ -173,12 +173,45 @@ def test_factor_f64(variant, nb, n):
     A = inputs.spd_bbt(n, 0)
     Uo, io = oracle.potrf(A, threads=8)
     Ad = to_dev(A, ld=n + (n % 3))
-    info = fl.factor(Ad, variant=variant, nb=nb)
+    # fixed_nb: the right-looking loop runs the block size named here (without
+    # it the last 6144 columns use blocks of at most 128)
+    info = fl.factor(Ad, variant=variant, nb=nb, fixed_nb=True)
     Ug = to_host(Ad)
     assert int(info.item()) == io == 0
     assert _rel_max(Ug, Uo) <= TOL_PAR64
     assert oracle.factor_backward_error(A, Ug) <= TOL_BETA64
     assert np.array_equal(np.tril(Ug, -1), np.tril(to_host(to_dev(A, ld=n + (n % 3))), -1))
+
+
+@pytest.mark.parametrize("n", [513, 1000, 1531])
+@pytest.mark.parametrize("lookahead", [0, -1])
+def test_factor_right_nb512_fixed(n, lookahead):
+    """Blocks of 512 throughout (K = 512 trailing products, the 512-row CHOL
+    and TRSM taken three levels deep), with and without lookahead."""
+    A = inputs.spd_bbt(n, 21)
+    Uo, _ = oracle.potrf(A, threads=8)
+    Ad = to_dev(A, ld=n + 5)
+    info = fl.factor(Ad, variant=3, nb=512, lookahead=lookahead, fixed_nb=True)
+    Ug = to_host(Ad)
+    assert int(info.item()) == 0
+    assert _rel_max(Ug, Uo) <= TOL_PAR64
+    assert oracle.factor_backward_error(A, Ug) <= TOL_BETA64
+
+
+def test_factor_default_options_reach_schedule():
+    """NULL options (variant chosen by the library, nb = 0) factor correctly;
+    at this order the default schedule (512 / 256 / 128 by position) runs its
+    128-column tail."""
+    n = 1100
+    A = inputs.spd_bbt(n, 22)
+    Uo, _ = oracle.potrf(A, threads=8)
+    Ad = to_dev(A)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    rc = fl.lib().flame_factor(fl.F64, n, Ad.data_ptr(), n, None, info.data_ptr(), fl._stream_ptr())
+    assert rc == 0
+    Ug = to_host(Ad)
+    assert int(info.item()) == 0
+    assert _rel_max(Ug, Uo) <= TOL_PAR64
 
 
 @pytest.mark.parametrize("lookahead", [1, -1])
@@ -316,7 +349,7 @@ def test_tall_k_products_split(variant, nb):
     n = 2600
     A, Uo = _oracle_factor(n, 12)
     Ad = to_dev(A, ld=n + 8)
-    info = fl.factor(Ad, variant=variant, nb=nb)
+    info = fl.factor(Ad, variant=variant, nb=nb, fixed_nb=True)
     assert int(info.item()) == 0
     Ug = to_host(Ad)
     assert _rel_max(Ug, Uo) <= TOL_PAR64
@@ -343,27 +376,166 @@ def test_solve_plain(n, nrhs):
     assert oracle.solve_backward_error(A, X, B) <= 1e-14
 
 
+def _forward_bound(A0, eta_gpu, eta_oracle):
+    """Normwise forward-error bound of two solutions of A0 x = b with
+    backward errors eta_gpu and eta_oracle: each is within
+    2 eta kappa_inf / (1 - eta kappa_inf) of the exact x (perturbation theory
+    for (A0 + dA) x = b + db, ||dA|| <= eta ||A0||, ||db|| <= eta ||b||)."""
+    k_inf = np.linalg.norm(A0, np.inf) * np.linalg.norm(np.linalg.inv(A0), np.inf)
+    one = lambda e: 2.0 * e * k_inf / max(1.0 - e * k_inf, 0.5)
+    return one(eta_gpu) + one(eta_oracle)
+
+
 @pytest.mark.parametrize("trail", ["f32", "bf16"])
-@pytest.mark.parametrize("kappa", [1e2, 1e4])
-@pytest.mark.parametrize("nrhs", [1, 8])
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
+@pytest.mark.parametrize("nrhs", [1, 64])
 def test_mixed_factor_and_refinement(trail, kappa, nrhs):
+    """flame_solve_mixed on A0 = Q diag(s) Q^T: unit-diagonal scaling, the
+    low-precision factorization (shifted after a breakdown), FP64 refinement
+    (IR while it halves eta, then preconditioned CG).  Every cell must reach
+    eta <= 1e-13 (checked by the oracle's own metric), take at least one
+    refinement step, and agree with the oracle's FP64 solution within the
+    forward-error bound both backward errors imply."""
     n = 768
-    if trail == "bf16" and kappa > 1e2:
-        pytest.skip("BF16 trailing updates break down or stall above kappa ~ 1e2")
     A0 = inputs.spd_kappa(n, kappa, 0)
     B = inputs.rhs(n, nrhs, 0)
-    x_star = oracle.solve(np.triu(oracle.potrf(A0, threads=8)[0]), B)
-    Ad = to_dev(A0)
-    A0d = to_dev(A0)
-    info = fl.factor(Ad, variant=3, nb=128, trail=trail)
-    assert int(info.item()) == 0
-    Bd = to_dev(B)
-    rep = fl.solve(Ad, Bd, A0=A0d, tol=1e-13, max_iter=60)
+    Uo, io = oracle.potrf(A0, threads=8)
+    assert io == 0
+    x_star = oracle.solve(np.triu(Uo), B)
+    A0d = to_dev(A0, ld=n + 2)
+    Bd = to_dev(B, ld=n + 1)
+    rep = fl.solve_mixed(A0d, Bd, trail=trail, nb=128, tol=1e-13, max_iter=2000, method="auto")
     X = to_host(Bd)
     assert rep["status"] == fl.FLAME_OK, rep
-    assert rep["eta"] <= 1e-13
+    assert rep["iters"] >= 1 and rep["factor_info"] == 0, rep
+    eta = oracle.solve_backward_error(A0, X, B)
+    assert eta <= 1e-13 and rep["eta"] <= 1e-13
+    assert abs(rep["eta"] - eta) <= 1e-2 * max(eta, 1e-17) + 1e-18
+    eta_o = oracle.solve_backward_error(A0, x_star, B)
+    fwd = np.max(np.abs(X - x_star)) / np.max(np.abs(x_star))
+    assert fwd <= _forward_bound(A0, eta, eta_o), (fwd, eta, eta_o)
+    # A0 is not modified
+    assert np.array_equal(np.triu(to_host(A0d)), np.triu(A0))
+
+
+def test_mixed_bf16_high_kappa_needs_shift_and_cg():
+    """kappa = 1e6 with BF16 products: the unshifted factorization breaks
+    down on this input and classical refinement cannot converge
+    (kappa u_bf16 >> 1), so the driver must have shifted and finished with
+    CG."""
+    n = 768
+    A0 = inputs.spd_kappa(n, 1e6, 0)
+    B = inputs.rhs(n, 1, 0)
+    A0d = to_dev(A0)
+    Bd = to_dev(B)
+    rep = fl.solve_mixed(A0d, Bd, trail="bf16", nb=128, tol=1e-13, max_iter=2000, method="auto")
+    assert rep["status"] == fl.FLAME_OK, rep
+    assert rep["attempts"] >= 2 and rep["shift"] > 0.0, rep
+    assert rep["method"] == "cg", rep
+    assert oracle.solve_backward_error(A0, to_host(Bd), B) <= 1e-13
+
+
+@pytest.mark.parametrize("method", ["ir", "cg"])
+def test_mixed_methods_without_switch(method):
+    """Each refinement method alone converges where it should: classical IR
+    with FP32 products at kappa = 1e4, CG with BF16 products at kappa = 1e4."""
+    n = 640
+    trail = "f32" if method == "ir" else "bf16"
+    A0 = inputs.spd_kappa(n, 1e4, 4)
+    B = inputs.rhs(n, 3, 4)
+    A0d = to_dev(A0)
+    Bd = to_dev(B)
+    rep = fl.solve_mixed(A0d, Bd, trail=trail, nb=128, tol=1e-13, max_iter=1000, method=method)
+    assert rep["status"] == fl.FLAME_OK and rep["method"] == method, rep
+    assert oracle.solve_backward_error(A0, to_host(Bd), B) <= 1e-13
+
+
+def test_mixed_not_positive_diagonal_is_a_breakdown():
+    n = 300
+    A0 = inputs.spd_kappa(n, 1e2, 1)
+    A0[40, 40] = -A0[40, 40]
+    with pytest.raises(fl.FlameError) as e:
+        fl.solve_mixed(to_dev(A0), to_dev(inputs.rhs(n, 1, 1)), trail="f32")
+    assert e.value.status == fl.FLAME_ERR_BREAKDOWN
+
+
+def test_mixed_every_attempt_breaks_down():
+    """An indefinite matrix with a positive diagonal: no shift within the
+    allowed retries makes it definite at BF16, so the driver reports a
+    breakdown rather than a wrong factor."""
+    n = 256
+    g = np.random.Generator(np.random.PCG64(5))
+    Q, _ = np.linalg.qr(g.standard_normal((n, n)))
+    s = np.linspace(1.0, 2.0, n)
+    s[-8:] = -1.0  # eight negative eigenvalues
+    A0 = np.asfortranarray((Q * s) @ Q.T)
+    A0 = np.asfortranarray(np.triu(A0) + np.triu(A0, 1).T)
+    assert np.all(np.diag(A0) > 0)
+    with pytest.raises(fl.FlameError) as e:
+        fl.solve_mixed(to_dev(A0), to_dev(inputs.rhs(n, 1, 2)), trail="bf16", max_shifts=2)
+    assert e.value.status == fl.FLAME_ERR_BREAKDOWN
+
+
+def test_refinement_nrhs64_takes_correction_steps():
+    """The blocked (nrhs > 8) refinement path: FP32-trailing factor, IR with
+    at least one correction step, every column to eta <= 1e-13."""
+    n = 900
+    A0 = inputs.spd_kappa(n, 1e4, 6)
+    B = inputs.rhs(n, 64, 6)
+    Ad = to_dev(A0)
+    A0d = to_dev(A0, ld=n + 3)
+    assert int(fl.factor(Ad, variant=3, nb=128, trail="f32").item()) == 0
+    Bd = to_dev(B, ld=n + 1)
+    rep = fl.solve(Ad, Bd, A0=A0d, tol=1e-13, max_iter=30, method="ir")
+    X = to_host(Bd)
+    assert rep["status"] == fl.FLAME_OK and rep["iters"] >= 1, rep
     assert oracle.solve_backward_error(A0, X, B) <= 1e-13
-    assert np.linalg.norm(X - x_star) / np.linalg.norm(x_star) <= kappa * 1e-13
+
+
+@pytest.mark.parametrize("nrhs", [1, 9])
+def test_refinement_cg_on_plain_factor(nrhs):
+    """CG on the factor of flame_factor (BF16 products, kappa = 1e2): both the
+    single-launch (nrhs <= 8) and the blocked (nrhs > 8) paths."""
+    n = 700
+    A0 = inputs.spd_kappa(n, 1e2, 7)
+    B = inputs.rhs(n, nrhs, 7)
+    Ad = to_dev(A0)
+    A0d = to_dev(A0)
+    assert int(fl.factor(Ad, variant=3, nb=128, trail="bf16").item()) == 0
+    Bd = to_dev(B)
+    rep = fl.solve(Ad, Bd, A0=A0d, tol=1e-13, max_iter=500, method="cg")
+    assert rep["status"] == fl.FLAME_OK and rep["method"] == "cg" and rep["iters"] >= 1, rep
+    assert oracle.solve_backward_error(A0, to_host(Bd), B) <= 1e-13
+
+
+def test_mixed_graph_workspace_regrowth():
+    """A graph captured for a mixed factorization at a small order must not be
+    replayed into a panel workspace that a larger call has since replaced:
+    capture at n = 600, grow the workspace with an eager n = 4096 call, then
+    call the first configuration again and compare with the oracle."""
+    n = 600
+    A = inputs.spd_kappa(n, 1e2, 9)
+    Uo, _ = oracle.potrf(A, threads=8)
+    Ad = to_dev(A)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        info = fl.factor(Ad, variant=3, nb=128, trail="f32", graph=1)
+        s.synchronize()
+        first = to_host(Ad)
+        big = to_dev(inputs.spd_bbt(4096, 9))
+        assert int(fl.factor(big, variant=3, nb=256, trail="f32").item()) == 0
+        torch.cuda.synchronize()
+        del big
+        filler = torch.full((1 << 24,), 7.0, dtype=torch.float64, device="cuda:0")  # reuse of freed memory
+        Ad.copy_(to_dev(A))
+        info = fl.factor(Ad, variant=3, nb=128, trail="f32", graph=1)
+        s.synchronize()
+        again = to_host(Ad)
+        assert torch.all(filler == 7.0)
+    assert int(info.item()) == 0
+    assert np.array_equal(first, again)
+    # FP32 products: the factor of a kappa = 1e2 matrix within FP32 rounding
+    assert _rel_max(again, Uo) <= 1e-4
 
 
 @pytest.mark.parametrize("nrhs", [1, 3, 9])
