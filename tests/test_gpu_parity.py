@@ -408,9 +408,11 @@ def test_mixed_factor_and_refinement(trail, kappa, nrhs):
     X = to_host(Bd)
     assert rep["status"] == fl.FLAME_OK, rep
     assert rep["iters"] >= 1 and rep["factor_info"] == 0, rep
+    # both etas at or below the target (near the rounding floor the two
+    # residuals differ by their rounding order, so only the bound is compared;
+    # test_refinement_eta_matches_oracle compares them where eta is large)
     eta = oracle.solve_backward_error(A0, X, B)
     assert eta <= 1e-13 and rep["eta"] <= 1e-13
-    assert abs(rep["eta"] - eta) <= 1e-2 * max(eta, 1e-17) + 1e-18
     eta_o = oracle.solve_backward_error(A0, x_star, B)
     fwd = np.max(np.abs(X - x_star)) / np.max(np.abs(x_star))
     assert fwd <= _forward_bound(A0, eta, eta_o), (fwd, eta, eta_o)
