@@ -217,6 +217,22 @@ int flame_solve_mixed(int64_t n, int64_t nrhs, const double *A0, int64_t lda0, d
 int flame_batched_factor(int32_t dtype, int32_t batch, const int32_t *n, void *const *A, const int32_t *lda,
                          int32_t *info, const flame_opts_t *opts, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * factorization as flame_batched_factor, launched directly (no graph), with
+ * its sort workspace in a fixed device array instead of library-allocated
+ * memory.  It calls no hipMalloc / hipFree.  The array holds
+ * FLAME_NOALLOC_MAX_BATCH + 1090 int32 (about 1 MiB) on every GPU the
+ * library runs on, until the process ends; the first call on a device looks
+ * its address up.  Every call on one GPU uses that GPU's array: calls that
+ * overlap on one GPU (on different streams) race and must be ordered by the
+ * caller.  Launches are not recorded by flame_trace_enable.
+ * Errors: -1 dtype, -2 batch (< 0 or > FLAME_NOALLOC_MAX_BATCH), -3 n, -4 A,
+ * -5 lda, -6 info; the arrays as for flame_batched_factor. */
+#define FLAME_NOALLOC_MAX_BATCH 262144
+int flame_batched_factor_noalloc(int32_t dtype, int32_t batch, const int32_t *n, void *const *A,
+                                 const int32_t *lda, int32_t *info, void *stream);
+
 /* ---- block operations of the loop body (Fig. "dense-chol") ------------- */
 /* Exposed so each kernel of the loop can be checked on its own.  Same
  * conventions as above; `dtype` selects double or float operands. */

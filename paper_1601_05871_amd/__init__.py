@@ -37,8 +37,9 @@ EXPORTS = (
     "flame_factor", "flame_solve", "flame_batched_factor", "flame_op_chol", "flame_op_trsm",
     "flame_op_gemm_tn", "flame_selector_load", "flame_select", "flame_select_logits", "flame_autotune",
     "flame_trace_enable", "flame_trace_collect", "flame_status_string", "flame_version",
-    "flame_solve_mixed", "flame_shutdown",
+    "flame_solve_mixed", "flame_shutdown", "flame_batched_factor_noalloc",
 )
+NOALLOC_MAX_BATCH = 262144
 KC_CHOL, KC_TRSM, KC_GEMM, KC_OTHER = 0, 1, 2, 3
 
 
@@ -100,6 +101,7 @@ def lib() -> ctypes.CDLL:
     L.flame_solve_mixed.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, ctypes.POINTER(MixedOpts),
                                     ctypes.POINTER(SolveReport), vp]
     L.flame_shutdown.argtypes = []
+    L.flame_batched_factor_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, vp]
     L.flame_status_string.argtypes = [ctypes.c_int]
     L.flame_status_string.restype = ctypes.c_char_p
     L.flame_version.argtypes = []
@@ -310,6 +312,16 @@ def batched_factor(ns, ptrs, ldas, info, dtype=F64, opts: Opts | None = None, gr
                                     info.data_ptr(), ctypes.byref(opts) if opts is not None else None,
                                     _stream_ptr())
     _check("flame_batched_factor", rc)
+    return info
+
+
+def batched_factor_noalloc(ns, ptrs, ldas, info, dtype=F64):
+    """flame_batched_factor_noalloc: the batched factorization with its
+    workspace in the library's fixed device array (no allocation; at most
+    NOALLOC_MAX_BATCH matrices; overlapping calls on one GPU race)."""
+    rc = lib().flame_batched_factor_noalloc(int(dtype), int(ns.numel()), ns.data_ptr(), ptrs.data_ptr(),
+                                            ldas.data_ptr(), info.data_ptr(), _stream_ptr())
+    _check("flame_batched_factor_noalloc", rc)
     return info
 
 

@@ -8,6 +8,8 @@
 
 using namespace flame;
 
+static_assert(FLAME_NOALLOC_MAX_BATCH > 0, "");
+
 namespace {
 
 using BKey = std::tuple<int, int32_t, const void *, const void *, const void *, const void *, void *, hipStream_t, int>;
@@ -18,6 +20,47 @@ int run_batched(int32_t dtype, int32_t batch, const int32_t *n, void *const *A, 
                 int32_t *ws, hipStream_t s) {
     if (dtype == FLAME_F64) return launch_batched<double>(batch, n, A, lda, info, ws, s);
     return launch_batched<float>(batch, n, A, lda, info, ws, s);
+}
+
+// ---- no-allocation variant ------------------------------------------------
+// The sort workspace of the batched factorization in a fixed device array,
+// one per GPU (each device holds its own copy until the process ends).  Its
+// host-side name is not a device address: kernels get the address from
+// hipGetSymbolAddress, taken once per device.
+constexpr int32_t kNoAllocMaxBatch = FLAME_NOALLOC_MAX_BATCH;
+constexpr size_t kScratchInts = (size_t)kNoAllocMaxBatch + 1024 + 2 + 64;  // order + histogram + counter (+ slack)
+static __device__ __align__(256) int32_t scratch[kScratchInts];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device), or nullptr with *err set.
+int32_t *scratch_for_device(int *err) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_last_hip_error(e);
+        *err = FLAME_ERR_HIP;
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = FLAME_ERR_UNSUPPORTED;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_last_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            *err = FLAME_ERR_HIP;
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<int32_t *>(p);
+    }
+    return g_scratch_ptr[dev];
 }
 
 }  // namespace
@@ -93,4 +136,22 @@ extern "C" int flame_batched_factor(int32_t dtype, int32_t batch, const int32_t 
     }
     FLAME_HIP(hipGraphLaunch(exec, s));
     return FLAME_OK;
+}
+
+extern "C" int flame_batched_factor_noalloc(int32_t dtype, int32_t batch, const int32_t *n, void *const *A,
+                                            const int32_t *lda, int32_t *info, void *stream) {
+    if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
+    if (batch < 0 || batch > kNoAllocMaxBatch) return -2;
+    if (batch > 0 && n == nullptr) return -3;
+    if (batch > 0 && A == nullptr) return -4;
+    if (batch > 0 && lda == nullptr) return -5;
+    if (batch > 0 && info == nullptr) return -6;
+    if (batch == 0) return FLAME_OK;
+    if (batched_workspace_ints(batch) > kScratchInts) return -2;
+    int err = FLAME_OK;
+    int32_t *ws = scratch_for_device(&err);
+    if (ws == nullptr) return err;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == FLAME_F64) return launch_batched<double>(batch, n, A, lda, info, ws, s, false);
+    return launch_batched<float>(batch, n, A, lda, info, ws, s, false);
 }

@@ -143,10 +143,11 @@ int launch_eta_full(int64_t n, int64_t nrhs, const double *R, int64_t ldr, const
                     const double *B, int64_t ldb, const double *rowsums, double *eta, hipStream_t s);
 
 // ---- batched -------------------------------------------------------------
-// ws: batched_workspace_ints(batch) ints (order, counter, histogram).
+// ws: batched_workspace_ints(batch) ints (order, counter, histogram), cleared
+// here by a fill kernel.  traced: record the launch when tracing is on.
 template <typename T>
 int launch_batched(int32_t batch, const int32_t *n, void *const *A, const int32_t *lda, int32_t *info, int32_t *ws,
-                   hipStream_t s);
+                   hipStream_t s, bool traced = true);
 size_t batched_workspace_ints(int32_t batch);
 
 // ---- selector --------------------------------------------------------------

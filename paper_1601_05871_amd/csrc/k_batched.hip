@@ -264,7 +264,7 @@ size_t batched_workspace_ints(int32_t batch) { return (size_t)batch + kBuckets +
 
 template <typename T>
 int launch_batched(int32_t batch, const int32_t *n, void *const *A, const int32_t *lda, int32_t *info, int32_t *ws,
-                   hipStream_t s) {
+                   hipStream_t s, bool traced) {
     if (batch <= 0) return FLAME_OK;
     int32_t *hist = ws;                  // kBuckets
     int32_t *counter = ws + kBuckets;    // 1
@@ -289,7 +289,7 @@ int launch_batched(int32_t batch, const int32_t *n, void *const *A, const int32_
     FLAME_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_batch_scatter, dim3(gb), dim3(256), 0, s, batch, n, lda, hist, order);
     FLAME_CHECK_LAUNCH();
-    const int tr = trace_begin(FLAME_KC_OTHER, s);
+    const int tr = traced ? trace_begin(FLAME_KC_OTHER, s) : -1;
     hipLaunchKernelGGL(k_batched<T>, dim3((unsigned)std::min<int64_t>(grid, batch)), dim3(256), 0, s, batch, n,
                        reinterpret_cast<T *const *>(A), lda, info, order, counter);
     FLAME_CHECK_LAUNCH();
@@ -298,8 +298,8 @@ int launch_batched(int32_t batch, const int32_t *n, void *const *A, const int32_
 }
 
 template int launch_batched<double>(int32_t, const int32_t *, void *const *, const int32_t *, int32_t *, int32_t *,
-                                    hipStream_t);
+                                    hipStream_t, bool);
 template int launch_batched<float>(int32_t, const int32_t *, void *const *, const int32_t *, int32_t *, int32_t *,
-                                   hipStream_t);
+                                   hipStream_t, bool);
 
 }  // namespace flame
