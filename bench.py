@@ -8,11 +8,14 @@ for the last 8192 and 6144 columns), lookahead.
 Each timed step factors its own pre-generated copy already resident in HBM,
 so the timed region holds nothing but the K factorizations.  Prints one JSON
 line with GFLOP/s (potrf flop count n^3/3 + n^2/2 + n/6), the live roofline of
-the dominant kernel (the trailing SYRK/GEMM, from per-launch HIP events), the
-mixed-precision time to solution against the FP64 path at equal backward
-error, and the CPU oracle's rate on the host cores.
+the dominant kernel (the trailing SYRK/GEMM: its flops over the union of its
+launch intervals, from per-launch HIP events), the mixed-precision time to
+solution against the FP64 path at equal backward error for every
+kappa x trail x nrhs cell, the batched factorization, and the CPU oracle's
+rate on the host cores.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+    python bench.py --table [--steps 2]     # the n x nb x variant x seed sweep
 """
 from __future__ import annotations
 
@@ -54,9 +57,16 @@ def main() -> int:
     ap.add_argument("--no-trace", action="store_true",
                     help="time without the per-launch events (no roofline figures)")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--kappa", type=float, default=1e4)
-    ap.add_argument("--trail", default="f32")
+    ap.add_argument("--kappas", default="1e2,1e4,1e6", help="condition numbers of the mixed-precision cells")
+    ap.add_argument("--trails", default="f32,bf16", help="trailing-product precisions of the mixed cells")
+    ap.add_argument("--nrhs", default="1,64", help="right-hand-side counts of the mixed cells")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--table", action="store_true",
+                    help="instead of the default run: time every (n, nb, variant, seed) cell of the "
+                         "single-matrix FP64 sweep and print a markdown table")
+    ap.add_argument("--table-ns", default="4096,8192,16384")
+    ap.add_argument("--table-nbs", default="64,128,256")
+    ap.add_argument("--table-seeds", default="0,1,2")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch", type=int, default=10000)
@@ -79,6 +89,8 @@ def main() -> int:
     fl.lib()  # fails loudly if the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.table:
+        return table_mode(args, dev, fl, inputs, torch)
     if args.copy_probe_gib > 0:
         words = int(args.copy_probe_gib * (1 << 30)) // 8
         src = torch.ones(words, dtype=torch.float64, device=dev)
@@ -129,7 +141,8 @@ def main() -> int:
     # first) with HIP events around every kernel launch, on the stream each
     # launch uses; the events cost ~10 % of the step time, so they are kept out
     # of the timed region above
-    trace = {k: {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0} for k in ("chol", "trsm", "gemm", "other")}
+    trace = {k: {"launches": 0, "ms": 0.0, "busy_ms": 0.0, "flops": 0.0, "bytes": 0.0}
+             for k in ("chol", "trsm", "gemm", "other")}
     traced_ms = None
     if not args.no_trace:
         for c in copies:
@@ -145,9 +158,14 @@ def main() -> int:
         trace = fl.trace_collect()
         fl.trace_enable(False)
 
-    # dominant kernel: the trailing update (SYRK/GEMM on FP64 matrix cores)
+    # dominant kernel: the trailing update (SYRK/GEMM on FP64 matrix cores).
+    # Its launches overlap each other (remainder and panel-row updates run on
+    # two streams), so the rate is taken over their busy time per step: the
+    # union of the launches' intervals, not the sum of their durations.
     g = trace["gemm"]
-    gemm_tflops = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    busy_ms = g.get("busy_ms", 0.0)
+    gemm_tflops = g["flops"] / (busy_ms * 1e-3) / 1e12 if busy_ms > 0 else 0.0
+    per_launch_tflops = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
     roofline = {
         "kernel": "k_gemm_lds<F64> (trailing SYRK/GEMM, 128- and 64-tiles)",
         "bound": "mfma",
@@ -157,15 +175,21 @@ def main() -> int:
         "frac": round(gemm_tflops / PEAK_F64_TFLOPS, 4),
         "traffic": gemm_traffic(),
         "launches_per_step": g["launches"] / K,
+        "gflop_per_step": round(g["flops"] / K / 1e9, 3),
+        "busy_ms_per_step": round(busy_ms / K, 4),
+        "summed_launch_ms_per_step": round(g["ms"] / K, 4),
+        "per_launch_tflops": round(per_launch_tflops, 3),
         "avg_launch_ms": g["ms"] / max(1, g["launches"]),
         "avg_launch_gflop": g["flops"] / max(1, g["launches"]) / 1e9,
         "avg_launch_alg_bytes": g["bytes"] / max(1, g["launches"]),
-        "measured_in": "instrumented pass of the same K steps (per-launch HIP events)",
+        "measured_in": "instrumented pass of the same K steps (per-launch HIP events; achieved = trailing-update "
+                       "flops / union of their launch intervals)",
         "instrumented_ms_per_step": None if traced_ms is None else round(traced_ms, 4),
     }
     breakdown = {k: {"launches": v["launches"] // K, "ms": round(v["ms"] / K, 4),
+                     "busy_ms": round(v.get("busy_ms", 0.0) / K, 4),
                      "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] > 0 else None}
-                 for k, v in trace.items()}
+                 for k, v in trace.items() if k in ("chol", "trsm", "gemm", "other")}
 
     # ---- accuracy of the timed result (randomized backward-error estimate) --
     log("backward error of the FP64 factor")
@@ -250,50 +274,83 @@ def factor_backward_error_est(A_dev, U_dev, k: int = 8, seed: int = 0) -> float:
 
 
 def mixed_leg(args, n, dev, fl, inputs, torch):
-    """Time to solution of A0 x = b (kappa = args.kappa, one right-hand side)
-    at backward error <= 1e-13: FP64 factor + solve vs low-precision trailing
-    updates + FP64 iterative refinement, on the same A0 and b."""
-    log(f"mixed leg: generating A0 = Q diag(s) Q^T, kappa={args.kappa:g}")
-    A0 = inputs.spd_kappa_torch(n, args.kappa, args.seed, dev)
-    b = torch.from_numpy(inputs.rhs(n, 1, args.seed)).to(dev)
-    b = b.as_strided((n, 1), (1, n))
+    """Time to solution of A0 X = B at backward error <= 1e-13 for every cell
+    kappa x trail x nrhs: the FP64 path (flame_factor + one plain solve) against
+    flame_solve_mixed (unit-diagonal scaling, the factorization with FP32 or
+    BF16 trailing products, shifted retries after a breakdown, FP64
+    refinement: IR, then preconditioned CG once IR stops halving eta), on the
+    same A0 and B.  eta of every result is recomputed on the device in FP64."""
+    kappas = [float(k) for k in args.kappas.split(",") if k]
+    trails = [t for t in args.trails.split(",") if t]
+    nrhs_list = [int(k) for k in args.nrhs.split(",") if k]
+    tol = 1e-13
     W = torch.empty_strided((n, n), (1, n), dtype=torch.float64, device=dev)
-    x = torch.empty_strided((n, 1), (1, n), dtype=torch.float64, device=dev)
-    out = {"kappa": args.kappa, "nrhs": 1, "tol": 1e-13}
     stream = torch.cuda.current_stream()
 
-    def run(trail: str):
-        W.copy_(A0)
-        x.copy_(b)
+    def timed(fn):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(stream)
-        info = fl.factor(W, variant=3, nb=args.nb, trail=trail,
-                         lookahead=args.lookahead)
-        if trail == "native":
-            fl.solve(W, x)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            rep = {"iters": 0, "status": 0}
-        else:
-            rep = fl.solve(W, x, A0=A0, tol=1e-13, max_iter=50)
-            e1.record(stream)
-            torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        wall = (time.perf_counter() - t0) * 1e3
-        eta = solve_backward_error_dev(A0, x, b, torch)
-        return {"ms": round(ms, 3), "wall_ms": round(wall, 3), "eta": eta, "info": int(info.item()),
-                "iters": rep["iters"], "status": rep["status"]}
+        rep = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), (time.perf_counter() - t0) * 1e3, rep
 
-    for trail in ("native", args.trail):
-        log(f"mixed leg: {trail}")
-        run(trail)  # warm-up (graph-free; workspace allocation)
-        out[trail] = run(trail)
-    base, mix = out["native"], out[args.trail]
-    out["trail"] = args.trail
-    out["speedup_vs_fp64"] = round(base["ms"] / mix["ms"], 3) if mix["ms"] > 0 else None
-    out["equal_backward_error"] = bool(base["eta"] <= 1e-13 and mix["eta"] <= 1e-13)
+    def run_native(A0, b, x):
+        W.copy_(A0)
+        x.copy_(b)
+
+        def go():
+            info = fl.factor(W, variant=3, nb=args.nb, lookahead=args.lookahead)
+            fl.solve(W, x)
+            return info
+        ms, wall, info = timed(go)
+        return {"ms": round(ms, 3), "wall_ms": round(wall, 3), "info": int(info.item()),
+                "eta": solve_backward_error_dev(A0, x, b, torch)}
+
+    def run_mixed(A0, b, x, trail):
+        x.copy_(b)
+        ms, wall, rep = timed(lambda: fl.solve_mixed(A0, x, W=W, trail=trail, nb=0, tol=tol, max_iter=3000,
+                                                     method="auto"))
+        return {"ms": round(ms, 3), "wall_ms": round(wall, 3), "eta": solve_backward_error_dev(A0, x, b, torch),
+                "eta_reported": rep["eta"], "iters": rep["iters"], "method": rep["method"],
+                "shift": rep["shift"], "attempts": rep["attempts"], "status": rep["status"]}
+
+    out = {"n": n, "tol": tol, "method": "auto (IR, then PCG)", "scaling": "unit diagonal",
+           "cells": []}
+    nmax = max(nrhs_list)
+    for ki, kappa in enumerate(kappas):
+        log(f"mixed leg: generating A0 = Q diag(s) Q^T, kappa={kappa:g}")
+        A0 = inputs.spd_kappa_torch(n, kappa, args.seed, dev)
+        Bh = inputs.rhs(n, nmax, args.seed)
+        for nrhs in nrhs_list:
+            b = torch.from_numpy(np.asfortranarray(Bh[:, :nrhs])).to(dev).as_strided((n, nrhs), (1, n))
+            x = torch.empty_strided((n, nrhs), (1, n), dtype=torch.float64, device=dev)
+            if ki == 0:  # warm-up of every path at this nrhs (workspace allocation, code loading)
+                run_native(A0, b, x)
+                for trail in trails:
+                    run_mixed(A0, b, x, trail)
+            log(f"mixed leg: kappa={kappa:g} nrhs={nrhs} native")
+            base = run_native(A0, b, x)
+            for trail in trails:
+                log(f"mixed leg: kappa={kappa:g} nrhs={nrhs} {trail}")
+                mix = run_mixed(A0, b, x, trail)
+                ok = base["eta"] <= tol and mix["eta"] <= tol and mix["status"] == 0
+                out["cells"].append({"kappa": kappa, "nrhs": nrhs, "trail": trail, "fp64": base, "mixed": mix,
+                                     "speedup_vs_fp64": round(base["ms"] / mix["ms"], 3) if mix["ms"] > 0 else None,
+                                     "equal_backward_error": bool(ok)})
+            del b, x
+        del A0
+        torch.cuda.empty_cache()
+    good = [c for c in out["cells"] if c["equal_backward_error"]]
+    out["all_cells_converged"] = len(good) == len(out["cells"])
+    if good:
+        best = max(good, key=lambda c: c["speedup_vs_fp64"])
+        out["best_speedup_vs_fp64"] = best["speedup_vs_fp64"]
+        out["best_cell"] = {"kappa": best["kappa"], "nrhs": best["nrhs"], "trail": best["trail"]}
+    del W
+    torch.cuda.empty_cache()
     return out
 
 
@@ -353,6 +410,61 @@ def batched_leg(args, dev, fl, inputs, torch):
     del mats
     torch.cuda.empty_cache()
     return out
+
+
+def table_mode(args, dev, fl, inputs, torch) -> int:
+    """The single-matrix FP64 sweep: every n x nb x variant x seed cell, each
+    factorization timed with HIP events on a resident copy (restored outside
+    the timed region), median over seeds and repetitions; every block of the
+    right-looking loop runs at the named nb (no smaller tail blocks)."""
+    ns = [int(v) for v in args.table_ns.split(",") if v]
+    nbs = [int(v) for v in args.table_nbs.split(",") if v]
+    seeds = [int(v) for v in args.table_seeds.split(",") if v]
+    reps = max(1, args.steps)
+    names = {1: "bordered", 2: "left-looking", 3: "right-looking"}
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n in ns:
+        times = {(nb, v): [] for nb in nbs for v in (1, 2, 3)}
+        for seed in seeds:
+            log(f"table: n={n} seed={seed}")
+            P = inputs.spd_bbt_torch(n, seed, dev)
+            W = torch.empty_strided((n, n), (1, n), dtype=torch.float64, device=dev)
+            info = torch.zeros(1, dtype=torch.int32, device=dev)
+            for nb in nbs:
+                for v in (1, 2, 3):
+                    for r in range(1 + reps):
+                        W.copy_(P)
+                        torch.cuda.synchronize()
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        fl.factor(W, variant=v, nb=nb, lookahead=args.lookahead, fixed_nb=True, info=info)
+                        e1.record(stream)
+                        torch.cuda.synchronize()
+                        if int(info.item()) != 0:
+                            log(f"breakdown n={n} nb={nb} variant={v}")
+                            return 1
+                        if r > 0:
+                            times[(nb, v)].append(e0.elapsed_time(e1))
+            del P, W
+            torch.cuda.empty_cache()
+        for nb in nbs:
+            for v in (1, 2, 3):
+                t = np.array(times[(nb, v)])
+                med = float(np.median(t))
+                tf = potrf_flops(n) / (med * 1e-3) / 1e12
+                rec = {"n": n, "nb": nb, "variant": names[v], "ms_median": round(med, 3),
+                       "ms_min": round(float(t.min()), 3), "ms_max": round(float(t.max()), 3),
+                       "tflops": round(tf, 2), "pct_fp64_peak": round(100 * tf / PEAK_F64_TFLOPS, 1),
+                       "samples": int(t.size)}
+                rows.append(rec)
+                print(json.dumps(rec), flush=True)
+    print(f"\n| n | nb | variant | median ms | min ms | max ms | TFLOP/s | % FP64 peak |")
+    print("|---|---|---|---|---|---|---|---|")
+    for r in rows:
+        print(f"| {r['n']} | {r['nb']} | {r['variant']} | {r['ms_median']} | {r['ms_min']} | {r['ms_max']} | "
+              f"{r['tflops']} | {r['pct_fp64_peak']} |")
+    return 0
 
 
 def cpu_leg(P, n: int, seconds: float):

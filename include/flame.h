@@ -320,6 +320,37 @@ int flame_trace_enable(int32_t on);
  * Errors: FLAME_ERR_HIP if an event query fails. */
 int flame_trace_collect(int64_t *launches, double *ms, double *flops, double *bytes);
 
+/* Busy time per kernel class: the length of the union of the recorded
+ * launches' [start, end] intervals on one clock (launches of one class that
+ * overlap on different streams count once), host array of FLAME_KC_COUNT;
+ * span_ms (host, may be NULL): from the first record's start to the last end.
+ * Synchronizes the recorded events.  Errors: FLAME_ERR_HIP if an event query
+ * fails. */
+int flame_trace_busy(double *busy_ms, double *span_ms);
+
+/* ---- measurement probes ---------------------------------------------------- */
+
+/* The device rates the roofline fractions are read against, measured with
+ * plain loops on the calling device (instrumentation, not part of the
+ * factorization).  kind:
+ *   FLAME_PROBE_MFMA_F64   v_mfma_f64_16x16x4f64 chains, work = rounds per wavefront
+ *   FLAME_PROBE_MFMA_F32   v_mfma_f32_16x16x4f32 chains, work = rounds
+ *   FLAME_PROBE_MFMA_BF16  v_mfma_f32_16x16x32_bf16 chains, work = rounds
+ *   FLAME_PROBE_COPY       device copy of work bytes (multiple of 16) from the
+ *                          first half of buf to the second
+ * wg_per_cu: workgroups of four wavefronts per compute unit in the grid
+ * (1..8, 0 = 2).  buf: device scratch of buf_bytes (MFMA: >= wg_per_cu * CUs
+ * * 256 floats, written; copy: >= 2 * work).  The best of `reps` timed runs
+ * (after one warm-up) is returned in *rate (host): TFLOP/s for MFMA, GB/s
+ * (read + write) for copy.  Synchronous.  Errors: -1 kind, -2 work,
+ * -3 wg_per_cu, -4 buf, -5 buf_bytes, -6 reps, -7 rate. */
+#define FLAME_PROBE_MFMA_F64 0
+#define FLAME_PROBE_MFMA_F32 1
+#define FLAME_PROBE_MFMA_BF16 2
+#define FLAME_PROBE_COPY 3
+int flame_probe(int32_t kind, int64_t work, int32_t wg_per_cu, void *buf, int64_t buf_bytes, int32_t reps,
+                double *rate, void *stream);
+
 /* ---- teardown -------------------------------------------------------------- */
 
 /* Waits for every device the library has used, then releases its state there:

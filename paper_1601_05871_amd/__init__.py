@@ -37,8 +37,9 @@ EXPORTS = (
     "flame_factor", "flame_solve", "flame_batched_factor", "flame_op_chol", "flame_op_trsm",
     "flame_op_gemm_tn", "flame_selector_load", "flame_select", "flame_select_logits", "flame_autotune",
     "flame_trace_enable", "flame_trace_collect", "flame_status_string", "flame_version",
-    "flame_solve_mixed", "flame_shutdown", "flame_batched_factor_noalloc",
+    "flame_solve_mixed", "flame_shutdown", "flame_batched_factor_noalloc", "flame_trace_busy", "flame_probe",
 )
+PROBE = {"mfma_f64": 0, "mfma_f32": 1, "mfma_bf16": 2, "copy": 3}
 NOALLOC_MAX_BATCH = 262144
 KC_CHOL, KC_TRSM, KC_GEMM, KC_OTHER = 0, 1, 2, 3
 
@@ -98,6 +99,8 @@ def lib() -> ctypes.CDLL:
     L.flame_autotune.argtypes = [i32, i64, vp, i64, i32, vp, vp]
     L.flame_trace_enable.argtypes = [i32]
     L.flame_trace_collect.argtypes = [vp, vp, vp, vp]
+    L.flame_trace_busy.argtypes = [vp, vp]
+    L.flame_probe.argtypes = [i32, i64, i32, vp, i64, i32, ctypes.POINTER(dbl), vp]
     L.flame_solve_mixed.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, ctypes.POINTER(MixedOpts),
                                     ctypes.POINTER(SolveReport), vp]
     L.flame_shutdown.argtypes = []
@@ -385,18 +388,35 @@ def autotune(A, reps: int = 2):
     return t
 
 
+def probe(kind: str, work: int, buf, reps: int = 3, wg_per_cu: int = 0) -> float:
+    """Runs one measurement probe (flame_probe): TFLOP/s of an MFMA loop or
+    GB/s of a device copy; ``buf`` is a device tensor used as scratch."""
+    rate = ctypes.c_double(0.0)
+    rc = lib().flame_probe(PROBE[kind], int(work), int(wg_per_cu), buf.data_ptr(), buf.numel() * buf.element_size(),
+                           int(reps), ctypes.byref(rate), _stream_ptr())
+    _check("flame_probe", rc)
+    return rate.value
+
+
 def trace_enable(on: bool = True) -> None:
     """Per-launch HIP-event timing of the library's kernels (instrumentation)."""
     _check("flame_trace_enable", lib().flame_trace_enable(int(bool(on))))
 
 
 def trace_collect() -> dict:
-    """Per kernel class: launches, ms, flops, bytes (synchronizes)."""
+    """Per kernel class: launches, ms (sum of launch durations), busy_ms (the
+    union of the launches' intervals), flops, bytes; and span_ms, first start
+    to last end (synchronizes)."""
     arr_i = (ctypes.c_int64 * 4)()
     ms, fl_, by = (ctypes.c_double * 4)(), (ctypes.c_double * 4)(), (ctypes.c_double * 4)()
     _check("flame_trace_collect", lib().flame_trace_collect(arr_i, ms, fl_, by))
+    busy, span = (ctypes.c_double * 4)(), ctypes.c_double(0.0)
+    _check("flame_trace_busy", lib().flame_trace_busy(busy, ctypes.byref(span)))
     names = ("chol", "trsm", "gemm", "other")
-    return {names[k]: {"launches": int(arr_i[k]), "ms": ms[k], "flops": fl_[k], "bytes": by[k]} for k in range(4)}
+    out = {names[k]: {"launches": int(arr_i[k]), "ms": ms[k], "busy_ms": busy[k], "flops": fl_[k], "bytes": by[k]}
+           for k in range(4)}
+    out["span_ms"] = span.value
+    return out
 
 
 # ---- block operations of the loop body -------------------------------------

@@ -1,5 +1,7 @@
 // Per-launch HIP-event timing of the library's kernels (instrumentation for
 // measuring each kernel class against its roofline while the real loop runs).
+#include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "flame_internal.h"
@@ -82,5 +84,43 @@ extern "C" int flame_trace_collect(int64_t *launches, double *ms, double *flops,
         if (flops) flops[k] = F[k];
         if (bytes) bytes[k] = B[k];
     }
+    return FLAME_OK;
+}
+
+extern "C" int flame_trace_busy(double *busy_ms, double *span_ms) {
+    double B[FLAME_KC_COUNT] = {0, 0, 0, 0};
+    double span = 0.0;
+    if (!g_tr.recs.empty()) {
+        // every interval on one clock: milliseconds since the first record's start
+        const hipEvent_t ref = g_tr.recs.front().a;
+        std::vector<std::pair<double, double>> iv[FLAME_KC_COUNT];
+        for (const Rec &r : g_tr.recs) {
+            FLAME_HIP(hipEventSynchronize(r.b));
+            float t0 = 0.f, t1 = 0.f;
+            FLAME_HIP(hipEventElapsedTime(&t0, ref, r.a));
+            FLAME_HIP(hipEventElapsedTime(&t1, ref, r.b));
+            iv[r.kclass].emplace_back((double)t0, (double)t1);
+            span = std::max(span, (double)t1);
+        }
+        for (int k = 0; k < FLAME_KC_COUNT; ++k) {
+            auto &v = iv[k];
+            std::sort(v.begin(), v.end());
+            double cur0 = 0.0, cur1 = -1.0, sum = 0.0;
+            for (const auto &p : v) {
+                if (p.first > cur1) {
+                    if (cur1 > cur0) sum += cur1 - cur0;
+                    cur0 = p.first;
+                    cur1 = p.second;
+                } else {
+                    cur1 = std::max(cur1, p.second);
+                }
+            }
+            if (cur1 > cur0) sum += cur1 - cur0;
+            B[k] = sum;
+        }
+    }
+    for (int k = 0; k < FLAME_KC_COUNT; ++k)
+        if (busy_ms) busy_ms[k] = B[k];
+    if (span_ms) *span_ms = span;
     return FLAME_OK;
 }
