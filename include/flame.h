@@ -334,6 +334,7 @@ int flame_trace_busy(double *busy_ms, double *span_ms);
  * plain loops on the calling device (instrumentation, not part of the
  * factorization).  kind:
  *   FLAME_PROBE_MFMA_F64   v_mfma_f64_16x16x4f64 chains, work = rounds per wavefront
+ *                          (a round is 64 instructions: 16 steps of 4 chains)
  *   FLAME_PROBE_MFMA_F32   v_mfma_f32_16x16x4f32 chains, work = rounds
  *   FLAME_PROBE_MFMA_BF16  v_mfma_f32_16x16x32_bf16 chains, work = rounds
  *   FLAME_PROBE_COPY       device copy of work bytes (multiple of 16) from the

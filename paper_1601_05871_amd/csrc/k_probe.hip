@@ -5,8 +5,10 @@
 //
 //   MFMA probes: every wavefront runs kChains independent accumulation chains
 //   of one MFMA instruction (FP64 16x16x4, FP32 16x16x4, BF16 16x16x32) for
-//   `iters` rounds; operands stay in registers, so the loop is bound by the
-//   matrix cores only.  The accumulators are written out once so the work is
+//   `iters` rounds of kUnroll steps; operands stay in registers, so the loop
+//   is bound by the matrix cores only (the unrolled body keeps the copies of
+//   the accumulators between loop iterations, which the compiler inserts at
+//   the back edge, to one per kUnroll * kChains instructions).  The accumulators are written out once so the work is
 //   not removed.  Four wavefronts per workgroup, wg_per_cu workgroups per CU.
 //   Copy probe: a grid-stride copy of `bytes` bytes in 16-byte units (reads
 //   and writes `bytes` each).
@@ -17,6 +19,7 @@ namespace flame {
 namespace {
 
 constexpr int kChains = 4;
+constexpr int kUnroll = 16;
 
 template <int KIND>
 __global__ __launch_bounds__(256) void k_probe_mfma(int64_t iters, float *__restrict__ sink) {
@@ -27,7 +30,9 @@ __global__ __launch_bounds__(256) void k_probe_mfma(int64_t iters, float *__rest
         double a = 1.0 + lane * 1e-3, b = 1.0 - lane * 1e-3;
         for (int64_t i = 0; i < iters; ++i) {
 #pragma unroll
-            for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+            for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
         }
         double s = 0.0;
         for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
@@ -38,7 +43,9 @@ __global__ __launch_bounds__(256) void k_probe_mfma(int64_t iters, float *__rest
         float a = 1.0f + lane * 1e-3f, b = 1.0f - lane * 1e-3f;
         for (int64_t i = 0; i < iters; ++i) {
 #pragma unroll
-            for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+            for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
         }
         float s = 0.f;
         for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
@@ -53,7 +60,9 @@ __global__ __launch_bounds__(256) void k_probe_mfma(int64_t iters, float *__rest
         }
         for (int64_t i = 0; i < iters; ++i) {
 #pragma unroll
-            for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+            for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
         }
         float s = 0.f;
         for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
@@ -94,7 +103,7 @@ extern "C" int flame_probe(int32_t kind, int64_t work, int32_t wg_per_cu, void *
     } else {
         if (buf_bytes < (int64_t)grid * 256 * (int64_t)sizeof(float)) return -5;
         const double per = (kind == FLAME_PROBE_MFMA_BF16) ? 2.0 * 16 * 16 * 32 : 2.0 * 16 * 16 * 4;
-        flops_or_bytes = per * kChains * (double)work * (double)grid * 4.0;  // 4 wavefronts per workgroup
+        flops_or_bytes = per * kChains * kUnroll * (double)work * (double)grid * 4.0;  // 4 wavefronts per workgroup
     }
     hipEvent_t e0, e1;
     FLAME_HIP(hipEventCreate(&e0));

@@ -10,7 +10,7 @@ import argparse
 
 DATASHEET = {"mfma_f64": (78.6, "TFLOP/s"), "mfma_f32": (157.3, "TFLOP/s"), "mfma_bf16": (2500.0, "TFLOP/s"),
              "copy": (8000.0, "GB/s")}
-WORK = {"mfma_f64": 20000, "mfma_f32": 20000, "mfma_bf16": 20000}
+WORK = {"mfma_f64": 2000, "mfma_f32": 2000, "mfma_bf16": 2000}  # rounds of 16 x 4 instructions
 
 
 def main() -> None:
