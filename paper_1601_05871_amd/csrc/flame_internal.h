@@ -103,6 +103,14 @@ int launch_residual_tiled(int64_t n, int64_t nrhs, const double *A0, int64_t lda
                           const double *B, int64_t ldb, double *R, int64_t ldr, double *rowsums, double *part,
                           hipStream_t s);
 size_t residual_workspace_doubles(int64_t n, int64_t nrhs);
+// Many right-hand sides, FP64, one persistent launch per direction
+// (k_trsm_chain.hip): forward U^T Y = B or backward U X = Y in place on X,
+// with the block inverses Dt; column chunks side by side.  flags:
+// trsm_chain_flags(n, nrhs) ints (cleared here), err: one int set to 1 if a
+// wait gave up (the results are then NaN).
+int trsm_chain_flags(int64_t n, int64_t nrhs);
+int launch_trsm_chain(bool forward, int64_t n, int64_t nrhs, const double *U, int64_t ldu, const double *Dt,
+                      double *X, int64_t ldx, int32_t *flags, int32_t *err, hipStream_t s);
 template <typename T>
 int launch_trsv_fwd(int64_t n, int64_t nrhs, const T *U, int64_t ldu, T *B, int64_t ldb, hipStream_t s);
 template <typename T>

@@ -16,6 +16,7 @@
 //        tol the true residual b - A0 x is formed; if that eta is still above
 //        tol the iteration restarts from it.
 //   AUTO IR while eta at least halves per step, then CG from the current x.
+#include <algorithm>
 #include <cmath>
 #include <utility>
 #include <vector>
@@ -26,8 +27,13 @@ using namespace flame;
 
 namespace {
 
-constexpr int kTb = 128;     // row block of the single-launch solves
-constexpr int kFastRhs = 8;  // right-hand sides handled column by column
+constexpr int kTb = 128;  // row block of the single-launch solves
+// Right-hand sides solved column by column with the one-column kernels (n =
+// 16384: 1.63 ms per column for both directions); from 3 columns on the
+// matrix-core chain solves are faster (4.3 ms for 16 columns, 11.5 ms for 64).
+constexpr int kColumnRhs = 2;
+// Right-hand sides of the tiled residual (more use the row-block product).
+constexpr int kTiledRhs = 8;
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -46,10 +52,11 @@ class Carver {
 };
 
 struct SolveWs {
-    bool fast = false;
-    // single-launch solves (fast path)
+    bool fast = false;   // nrhs <= kColumnRhs: column-by-column solves
+    bool tiled = false;  // nrhs <= kTiledRhs: tiled residual
+    // FP64 solves
     double *Dt = nullptr;      // nblk blocks of 128 x 128: U_qq^{-T}
-    int32_t *flags = nullptr;  // nblk
+    int32_t *flags = nullptr;  // nblk, or one per row block and column chunk of the chain solves
     int32_t *err = nullptr;    // 1
     double *part = nullptr;    // partials of the tiled residual
     // refinement
@@ -59,14 +66,17 @@ struct SolveWs {
     double *rho = nullptr, *rho_old = nullptr, *pq = nullptr;                       // nrhs each
 };
 
-int solve_ws(int64_t n, int64_t nrhs, bool fast, bool refine, bool cg, SolveWs *w) {
+int solve_ws(int64_t n, int64_t nrhs, bool f64, bool refine, bool cg, SolveWs *w) {
     const int64_t nblk = (n + kTb - 1) / kTb;
+    const bool fast = f64 && nrhs <= kColumnRhs;
+    const bool tiled = f64 && nrhs <= kTiledRhs;
     const size_t col = (size_t)n * (size_t)nrhs * sizeof(double);
     Carver c;
-    const size_t oDt = fast ? c.add((size_t)nblk * kTb * kTb * sizeof(double)) : 0;
-    const size_t oFl = fast ? c.add((size_t)nblk * sizeof(int32_t)) : 0;
-    const size_t oEr = fast ? c.add(sizeof(int32_t)) : 0;
-    const size_t oPa = (fast && refine) ? c.add(residual_workspace_doubles(n, nrhs) * sizeof(double)) : 0;
+    const size_t oDt = f64 ? c.add((size_t)nblk * kTb * kTb * sizeof(double)) : 0;
+    const size_t nflags = fast ? (size_t)nblk : (size_t)trsm_chain_flags(n, nrhs);
+    const size_t oFl = f64 ? c.add(nflags * sizeof(int32_t)) : 0;
+    const size_t oEr = f64 ? c.add(sizeof(int32_t)) : 0;
+    const size_t oPa = (tiled && refine) ? c.add(residual_workspace_doubles(n, nrhs) * sizeof(double)) : 0;
     const size_t oB0 = refine ? c.add(col) : 0;
     const size_t oR = refine ? c.add(col) : 0;
     const size_t oZ = cg ? c.add(col) : 0;
@@ -85,12 +95,13 @@ int solve_ws(int64_t n, int64_t nrhs, bool fast, bool refine, bool cg, SolveWs *
     char *b = static_cast<char *>(base);
     auto D = [&](size_t o) { return reinterpret_cast<double *>(b + o); };
     w->fast = fast;
-    if (fast) {
+    w->tiled = tiled;
+    if (f64) {
         w->Dt = D(oDt);
         w->flags = reinterpret_cast<int32_t *>(b + oFl);
         w->err = reinterpret_cast<int32_t *>(b + oEr);
-        if (refine) w->part = D(oPa);
     }
+    if (tiled && refine) w->part = D(oPa);
     if (refine) {
         w->b0 = D(oB0);
         w->r = D(oR);
@@ -133,6 +144,9 @@ int apply_inverse(int64_t n, int64_t nrhs, const T *U, int64_t ldu, T *X, int64_
             }
             return FLAME_OK;
         }
+        int rc = launch_trsm_chain(true, n, nrhs, U, ldu, w.Dt, X, ldx, w.flags, w.err, s);
+        if (rc) return rc;
+        return launch_trsm_chain(false, n, nrhs, U, ldu, w.Dt, X, ldx, w.flags, w.err, s);
     }
     int rc = launch_trsv_fwd<T>(n, nrhs, U, ldu, X, ldx, s);
     if (rc) return rc;
@@ -143,7 +157,7 @@ int apply_inverse(int64_t n, int64_t nrhs, const T *U, int64_t ldu, T *X, int64_
 // when rowsums != nullptr.
 int apply_a0(int64_t n, int64_t nrhs, const double *A0, int64_t lda0, const double *X, int64_t ldx, const double *B,
              double *R, double *rowsums, const SolveWs &w, hipStream_t s) {
-    if (w.fast) return launch_residual_tiled(n, nrhs, A0, lda0, X, ldx, B, n, R, n, rowsums, w.part, s);
+    if (w.tiled) return launch_residual_tiled(n, nrhs, A0, lda0, X, ldx, B, n, R, n, rowsums, w.part, s);
     if (B != nullptr) return launch_symm(n, nrhs, -1.0, A0, lda0, X, ldx, 1.0, B, n, R, n, rowsums, s);
     return launch_symm(n, nrhs, 1.0, A0, lda0, X, ldx, 0.0, nullptr, n, R, n, rowsums, s);
 }
@@ -155,7 +169,7 @@ int eta_to_host(int64_t n, int64_t nrhs, const double *X, int64_t ldx, const Sol
     if (rc) return rc;
     int32_t err_h = 0;
     FLAME_HIP(hipMemcpyAsync(eta_h, w.eta + nrhs, sizeof(double), hipMemcpyDeviceToHost, s));
-    if (w.fast) FLAME_HIP(hipMemcpyAsync(&err_h, w.err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FLAME_HIP(hipMemcpyAsync(&err_h, w.err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     FLAME_HIP(hipStreamSynchronize(s));
     if (err_h != 0) return FLAME_ERR_HIP;  // a single-launch solve gave up waiting (results are NaN)
     return FLAME_OK;
@@ -163,15 +177,12 @@ int eta_to_host(int64_t n, int64_t nrhs, const double *X, int64_t ldx, const Sol
 
 int refine_solve(int64_t n, int64_t nrhs, const double *U, int64_t ldu, double *X, int64_t ldx,
                  const flame_refine_t &ref, flame_solve_report_t *report, hipStream_t s) {
-    const bool fast = nrhs <= kFastRhs;
     const bool may_cg = ref.method != FLAME_REFINE_IR;
     SolveWs w;
-    int rc = solve_ws(n, nrhs, fast, true, may_cg, &w);
+    int rc = solve_ws(n, nrhs, true, true, may_cg, &w);
     if (rc) return rc;
-    if (fast) {
-        rc = fast_prepare(n, U, ldu, w, s);
-        if (rc) return rc;
-    }
+    rc = fast_prepare(n, U, ldu, w, s);
+    if (rc) return rc;
     rc = launch_copy_cols(n, nrhs, X, ldx, w.b0, n, s);
     if (rc) return rc;
     rc = apply_inverse<double>(n, nrhs, U, ldu, X, ldx, w, s);
@@ -279,16 +290,14 @@ extern "C" int flame_solve(int32_t dtype, int64_t n, int64_t nrhs, const void *U
     if (refine != nullptr)
         return refine_solve(n, nrhs, static_cast<const double *>(U), ldu, static_cast<double *>(B), ldb, *refine,
                             report, s);
-    const bool fast = dtype == FLAME_F64 && nrhs <= kFastRhs;
     SolveWs w;
-    int rc = solve_ws(n, nrhs, fast, false, false, &w);
+    int rc = solve_ws(n, nrhs, dtype == FLAME_F64, false, false, &w);
     if (rc) return rc;
     if (dtype == FLAME_F64) {
         const double *Ud = static_cast<const double *>(U);
-        if (fast) {
-            rc = fast_prepare(n, Ud, ldu, w, s);
-            if (rc) return rc;
-        }
+        rc = fast_prepare(n, Ud, ldu, w, s);
+        if (rc) return rc;
+        // asynchronous: a solve whose bounded wait gave up writes NaN
         return apply_inverse<double>(n, nrhs, Ud, ldu, static_cast<double *>(B), ldb, w, s);
     }
     return apply_inverse<float>(n, nrhs, static_cast<const float *>(U), ldu, static_cast<float *>(B), ldb, w, s);

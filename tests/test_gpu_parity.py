@@ -386,6 +386,43 @@ def _forward_bound(A0, eta_gpu, eta_oracle):
     return one(eta_gpu) + one(eta_oracle)
 
 
+@pytest.mark.parametrize("n,nrhs", [(100, 9), (128, 16), (129, 17), (700, 40), (1000, 64), (1281, 65),
+                                    (2500, 130), (3000, 33)])
+def test_solve_many_rhs(n, nrhs):
+    """The matrix-core chain solves (more than 8 right-hand sides): ragged
+    last row block, one to three 64-column launches, split sums; against the
+    oracle's substitutions."""
+    A = inputs.spd_bbt(n, 30)
+    Uo, _ = oracle.potrf(A, threads=8)
+    B = inputs.rhs(n, nrhs, 30)
+    Xo = oracle.solve(np.triu(Uo), B)
+    Ud = to_dev(A, ld=n + 3)
+    assert int(fl.factor(Ud, variant=3, nb=128).item()) == 0
+    Bd = to_dev(B, ld=n + 5)
+    fl.solve(Ud, Bd)
+    X = to_host(Bd)
+    assert np.all(np.isfinite(X))
+    assert np.max(np.abs(X - Xo)) <= 1e-12 * max(1.0, np.max(np.abs(Xo)))
+    assert oracle.solve_backward_error(A, X, B) <= 1e-14
+
+
+def test_solve_many_rhs_exact_structure():
+    """min(i, j) factor U_ij = d_j and right-hand sides B = U^T U X for an
+    integer X: both substitutions are exact in FP64 (every intermediate is an
+    integer times a power of two), so X comes back bit for bit."""
+    n, nrhs = 777, 20
+    A = inputs.minij_scaled(n)
+    U = inputs.minij_factor(n)
+    g = np.random.Generator(np.random.PCG64(3))
+    Xi = g.integers(-4, 5, size=(n, nrhs)).astype(np.float64)
+    B = np.asfortranarray(U.T @ (U @ Xi))
+    Ud = to_dev(A)
+    assert int(fl.factor(Ud, variant=3, nb=128).item()) == 0
+    Bd = to_dev(B)
+    fl.solve(Ud, Bd)
+    assert np.array_equal(to_host(Bd), Xi)
+
+
 @pytest.mark.parametrize("trail", ["f32", "bf16"])
 @pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
 @pytest.mark.parametrize("nrhs", [1, 64])
