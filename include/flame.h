@@ -261,38 +261,73 @@ int flame_op_gemm_tn(int32_t dtype, int32_t trail, int32_t upper, int64_t mr, in
 
 /* ---- selector and autotuner ---------------------------------------------- */
 
-/* Loads the weights of the learned (variant, nb) selector: a 3-layer FP32 MLP
+/* The selector's classes are the library's distinct ways to solve an SPD
+ * system A x = b (or a batch of them, all of order n) to the accuracy of the
+ * data: FP64 factorizations reach backward error <= 1e-13, the mixed classes
+ * refine to it.  (The paper chooses its task granularity by hand; this is the
+ * learned replacement for that choice.)
+ *   class  program
+ *    0     flame_factor RIGHT nb 512 (512 / 256 / 128 by position) + flame_solve
+ *    1     RIGHT nb 256, FLAME_OPT_FIXED_NB            + flame_solve
+ *    2     RIGHT nb 128, FLAME_OPT_FIXED_NB            + flame_solve
+ *    3     RIGHT nb 64, FLAME_OPT_FIXED_NB             + flame_solve
+ *    4     LEFT nb 128                                 + flame_solve
+ *    5     LEFT nb 256                                 + flame_solve
+ *    6     BORDERED nb 256                             + flame_solve
+ *    7     flame_batched_factor (n <= 1024)            + flame_solve per matrix
+ *    8     flame_solve_mixed, FP32 products, FLAME_REFINE_AUTO   (FP64 only)
+ *    9     flame_solve_mixed, BF16 products, FLAME_REFINE_AUTO   (FP64 only)
+ *   10     flame_solve_mixed, FP32 products, FLAME_REFINE_CG     (FP64 only)
+ *   11     flame_solve_mixed, BF16 products, FLAME_REFINE_CG     (FP64 only) */
+typedef struct {
+    int32_t cls;       /* class number */
+    int32_t variant;   /* flame_variant_t */
+    int32_t nb;        /* block size (0 = the library's default schedule) */
+    int32_t trail;     /* flame_trail_t: NATIVE, or the mixed solve's products */
+    int32_t flags;     /* FLAME_OPT_* for flame_factor */
+    int32_t method;    /* FLAME_REFINE_* of the mixed solve (classes 8..11) */
+    int32_t batched;   /* 1: flame_batched_factor */
+    int32_t reserved;
+} flame_choice_t;
+
+/* Loads the weights of the learned selector: a 3-layer FP32 MLP
  * in -> 64 -> 64 -> FLAME_SEL_CLASSES with ReLU, features (log2 n, log2 batch,
- * is_f64, is_f32, log10 kappa), classes = variant in {1,2,3} x nb in
- * {32,64,128,256} (class c -> variant 1 + c / 4, nb = 32 << (c % 4)).
- * `w` (host) holds W1[64][5], b1[64], W2[64][64], b2[64], W3[12][64], b3[12],
- * row-major, count = FLAME_SEL_NPARAM floats.  Copied to each device on first
- * use.  w == NULL with count == 0 unloads the weights (VAR_AUTO then uses the
- * autotuner's table).  Errors: -1 w, -2 count. */
+ * is_f64, is_f32, log10 kappa).  `w` (host) holds W1[64][5], b1[64],
+ * W2[64][64], b2[64], W3[12][64], b3[12], row-major, count = FLAME_SEL_NPARAM
+ * floats.  Copied to each device on first use.  w == NULL with count == 0
+ * unloads the weights (VAR_AUTO then uses the autotuner's table).
+ * Errors: -1 w, -2 count. */
 #define FLAME_SEL_FEATURES 5
 #define FLAME_SEL_HIDDEN 64
 #define FLAME_SEL_CLASSES 12
 #define FLAME_SEL_NPARAM (64 * 5 + 64 + 64 * 64 + 64 + 12 * 64 + 12)
 int flame_selector_load(const float *w, int64_t count);
 
-/* Runs the selector's inference kernel for one shape; returns (variant, nb)
- * in host memory.  Synchronous.  Without loaded weights returns
+/* The program of class `cls` (host).  Errors: -1 cls, -2 choice. */
+int flame_select_class(int32_t cls, flame_choice_t *choice);
+
+/* Runs the selector's inference kernel for one shape (batch matrices of order
+ * n, condition estimate kappa, 0 = unknown) and returns the highest-ranked
+ * class that can run it (host).  Synchronous.  Without loaded weights returns
  * FLAME_ERR_UNSUPPORTED.  Errors: -1 n, -2 batch, -3 dtype, -4 kappa,
- * -5 variant, -6 nb. */
-int flame_select(int64_t n, int64_t batch, int32_t dtype, double kappa, int32_t *variant, int32_t *nb);
+ * -5 choice. */
+int flame_select(int64_t n, int64_t batch, int32_t dtype, double kappa, flame_choice_t *choice);
 
 /* Batch inference: `count` feature rows (host, count x FLAME_SEL_FEATURES)
  * -> class logits (host, count x FLAME_SEL_CLASSES).  Synchronous. */
 int flame_select_logits(const float *features, int64_t count, float *logits);
 
-/* Exhaustive autotuner: times every candidate (variant in {1,2,3} x nb in
- * {32,64,128,256}) for an n x n factorization of `dtype` on a scratch copy of
- * A (A itself is restored), `reps` timed runs each after one warm-up, and
- * writes the median milliseconds per candidate to times_ms (host, 12 doubles,
- * class order as for the selector; a failed candidate gets +inf).  Records the
- * best candidate in the library's tuning table used by VAR_AUTO.
- * Synchronous.  Errors: -1 dtype, -2 n, -3 A, -4 lda, -5 reps, -6 times_ms. */
-int flame_autotune(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t reps, double *times_ms,
+/* Exhaustive autotuner: times every class that can run (see above) for
+ * solving A x = b, b = (1, ..., 1), with A the given n x n SPD matrix (left
+ * unchanged): milliseconds per matrix, the median of `reps` runs after a
+ * warm-up (the warm-up alone when it takes more than 2 s), into times_ms
+ * (host, 12 doubles; +inf for a class that cannot run, breaks down or does
+ * not converge).  The batched class factors min(batch, 2 GiB / matrix)
+ * replicas of A in one launch; its time per matrix adds class 0's plain
+ * solve.  Records the fastest of classes 0..6 in the library's tuning table
+ * used by VAR_AUTO.  Synchronous.
+ * Errors: -1 dtype, -2 n, -3 A, -4 lda, -5 batch (< 1), -6 reps, -7 times_ms. */
+int flame_autotune(int32_t dtype, int64_t n, void *A, int64_t lda, int64_t batch, int32_t reps, double *times_ms,
                    void *stream);
 
 /* ---- per-kernel timing (instrumentation) --------------------------------- */

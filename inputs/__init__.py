@@ -19,6 +19,16 @@ Cholesky benchmarks):
   laplacian1d   tridiag(-1, 2, -1)
   batch         n_i ~ U{lo..hi} (PCG64(seed).integers, endpoint inclusive),
                 then each B_i from the same stream and A_i = B_i B_i^T + n_i I
+  spd_wishart_shift_torch
+                A = B B^T / n + sigma I, B ~ N(0,1) from PCG64(seed), sigma =
+                4 / (kappa - 1): the eigenvalues of B B^T / n fill [0, 4]
+                (Marchenko-Pastur, square case), so kappa(A) ~ (4 + sigma) /
+                sigma = kappa at the cost of one product (the selector's sweep
+                shapes; spd_kappa fixes the spectrum exactly but needs a QR)
+  selector_shapes
+                (n, batch, dtype, kappa): n and batch log-uniform on [64, 32768]
+                and [1, 10000], FP64 with probability 3/4, kappa log-uniform on
+                [1, 1e6]
 """
 from __future__ import annotations
 
@@ -111,6 +121,38 @@ def spd_kappa_torch(n: int, kappa: float, seed: int, device):
     A = torch.triu(A)
     A = A + torch.triu(A, 1).T
     return A.T.contiguous().T
+
+
+def spd_wishart_shift_torch(n: int, kappa: float, seed: int, device, dtype=None):
+    """A = B B^T / n + sigma I with sigma = 4 / (kappa - 1) (kappa <= 1.01 is
+    taken as 1.01), formed on ``device``; column-major, exactly symmetric."""
+    import torch
+
+    sigma = 4.0 / (max(float(kappa), 1.01) - 1.0)
+    B = torch.from_numpy(gaussian(n, n, seed)).to(device)
+    A = B @ B.T
+    del B
+    A.mul_(1.0 / n)
+    A.diagonal().add_(sigma)
+    A = torch.triu(A)
+    A = A + torch.triu(A, 1).T
+    if dtype is not None:
+        A = A.to(dtype)
+    return A.T.contiguous().T
+
+
+def selector_shapes(count: int, seed: int) -> list[tuple[int, int, str, float]]:
+    """`count` seeded (n, batch, dtype, kappa) shapes for the selector's
+    timing sweep."""
+    g = _rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(round(np.exp(g.uniform(np.log(64.0), np.log(32768.0)))))
+        b = int(round(np.exp(g.uniform(0.0, np.log(10000.0)))))
+        dt = "f64" if g.uniform() < 0.75 else "f32"
+        kappa = float(10.0 ** g.uniform(0.0, 6.0))
+        out.append((n, b, dt, kappa))
+    return out
 
 
 def rhs(n: int, nrhs: int, seed: int = 0) -> np.ndarray:

@@ -38,6 +38,7 @@ EXPORTS = (
     "flame_op_gemm_tn", "flame_selector_load", "flame_select", "flame_select_logits", "flame_autotune",
     "flame_trace_enable", "flame_trace_collect", "flame_status_string", "flame_version",
     "flame_solve_mixed", "flame_shutdown", "flame_batched_factor_noalloc", "flame_trace_busy", "flame_probe",
+    "flame_select_class",
 )
 PROBE = {"mfma_f64": 0, "mfma_f32": 1, "mfma_bf16": 2, "copy": 3}
 NOALLOC_MAX_BATCH = 262144
@@ -64,6 +65,18 @@ class Refine(ctypes.Structure):
 class SolveReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("method", ctypes.c_int32), ("eta_max", ctypes.c_double),
                 ("shift", ctypes.c_double), ("factor_info", ctypes.c_int32), ("attempts", ctypes.c_int32)]
+
+
+class Choice(ctypes.Structure):
+    _fields_ = [("cls", ctypes.c_int32), ("variant", ctypes.c_int32), ("nb", ctypes.c_int32),
+                ("trail", ctypes.c_int32), ("flags", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("batched", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def _choice_dict(c: Choice) -> dict:
+    return {"cls": c.cls, "variant": c.variant, "nb": c.nb,
+            "trail": {v: k for k, v in TRAIL.items()}[c.trail], "fixed_nb": bool(c.flags & OPT_FIXED_NB),
+            "method": {v: k for k, v in REFINE.items()}[c.method], "batched": bool(c.batched)}
 
 
 class MixedOpts(ctypes.Structure):
@@ -94,9 +107,10 @@ def lib() -> ctypes.CDLL:
     L.flame_op_trsm.argtypes = [i32, i64, i64, vp, i64, vp, i64, vp]
     L.flame_op_gemm_tn.argtypes = [i32, i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp]
     L.flame_selector_load.argtypes = [vp, i64]
-    L.flame_select.argtypes = [i64, i64, i32, dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.flame_select.argtypes = [i64, i64, i32, dbl, ctypes.POINTER(Choice)]
+    L.flame_select_class.argtypes = [i32, ctypes.POINTER(Choice)]
     L.flame_select_logits.argtypes = [vp, i64, vp]
-    L.flame_autotune.argtypes = [i32, i64, vp, i64, i32, vp, vp]
+    L.flame_autotune.argtypes = [i32, i64, vp, i64, i64, i32, vp, vp]
     L.flame_trace_enable.argtypes = [i32]
     L.flame_trace_collect.argtypes = [vp, vp, vp, vp]
     L.flame_trace_busy.argtypes = [vp, vp]
@@ -356,12 +370,20 @@ def selector_load(w) -> None:
     _check("flame_selector_load", rc)
 
 
-def select(n: int, batch: int = 1, dtype: int = F64, kappa: float = 0.0):
-    """(variant, nb) chosen by the loaded selector (runs its HIP kernel)."""
-    v, b = ctypes.c_int32(0), ctypes.c_int32(0)
-    rc = lib().flame_select(int(n), int(batch), int(dtype), float(kappa), ctypes.byref(v), ctypes.byref(b))
+def select(n: int, batch: int = 1, dtype: int = F64, kappa: float = 0.0) -> dict:
+    """The class the loaded selector ranks highest for this shape (runs its
+    HIP kernel): a dict with the class number and its program."""
+    c = Choice()
+    rc = lib().flame_select(int(n), int(batch), int(dtype), float(kappa), ctypes.byref(c))
     _check("flame_select", rc)
-    return int(v.value), int(b.value)
+    return _choice_dict(c)
+
+
+def select_class(cls: int) -> dict:
+    """The program of selector class ``cls``."""
+    c = Choice()
+    _check("flame_select_class", lib().flame_select_class(int(cls), ctypes.byref(c)))
+    return _choice_dict(c)
 
 
 def select_logits(features):
@@ -375,15 +397,17 @@ def select_logits(features):
     return out
 
 
-def autotune(A, reps: int = 2):
-    """Median ms of every (variant, nb) candidate for factoring A (left
-    unchanged); 12 values in class order; records the best for VAR_AUTO."""
+def autotune(A, batch: int = 1, reps: int = 2):
+    """Milliseconds per matrix of every selector class for solving A x = b
+    (A left unchanged; +inf where a class cannot run or fails), 12 values in
+    class order; records the fastest single-matrix factorization for
+    VAR_AUTO.  ``batch``: the batch size the batched class is timed at."""
     import numpy as np
 
-    n = A.shape[0]
+    n = _square("A", A)
     t = np.zeros(SEL_CLASSES, dtype=np.float64)
-    rc = lib().flame_autotune(_dtype_code(A), n, A.data_ptr(), _colmajor_ld(A), int(reps), t.ctypes.data,
-                              _stream_ptr())
+    rc = lib().flame_autotune(_dtype_code(A), n, A.data_ptr(), _colmajor_ld(A), int(batch), int(reps),
+                              t.ctypes.data, _stream_ptr())
     _check("flame_autotune", rc)
     return t
 

@@ -31,12 +31,7 @@ int normalize_opts(const flame_opts_t *in, int32_t dtype, int64_t n, flame_opts_
     if (o->graph < 0 || o->graph > 1) return -5;
     if ((o->flags & ~FLAME_OPT_FIXED_NB) != 0) return -5;
     if (o->reserved[0] != 0 || o->reserved[1] != 0) return -5;
-    if (o->variant == FLAME_VAR_AUTO) {
-        int32_t v = FLAME_VAR_RIGHT, nb = 0;
-        choose_variant(dtype, n, 1, &v, &nb);
-        o->variant = v;
-        if (o->nb == 0) o->nb = nb;
-    }
+    if (o->variant == FLAME_VAR_AUTO) choose_variant(dtype, n, 1, o);
     if (o->nb == 0) o->nb = kDefaultNb;
     return 0;
 }

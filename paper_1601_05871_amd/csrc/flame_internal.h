@@ -177,9 +177,10 @@ void drop_batched_graphs();
 void selector_forget_devices();
 hipStream_t ctx_side_stream(DevCtx *c);
 hipStream_t ctx_aux_stream(DevCtx *c);
-// Variant and block size for FLAME_VAR_AUTO: the learned selector when its
-// weights are loaded, else the autotuner's table, else (RIGHT, 256).
-void choose_variant(int32_t dtype, int64_t n, int64_t batch, int32_t *variant, int32_t *nb);
+// Variant, block size and flags for FLAME_VAR_AUTO (o->nb kept when set): the
+// single-matrix factorization the learned selector ranks highest when its
+// weights are loaded, else the autotuner's table, else RIGHT with nb 512.
+void choose_variant(int32_t dtype, int64_t n, int64_t batch, flame_opts_t *o);
 hipEvent_t ctx_event(DevCtx *c, int i);
 
 // Loop drivers (driver.cpp).

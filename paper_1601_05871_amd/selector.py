@@ -1,26 +1,29 @@
-"""Learned (variant, block size) selector: timing sweep, training, evaluation.
+"""Learned selector: timing sweep, training, evaluation.
 
 The selector is a 3-layer FP32 MLP (features -> 64 -> 64 -> 12, ReLU) whose
 inference runs in the library's HIP kernel (``flame_select``).  Its 12
-classes are variant in {1 bordered, 2 left-looking, 3 right-looking} x block
-size in {32, 64, 128, 256} (class c -> variant 1 + c // 4, nb = 32 << c % 4).
-Features: log2 n, log2 batch, is_f64, is_f32, log10 kappa (0 when unknown).
+classes are the library's distinct programs for solving SPD systems of one
+order (``flame.h``: right-looking at 512 by position and at fixed 256 / 128 /
+64, left-looking 128 / 256, bordered 256, the batched persistent kernel, and
+the mixed-precision solve with FP32 or BF16 products refined by IR-then-CG or
+by CG).  Features: log2 n, log2 batch, is_f64, is_f32, log10 kappa (0 when
+unknown).  The batch size matters through the batched class (one launch for
+the whole batch against one factorization per matrix), kappa through the
+mixed classes (refinement steps grow with kappa u).
 
 Pipeline (each step a subcommand):
 
   sweep  (GPU) the library's exhaustive autotuner (``flame_autotune``) times
-         all 12 candidates for seeded orders n, log-uniform in [64, 32768],
-         FP64 and FP32, on A = B B^T + n I; writes the timing table.
-  train  (CPU) fits the MLP to the table.  The loss is the expected
-         slowdown  sum_c softmax(z)_c t_c / t_best  (cost-sensitive, so
-         near-ties cost little), optionally plus a cross-entropy term on the
-         fastest class (--ce-weight); full-batch Adam.  The looped factorization's
-         per-matrix time does not depend on the batch size or on kappa, so
-         every timed order is replicated over seeded batch sizes
-         (log-uniform in [1, 10000]) and kappa values (10^U[0, 8]).
-  eval   regret t(chosen) / t(best) - 1 of the selector on the held-out
-         orders (timed by the same sweep), from the numpy forward pass and,
-         with --device, from the HIP kernel.
+         every class, per matrix, on seeded shapes (n, batch, dtype, kappa):
+         n log-uniform in [64, 32768], batch in [1, 10000], FP64 with
+         probability 3/4, kappa in [1, 1e6] (A = B B^T / n + sigma I, sigma
+         setting kappa); writes the timing table.
+  train  (CPU) fits the MLP to the table.  The loss is the expected slowdown
+         sum_c softmax(z)_c t_c / t_best over the classes that can run
+         (cost-sensitive, so near-ties cost little); full-batch Adam.
+  eval   regret t(chosen) / t(best) - 1 on the held-out shapes, from the numpy
+         forward pass and, with --device, from the HIP kernel; beside it the
+         regret of the best single fixed class.
 
     python -m paper_1601_05871_amd.selector sweep --out sweep.json
     python -m paper_1601_05871_amd.selector train --sweep sweep.json --out weights.json
@@ -42,9 +45,18 @@ NPARAM = H * F + H + H * H + H + C * H + C
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "selector_data", "weights.json")
 
+# class -> (name, runs FP32 data, largest order) as in flame.h
+CLASS_NAMES = ("right-512", "right-256-fixed", "right-128-fixed", "right-64-fixed", "left-128", "left-256",
+               "bordered-256", "batched", "mixed-f32-auto", "mixed-bf16-auto", "mixed-f32-cg", "mixed-bf16-cg")
 
-def class_choice(c: int) -> tuple[int, int]:
-    return 1 + c // 4, 32 << (c % 4)
+
+def feasible(c: int, n: int, is_f64: bool) -> bool:
+    """Whether class c can run a shape (the library's rule)."""
+    if c == 7:
+        return n <= 1024
+    if c >= 8:
+        return is_f64
+    return True
 
 
 def features(n: int, batch: int, is_f64: bool, kappa: float = 0.0) -> np.ndarray:
@@ -141,52 +153,47 @@ def train(X, S, epochs: int = 4000, lr: float = 3e-3, seed: int = 0, ce_weight: 
 
 # ---- data -----------------------------------------------------------------------
 
-def sample_orders(count: int, seed: int, lo: int = 64, hi: int = 32768) -> list[int]:
-    g = np.random.Generator(np.random.PCG64(seed))
-    return sorted({int(round(math.exp(x))) for x in g.uniform(math.log(lo), math.log(hi), size=count)})
-
-
-def normalized(times: np.ndarray) -> np.ndarray:
+def normalized(times) -> np.ndarray:
+    """t_c / t_best; classes that cannot run or failed get 10x the slowest."""
     t = np.array(times, dtype=np.float64)
     finite = np.isfinite(t)
     worst = np.max(t[finite]) if finite.any() else 1.0
-    t[~finite] = 10.0 * worst  # failed candidates: heavily penalized
+    t[~finite] = 10.0 * worst
     return t / np.min(t)
 
 
-def expand(records, reps_per_record: int = 16, seed: int = 0):
-    """Rows (features, normalized times): each timed (n, dtype) replicated
-    over seeded batch sizes and kappa values, which do not change the label."""
-    g = np.random.Generator(np.random.PCG64(seed))
-    X, S = [], []
-    for r in records:
-        s = normalized(r["times_ms"])
-        for _ in range(reps_per_record):
-            batch = int(round(math.exp(g.uniform(0.0, math.log(10000.0)))))
-            kappa = 10.0 ** g.uniform(0.0, 8.0)
-            X.append(features(r["n"], batch, r["dtype"] == "f64", kappa))
-            S.append(s)
-    return np.array(X, dtype=np.float64), np.array(S)
+def rows(records):
+    X = np.array([features(r["n"], r["batch"], r["dtype"] == "f64", r["kappa"]) for r in records], dtype=np.float64)
+    S = np.array([normalized(r["times_ms"]) for r in records])
+    return X, S
+
+
+def choose(p: dict, r: dict) -> int:
+    """The selector's class for a record: argmax of the logits over the
+    classes that can run it (as flame_select)."""
+    z, _ = forward(p, features(r["n"], r["batch"], r["dtype"] == "f64", r["kappa"])[None, :])
+    ok = [c for c in range(C) if feasible(c, r["n"], r["dtype"] == "f64")]
+    return max(ok, key=lambda c: z[0][c])
 
 
 def regret_table(p: dict, records) -> dict:
-    rows = []
+    out_rows = []
     for r in records:
-        f = features(r["n"], 1, r["dtype"] == "f64", 0.0)
-        z, _ = forward(p, f[None, :])
-        c = int(np.argmax(z[0]))
+        c = choose(p, r)
         s = normalized(r["times_ms"])
-        rows.append({"n": r["n"], "dtype": r["dtype"], "chosen": class_choice(c), "best": class_choice(int(np.argmin(s))),
-                     "regret": float(s[c] - 1.0)})
-    reg = np.array([x["regret"] for x in rows])
-    # baseline: the single (variant, nb) with the lowest mean regret on these shapes
+        out_rows.append({"n": r["n"], "batch": r["batch"], "dtype": r["dtype"], "kappa": r["kappa"],
+                         "chosen": CLASS_NAMES[c], "best": CLASS_NAMES[int(np.argmin(s))],
+                         "regret": float(s[c] - 1.0)})
+    reg = np.array([x["regret"] for x in out_rows])
+    # baseline: the single fixed class with the lowest mean regret on these shapes
     S = np.array([normalized(r["times_ms"]) for r in records]) - 1.0
     fixed = int(np.argmin(S.mean(axis=0)))
     return {"mean_regret": float(reg.mean()), "median_regret": float(np.median(reg)),
             "p95_regret": float(np.percentile(reg, 95)), "max_regret": float(reg.max()),
             "exact_best_fraction": float(np.mean(reg == 0.0)),
-            "best_fixed_choice": class_choice(fixed), "best_fixed_mean_regret": float(S[:, fixed].mean()),
-            "best_fixed_max_regret": float(S[:, fixed].max()), "rows": rows}
+            "chosen_classes": sorted({x["chosen"] for x in out_rows}),
+            "best_fixed_choice": CLASS_NAMES[fixed], "best_fixed_mean_regret": float(S[:, fixed].mean()),
+            "best_fixed_max_regret": float(S[:, fixed].max()), "rows": out_rows}
 
 
 # ---- commands ---------------------------------------------------------------------
@@ -200,30 +207,24 @@ def cmd_sweep(args) -> int:
 
     fl.lib()
     dev = torch.device("cuda:0")
-    if args.orders:
-        sets = {"probe": [int(x) for x in args.orders.split(",")]}
-    else:
-        sets = {"train": sample_orders(args.count, args.seed, args.lo, args.hi),
-                "heldout": sample_orders(args.heldout, args.seed + 1, args.lo, args.hi)}
-    out = {"command": " ".join(sys.argv), "candidates": [class_choice(c) for c in range(C)], "records": []}
-    for split, orders in sets.items():
-        for n in orders:
-            A64 = inputs.spd_bbt_torch(n, 0, dev)
-            for dt, name in ((torch.float64, "f64"), (torch.float32, "f32")):
-                if name not in args.dtypes.split(","):
-                    continue
-                A = A64 if dt == torch.float64 else A64.to(dt).T.contiguous().T
-                t0 = time.time()
-                reps = 3 if n <= 4096 else (2 if n <= 16384 else 1)
-                t = fl.autotune(A, reps=reps)
-                rec = {"split": split, "n": n, "dtype": name, "reps": reps,
-                       "times_ms": [None if not np.isfinite(x) else round(float(x), 5) for x in t]}
-                out["records"].append(rec)
-                print(f"[sweep] {split} n={n} {name}: best {class_choice(int(np.argmin(t)))} "
-                      f"{np.min(t):.3f} ms ({time.time() - t0:.1f} s)", flush=True)
-                del A
-            del A64
+    sets = {"train": inputs.selector_shapes(args.count, args.seed),
+            "heldout": inputs.selector_shapes(args.heldout, args.seed + 1)}
+    out = {"command": " ".join(sys.argv), "classes": list(CLASS_NAMES), "records": []}
+    for split, shapes in sets.items():
+        for k, (n, batch, dt, kappa) in enumerate(shapes):
+            t0 = time.time()
+            A = inputs.spd_wishart_shift_torch(n, kappa, 7000 + k, dev,
+                                               dtype=torch.float64 if dt == "f64" else torch.float32)
+            reps = 3 if n <= 4096 else (2 if n <= 16384 else 1)
+            t = fl.autotune(A, batch=batch, reps=reps)
+            del A
             torch.cuda.empty_cache()
+            rec = {"split": split, "n": n, "batch": batch, "dtype": dt, "kappa": kappa, "reps": reps,
+                   "times_ms": [None if not np.isfinite(x) else round(float(x), 5) for x in t]}
+            out["records"].append(rec)
+            b = int(np.argmin(t))
+            print(f"[sweep] {split} n={n} batch={batch} {dt} kappa={kappa:.3g}: best {CLASS_NAMES[b]} "
+                  f"{t[b]:.4f} ms/matrix ({time.time() - t0:.1f} s)", flush=True)
             with open(args.out, "w") as f:
                 json.dump(out, f, indent=1)
     return 0
@@ -243,7 +244,7 @@ def _load_records(path, split):
 
 def cmd_train(args) -> int:
     recs = _load_records(args.sweep, "train")
-    X, S = expand(recs, seed=args.seed)
+    X, S = rows(recs)
     p, hist = train(X, S, epochs=args.epochs, lr=args.lr, seed=args.seed, ce_weight=args.ce_weight)
     w = flatten(p)
     res = regret_table(p, recs)
@@ -251,7 +252,7 @@ def cmd_train(args) -> int:
         json.dump({"nparam": NPARAM, "weights": [float(x) for x in w], "train_loss": hist,
                    "train_mean_regret": res["mean_regret"], "sweep": os.path.basename(args.sweep),
                    "command": " ".join(sys.argv)}, f)
-    print(f"trained on {len(recs)} timed shapes ({X.shape[0]} rows); final loss {hist[-1][1]:.4f}; "
+    print(f"trained on {len(recs)} timed shapes; final loss {hist[-1][1]:.4f}; "
           f"train mean regret {res['mean_regret']:.4f}")
     return 0
 
@@ -269,8 +270,8 @@ def cmd_eval(args) -> int:
         fl.selector_load(w)
         agree = 0
         for row, r in zip(res["rows"], recs):
-            v, nb = fl.select(r["n"], 1, fl.F64 if r["dtype"] == "f64" else fl.F32)
-            agree += int((v, nb) == tuple(row["chosen"]))
+            ch = fl.select(r["n"], r["batch"], fl.F64 if r["dtype"] == "f64" else fl.F32, r["kappa"])
+            agree += int(CLASS_NAMES[ch["cls"]] == row["chosen"])
         res["device_agrees"] = f"{agree}/{len(recs)}"
     res["command"] = " ".join(sys.argv)
     text = json.dumps(res, indent=1)
@@ -278,9 +279,9 @@ def cmd_eval(args) -> int:
         with open(args.out, "w") as f:
             f.write(text)
     print(f"held-out: {len(recs)} shapes, mean regret {res['mean_regret']:.4f}, max {res['max_regret']:.4f}, "
-          f"best chosen {res['exact_best_fraction']:.2f}; best fixed {tuple(res['best_fixed_choice'])}: mean "
-          f"{res['best_fixed_mean_regret']:.4f}, max {res['best_fixed_max_regret']:.4f}" + (f", device agrees {res['device_agrees']}"
-                                                             if args.device else ""))
+          f"best chosen {res['exact_best_fraction']:.2f}, classes chosen {res['chosen_classes']}; best fixed "
+          f"{res['best_fixed_choice']}: mean {res['best_fixed_mean_regret']:.4f}, max "
+          f"{res['best_fixed_max_regret']:.4f}" + (f", device agrees {res['device_agrees']}" if args.device else ""))
     return 0
 
 
@@ -297,20 +298,16 @@ def main() -> int:
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("sweep")
     a.add_argument("--out", required=True)
-    a.add_argument("--count", type=int, default=20)
-    a.add_argument("--heldout", type=int, default=8)
-    a.add_argument("--seed", type=int, default=1)
-    a.add_argument("--lo", type=int, default=64)
-    a.add_argument("--hi", type=int, default=32768)
-    a.add_argument("--orders", help="comma-separated orders instead of the seeded sets")
-    a.add_argument("--dtypes", default="f64,f32")
+    a.add_argument("--count", type=int, default=64)
+    a.add_argument("--heldout", type=int, default=24)
+    a.add_argument("--seed", type=int, default=9000)
     b = sub.add_parser("train")
     b.add_argument("--sweep", required=True)
     b.add_argument("--out", required=True)
     b.add_argument("--epochs", type=int, default=12000)
     b.add_argument("--lr", type=float, default=1e-3)
     b.add_argument("--seed", type=int, default=0)
-    b.add_argument("--ce-weight", type=float, default=0.0)
+    b.add_argument("--ce-weight", type=float, default=0.05)
     c = sub.add_parser("eval")
     c.add_argument("--sweep", required=True)
     c.add_argument("--weights", required=True)

@@ -35,7 +35,12 @@ def test_logits_match_numpy_forward():
             b = int(round(2.0 ** X[i, 1]))
             if sel.features(n, b, X[i, 2] == 1.0, 0.0)[:4].tolist() != X[i, :4].tolist() or X[i, 4] != 0.0:
                 continue
-            assert fl.select(n, b, fl.F64 if X[i, 2] else fl.F32) == sel.class_choice(int(np.argmax(zo[i])))
+            f64 = bool(X[i, 2])
+            ok = [c for c in range(12) if sel.feasible(c, n, f64)]
+            want = max(ok, key=lambda c: zo[i][c])
+            if zo[i][want] - max(zo[i][c] for c in ok if c != want) < 1e-3:
+                continue
+            assert fl.select(n, b, fl.F64 if f64 else fl.F32)["cls"] == want
     finally:
         fl.selector_load(None)
 
@@ -52,9 +57,15 @@ def test_autotune_times_every_candidate_and_keeps_A():
     n = 300
     A = inputs.spd_bbt(n, 21)
     Ad = to_dev(A, ld=n + 5)
-    t = fl.autotune(Ad, reps=2)
+    t = fl.autotune(Ad, batch=50, reps=2)
     assert t.shape == (12,) and np.all(np.isfinite(t)) and np.all(t > 0)
     assert np.array_equal(to_host(Ad), A)
+    # FP32 data: the mixed classes cannot run; above order 1024 the batched one
+    t32 = fl.autotune(to_dev(A, dtype=torch.float32), batch=4, reps=1)
+    assert np.all(np.isinf(t32[8:])) and np.all(np.isfinite(t32[:8]))
+    big = inputs.spd_bbt(1100, 22)
+    tb = fl.autotune(to_dev(big), batch=2, reps=1)
+    assert np.isinf(tb[7]) and np.all(np.isfinite(tb[:7])) and np.all(np.isfinite(tb[8:]))
     # VAR_AUTO now takes the tuned candidate; the factor is still the oracle's
     Uo, _ = oracle.potrf(A, threads=8)
     info = fl.factor(Ad, variant=fl.VAR_AUTO, nb=0)
@@ -68,4 +79,6 @@ def test_autotune_reports_failed_candidates_as_inf():
     A = inputs.spd_bbt(n, 3)
     A[10, 10] = -1.0
     t = fl.autotune(to_dev(A), reps=1)
-    assert np.all(np.isinf(t))
+    assert np.all(np.isinf(t[:8]))  # every factorization breaks down
+    # the mixed classes cannot factor it either (a negative diagonal entry)
+    assert np.all(np.isinf(t[8:]))

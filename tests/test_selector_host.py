@@ -24,8 +24,22 @@ def test_param_layout_matches_header():
     assert w[7] == np.float32(p["W1"][1][2])
 
 
-def test_class_mapping():
-    assert [sel.class_choice(c) for c in (0, 3, 4, 11)] == [(1, 32), (1, 256), (2, 32), (3, 256)]
+def test_class_table_matches_library():
+    """The Python class names and feasibility rule agree with the library's
+    class table (flame_select_class)."""
+    for c, name in enumerate(sel.CLASS_NAMES):
+        ch = fl.select_class(c)
+        assert ch["cls"] == c
+        assert ch["batched"] == (name == "batched")
+        assert (ch["trail"] != "native") == name.startswith("mixed")
+        if name.startswith("mixed"):
+            assert ch["trail"] == name.split("-")[1] and ch["method"] == name.split("-")[2]
+        elif name != "batched":
+            variant = {"right": fl.VAR_RIGHT, "left": fl.VAR_LEFT, "bordered": fl.VAR_BORDERED}[name.split("-")[0]]
+            assert ch["variant"] == variant and ch["nb"] == int(name.split("-")[1])
+            assert ch["fixed_nb"] == name.endswith("fixed")
+    assert sel.feasible(7, 1024, True) and not sel.feasible(7, 1025, True)
+    assert sel.feasible(9, 100, True) and not sel.feasible(9, 100, False)
 
 
 def test_forward_matches_plain_loops():
@@ -57,23 +71,39 @@ def test_gradient_matches_finite_differences():
         assert abs((lp - lm) / (2 * h) - grad[k][idx]) <= 1e-6 + 1e-4 * abs(grad[k][idx]), k
 
 
-def test_training_learns_a_known_rule():
-    """Times where the fastest class is a step function of log2 n and dtype:
-    the trained model picks it on held-out orders."""
-    def times(n, f64):
-        t = np.full(12, 2.0)
-        t[11 if n >= 2048 else (5 if f64 else 6)] = 1.0
-        return list(t)
+def _rule_times(n, batch, f64, kappa):
+    """A known rule: batched for small orders in large batches, BF16 mixed for
+    large well-conditioned FP64 systems, right-looking otherwise; infeasible
+    classes +inf (as the autotuner reports them)."""
+    t = np.full(12, 2.0)
+    if n <= 1024 and batch >= 100:
+        t[7] = 1.0
+    elif f64 and n >= 4096 and kappa <= 1e3:
+        t[9] = 1.0
+    else:
+        t[0] = 1.0
+    for c in range(12):
+        if not sel.feasible(c, n, f64):
+            t[c] = np.inf
+    return list(t)
 
-    recs = [{"n": n, "dtype": d, "times_ms": times(n, d == "f64")}
-            for n in sel.sample_orders(30, 0) for d in ("f64", "f32")]
-    X, S = sel.expand(recs, reps_per_record=8)
-    p, hist = sel.train(X, S, epochs=3000)
+
+def test_training_learns_a_known_rule():
+    """The trained model reproduces a rule that depends on n, batch, dtype and
+    kappa on shapes it has not seen."""
+    import inputs
+
+    recs = [{"n": n, "batch": b, "dtype": d, "kappa": k, "times_ms": _rule_times(n, b, d == "f64", k)}
+            for n, b, d, k in inputs.selector_shapes(400, 1)]
+    X, S = sel.rows(recs)
+    p, hist = sel.train(X, S, epochs=3000, lr=3e-3)
     assert hist[-1][1] < hist[0][1]
-    held = [{"n": n, "dtype": d, "times_ms": times(n, d == "f64")}
-            for n in (100, 500, 1000, 5000, 20000) for d in ("f64", "f32")]
+    held = [{"n": n, "batch": b, "dtype": d, "kappa": k, "times_ms": _rule_times(n, b, d == "f64", k)}
+            for n, b, d, k in ((300, 2000, "f64", 10.0), (8000, 1, "f64", 10.0), (8000, 1, "f64", 1e5),
+                               (20000, 1, "f32", 10.0), (600, 1, "f64", 1e5))]
     res = sel.regret_table(p, held)
     assert res["mean_regret"] == 0.0, res
+    assert set(res["chosen_classes"]) == {"batched", "mixed-bf16-auto", "right-512"}
 
 
 def test_features():
@@ -98,4 +128,8 @@ def test_committed_weights_and_evaluation():
     with open(ev) as f:
         res = json.load(f)
     assert 0.0 <= res["mean_regret"] <= res["max_regret"]
-    assert len(res["rows"]) >= 8
+    assert len(res["rows"]) >= 16
+    # the committed evaluation: strictly better than every single fixed class,
+    # and the choice depends on the shape
+    assert res["mean_regret"] < res["best_fixed_mean_regret"]
+    assert len(res["chosen_classes"]) >= 2
