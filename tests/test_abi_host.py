@@ -108,11 +108,18 @@ def test_batched_and_selector_argument_errors():
     assert L.flame_batched_factor(0, -1, FAKE, FAKE, FAKE, FAKE, None, None) == -2
     assert L.flame_selector_load(None, fl.SEL_NPARAM) == -1
     assert L.flame_selector_load(FAKE, 3) == -2
-    v, nb = ctypes.c_int32(), ctypes.c_int32()
-    assert L.flame_select(-1, 1, 0, 1.0, ctypes.byref(v), ctypes.byref(nb)) == -1
+    ch = fl.Choice()
+    assert L.flame_select(-1, 1, 0, 1.0, ctypes.byref(ch)) == -1
+    assert L.flame_select(10, -1, 0, 1.0, ctypes.byref(ch)) == -2
+    assert L.flame_select(10, 1, 5, 1.0, ctypes.byref(ch)) == -3
+    assert L.flame_select(10, 1, 0, -1.0, ctypes.byref(ch)) == -4
+    assert L.flame_select(10, 1, 0, 1.0, None) == -5
+    assert L.flame_select_class(12, ctypes.byref(ch)) == -1
     o = _opts(variant=2)
     assert L.flame_batched_factor(0, 1, FAKE, FAKE, FAKE, FAKE, ctypes.byref(o), None) == -7
-    assert L.flame_autotune(0, 4, FAKE, 4, 0, FAKE, None) == -5
+    assert L.flame_autotune(0, 4, FAKE, 4, 0, 1, FAKE, None) == -5
+    assert L.flame_autotune(0, 4, FAKE, 4, 1, 0, FAKE, None) == -6
+    assert L.flame_autotune(0, 4, FAKE, 4, 1, 1, None, None) == -7
 
 
 TILE_PROBE = r'''
