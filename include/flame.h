@@ -51,13 +51,18 @@ typedef enum { FLAME_F64 = 0, FLAME_F32 = 1 } flame_dtype_t;
  *   BORDERED (1): A_TL = U_TL;                       A_TR, A_BR untouched
  *   LEFT     (2): A_TL = U_TL, A_TR = U_TR;          A_BR untouched
  *   RIGHT    (3): A_TL = U_TL, A_TR = U_TR, A_BR = A_BR - U_TR^T U_TR
- * RIGHT is the loop the paper prints (Fig. "dense-chol").  AUTO (0) lets the
- * library choose (learned selector, else autotuner table, else RIGHT). */
+ * RIGHT is the loop the paper prints (Fig. "dense-chol").  BY_BLOCKS (4): the
+ * paper's Cholesky-by-blocks (Fig. "sparse-chol" with dense 128 x 128
+ * blocks), its block operations run as tasks of one persistent kernel in
+ * dependence order (flame_factor_by_blocks; FP64, nb ignored).  AUTO (0)
+ * lets the library choose (learned selector, else autotuner table, else
+ * RIGHT). */
 typedef enum {
     FLAME_VAR_AUTO = 0,
     FLAME_VAR_BORDERED = 1,
     FLAME_VAR_LEFT = 2,
-    FLAME_VAR_RIGHT = 3
+    FLAME_VAR_RIGHT = 3,
+    FLAME_VAR_BY_BLOCKS = 4
 } flame_variant_t;
 
 /* Arithmetic of the trailing update A22 := A22 - A12^T A12 (RIGHT variant).
@@ -112,6 +117,36 @@ typedef struct {
  * with variant != RIGHT. */
 int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opts_t *opts, int32_t *info,
                  void *stream);
+
+/* Cholesky-by-blocks (Fig. "sparse-chol" of the paper, the by-blocks form of
+ * the loop of Fig. "dense-chol") over 128 x 128 blocks, run as a task DAG by
+ * one persistent kernel.  For iteration k the block operations are
+ *   A_kk := Chol(A_kk);  A_kj := triu(A_kk)^{-T} A_kj (existing A_kj, j > k);
+ *   A_ij := A_ij - A_ki^T A_kj (existing A_ki, A_kj and A_ij, k < i <= j),
+ * each a task that starts once the blocks it reads are final and the block
+ * it writes has received every update of earlier iterations (per-block
+ * counters in device memory play the role of the paper's futures; every wait
+ * is bounded).
+ *   dtype   FLAME_F64 (FLAME_ERR_UNSUPPORTED for FLAME_F32)
+ *   n, A, lda, info  as for flame_factor (info = -1 if a wait gave up)
+ *   pattern host, nbt x nbt row-major bytes, nbt = ceil(n / 128): nonzero =
+ *           block (i, j) exists (only i <= j is read; diagonal blocks always
+ *           exist); NULL = dense.  Blocks that do not exist are neither read
+ *           nor written, and an update whose target block does not exist is
+ *           dropped: with a pattern that is not closed under fill this is the
+ *           block incomplete Cholesky factorization of the pattern.
+ * Errors: -1 dtype, -2 n, -3 A, -4 lda, -6 info. */
+int flame_factor_by_blocks(int32_t dtype, int64_t n, void *A, int64_t lda, const uint8_t *pattern, int32_t *info,
+                           void *stream);
+
+/* The task list flame_factor_by_blocks runs for nbt x nbt blocks and a pattern
+ * (as above; NULL = dense), in the order the kernel's workgroups claim it:
+ * task q is tasks[4q .. 4q + 3] = (type, k, i, j) with type 0 = CHOL(A_kk),
+ * 1 = TRSM(A_kj) (i = k), 2 = update of A_ij from iteration k (HERK when
+ * i = j, GEMM else).  *count receives the number of tasks; tasks (host) may
+ * be NULL to query it.  Errors: -1 nbt (0..4096), -4 capacity (too small),
+ * -5 count. */
+int flame_by_blocks_tasks(int64_t nbt, const uint8_t *pattern, int32_t *tasks, int64_t capacity, int64_t *count);
 
 /* ---- solve and iterative refinement ----------------------------------- */
 

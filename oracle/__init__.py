@@ -147,6 +147,55 @@ def solve(U: np.ndarray, B: np.ndarray) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+# Cholesky-by-blocks over a block pattern (Fig. "sparse-chol" with dense
+# blocks), composed of the oracle's block operations above.
+
+def chol_by_blocks(A: np.ndarray, pattern=None, b: int = 128) -> tuple[np.ndarray, int]:
+    """The loop of Fig. "sparse-chol" on blocks of order b (the last ones
+    ragged): for each k, CHOL of the diagonal block, TRSM of every existing
+    block of block row k, then for every pair i <= j of existing blocks of that
+    row the HERK / GEMM update of block (i, j) if that block exists (the
+    exist(A22(i, j)) filter; an update of a missing block is dropped).
+    ``pattern``: nbt x nbt boolean array, True = block (i, j) exists (upper
+    triangle read; diagonal always exists); None = dense.  Blocks that do not
+    exist are left as they are.  Returns (A_out, info) on a copy; info as potrf
+    (1-based column of the first non-positive pivot).  Pinned (tests): a dense
+    pattern gives O1 bit for bit; a pattern closed under fill recovers U from
+    A = U^T U; with fill dropped, U^T U equals A on every existing block (the
+    defining property of the block incomplete factor)."""
+    W = np.array(_fortran(A), dtype=np.float64, order="F", copy=True)
+    n = W.shape[0]
+    nbt = (n + b - 1) // b
+
+    def ex(i, j):
+        return i == j or pattern is None or bool(pattern[i][j])
+
+    def sl(i):
+        return slice(i * b, min(n, (i + 1) * b))
+
+    for k in range(nbt):
+        Ukk, info = potrf(np.asfortranarray(W[sl(k), sl(k)]))
+        W[sl(k), sl(k)] = np.triu(Ukk) + np.tril(W[sl(k), sl(k)], -1)
+        if info:
+            return W, k * b + info
+        row = [j for j in range(k + 1, nbt) if ex(k, j)]
+        for j in row:
+            W[sl(k), sl(j)] = trsm_upper_t(np.triu(W[sl(k), sl(k)]), np.asfortranarray(W[sl(k), sl(j)]))
+        for i in row:
+            for j in row:
+                if j < i or not ex(i, j):
+                    continue
+                Xi = np.asfortranarray(W[sl(k), sl(i)])
+                Yj = np.asfortranarray(W[sl(k), sl(j)])
+                C = np.asfortranarray(W[sl(i), sl(j)])
+                if i == j:
+                    W[sl(i), sl(j)] = syrk_upper(C, Xi)
+                else:
+                    W[sl(i), sl(j)] = gemm_tn(C, Xi, Yj)
+    return W, 0
+
+
+# ----------------------------------------------------------------------------
 # Metrics (O4), FP64 numpy.  U is read from the upper triangle only.
 
 def upper(M: np.ndarray) -> np.ndarray:

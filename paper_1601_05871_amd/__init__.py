@@ -23,7 +23,8 @@ LIB_PATH = os.path.join(HERE, "libflame.so")
 
 F64, F32 = 0, 1
 OPT_FIXED_NB = 1
-VAR_AUTO, VAR_BORDERED, VAR_LEFT, VAR_RIGHT = 0, 1, 2, 3
+VAR_AUTO, VAR_BORDERED, VAR_LEFT, VAR_RIGHT, VAR_BY_BLOCKS = 0, 1, 2, 3, 4
+BY_BLOCKS_TILE = 128
 TRAIL = {"native": 0, "f32": 1, "bf16": 2}
 FLAME_OK, FLAME_ERR_HIP, FLAME_ERR_NOMEM, FLAME_ERR_NOT_CONVERGED, FLAME_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
 FLAME_ERR_BREAKDOWN = 5
@@ -38,7 +39,7 @@ EXPORTS = (
     "flame_op_gemm_tn", "flame_selector_load", "flame_select", "flame_select_logits", "flame_autotune",
     "flame_trace_enable", "flame_trace_collect", "flame_status_string", "flame_version",
     "flame_solve_mixed", "flame_shutdown", "flame_batched_factor_noalloc", "flame_trace_busy", "flame_probe",
-    "flame_select_class",
+    "flame_select_class", "flame_factor_by_blocks", "flame_by_blocks_tasks",
 )
 PROBE = {"mfma_f64": 0, "mfma_f32": 1, "mfma_bf16": 2, "copy": 3}
 NOALLOC_MAX_BATCH = 262144
@@ -118,6 +119,8 @@ def lib() -> ctypes.CDLL:
     L.flame_solve_mixed.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, ctypes.POINTER(MixedOpts),
                                     ctypes.POINTER(SolveReport), vp]
     L.flame_shutdown.argtypes = []
+    L.flame_factor_by_blocks.argtypes = [i32, i64, vp, i64, vp, vp, vp]
+    L.flame_by_blocks_tasks.argtypes = [i64, vp, vp, i64, ctypes.POINTER(i64)]
     L.flame_batched_factor_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, vp]
     L.flame_status_string.argtypes = [ctypes.c_int]
     L.flame_status_string.restype = ctypes.c_char_p
@@ -240,6 +243,54 @@ def _rows(name: str, t, n: int) -> int:
     if t.dim() != 2 or t.shape[0] != n:
         raise ValueError(f"{name} must be a 2-D tensor with {n} rows")
     return int(t.shape[1])
+
+
+def _pattern_bytes(pattern, nbt: int):
+    import numpy as np
+
+    if pattern is None:
+        return None
+    pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.uint8))
+    if pat.shape != (nbt, nbt):
+        raise ValueError(f"pattern must be {nbt} x {nbt} (one entry per block of {BY_BLOCKS_TILE})")
+    return pat
+
+
+def factor_by_blocks(A, pattern=None, info=None):
+    """Cholesky-by-blocks (flame_factor_by_blocks) in place on the FP64
+    column-major A: 128 x 128 blocks as tasks of one persistent kernel;
+    ``pattern`` (nbt x nbt, truthy = block (i, j) exists) gives the block
+    incomplete factorization of that pattern, None the dense one.  Returns the
+    device info tensor."""
+    torch = _torch()
+    n = _square("A", A)
+    if A.dtype != torch.float64:
+        raise TypeError("Cholesky-by-blocks takes float64 matrices")
+    nbt = (n + BY_BLOCKS_TILE - 1) // BY_BLOCKS_TILE
+    pat = _pattern_bytes(pattern, nbt)
+    lda = _colmajor_ld(A)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rc = lib().flame_factor_by_blocks(F64, n, A.data_ptr(), lda, None if pat is None else pat.ctypes.data,
+                                      info.data_ptr(), _stream_ptr())
+    _check("flame_factor_by_blocks", rc)
+    return info
+
+
+def by_blocks_tasks(nbt: int, pattern=None) -> list[tuple[int, int, int, int]]:
+    """The task list of Cholesky-by-blocks for nbt x nbt blocks (host only):
+    (type, k, i, j) with type 0 = CHOL(A_kk), 1 = TRSM(A_kj), 2 = update of
+    A_ij from iteration k, in the order the kernel claims them."""
+    import numpy as np
+
+    pat = _pattern_bytes(pattern, int(nbt))
+    pp = None if pat is None else pat.ctypes.data
+    cnt = ctypes.c_int64(0)
+    _check("flame_by_blocks_tasks", lib().flame_by_blocks_tasks(int(nbt), pp, None, 0, ctypes.byref(cnt)))
+    out = np.zeros(4 * max(cnt.value, 1), dtype=np.int32)
+    _check("flame_by_blocks_tasks", lib().flame_by_blocks_tasks(int(nbt), pp, out.ctypes.data, cnt.value,
+                                                                 ctypes.byref(cnt)))
+    return [tuple(int(x) for x in out[4 * q:4 * q + 4]) for q in range(cnt.value)]
 
 
 def solve(U, B, A0=None, tol: float = 1e-13, max_iter: int = 30, method: str = "ir"):

@@ -24,7 +24,7 @@ int normalize_opts(const flame_opts_t *in, int32_t dtype, int64_t n, flame_opts_
         *o = *in;
     else
         std::memset(o, 0, sizeof(*o));
-    if (o->variant < FLAME_VAR_AUTO || o->variant > FLAME_VAR_RIGHT) return -5;
+    if (o->variant < FLAME_VAR_AUTO || o->variant > FLAME_VAR_BY_BLOCKS) return -5;
     if (o->nb < 0 || o->nb > kMaxNb) return -5;
     if (o->trail < FLAME_TRAIL_NATIVE || o->trail > FLAME_TRAIL_BF16) return -5;
     if (o->lookahead < -1 || o->lookahead > 2) return -5;
@@ -52,6 +52,7 @@ int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opt
     if (rc) return rc;
     if (o.trail != FLAME_TRAIL_NATIVE && (dtype != FLAME_F64 || o.variant != FLAME_VAR_RIGHT))
         return FLAME_ERR_UNSUPPORTED;
+    if (o.variant == FLAME_VAR_BY_BLOCKS && dtype != FLAME_F64) return FLAME_ERR_UNSUPPORTED;
     return factor_dispatch(dtype, n, A, lda, o, info, as_stream(stream));
 }
 

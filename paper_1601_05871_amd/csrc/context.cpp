@@ -104,6 +104,7 @@ int shutdown_all() {
     const bool have_cur = hipGetDevice(&cur) == hipSuccess;
     drop_factor_graphs();
     drop_batched_graphs();
+    drop_dag_lists();
     selector_forget_devices();
     std::lock_guard<std::mutex> lk(g_mu);
     for (DevCtx *c : g_ctx) {

@@ -312,6 +312,9 @@ int factor_t(int64_t n, T *A, int64_t lda, const flame_opts_t &o, int32_t *info,
             return factor_left<T>(n, A, lda, nb, info, s);
         case FLAME_VAR_BORDERED:
             return factor_bordered<T>(n, A, lda, nb, info, s);
+        case FLAME_VAR_BY_BLOCKS:
+            if constexpr (sizeof(T) == 8) return by_blocks_factor(n, A, lda, nullptr, info, s);
+            return FLAME_ERR_UNSUPPORTED;
         default:
             return FLAME_ERR_UNSUPPORTED;
     }

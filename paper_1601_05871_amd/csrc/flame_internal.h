@@ -166,7 +166,17 @@ struct DevCtx;
 DevCtx *ctx_for_current_device();
 // Workspace slot `slot` (factor panel, solve, batched, selector) of
 // at least `bytes` (grown under a lock, kept until the process ends).
-enum { kWsFactor = 0, kWsSolve = 1, kWsBatched = 2, kWsSelector = 3, kWsTune = 4, kWsSplit = 5, kWsMixed = 6, kWsSlots = 7 };
+enum {
+    kWsFactor = 0,
+    kWsSolve = 1,
+    kWsBatched = 2,
+    kWsSelector = 3,
+    kWsTune = 4,
+    kWsSplit = 5,
+    kWsMixed = 6,
+    kWsDag = 7,
+    kWsSlots = 8
+};
 int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out);
 // Generation of a slot's buffer: changes every time ctx_workspace replaces it
 // (a graph that captured the old pointer must not be replayed).
@@ -174,6 +184,10 @@ uint64_t ctx_workspace_gen(DevCtx *c, int slot);
 // Teardown helpers of flame_shutdown: each drops its module's device state.
 void drop_factor_graphs();
 void drop_batched_graphs();
+void drop_dag_lists();
+// Cholesky-by-blocks on the device task DAG (by_blocks.cpp), FP64; pattern:
+// host nbt x nbt block mask or nullptr (dense).
+int by_blocks_factor(int64_t n, double *A, int64_t lda, const uint8_t *pattern, int32_t *info, hipStream_t s);
 void selector_forget_devices();
 hipStream_t ctx_side_stream(DevCtx *c);
 hipStream_t ctx_aux_stream(DevCtx *c);

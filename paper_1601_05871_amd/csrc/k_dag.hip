@@ -1,0 +1,321 @@
+// Cholesky-by-blocks as a task DAG run by one persistent kernel (Fig.
+// "sparse-chol" of the paper with dense 128 x 128 blocks; the dependence rule
+// of the by-blocks section: a block operation may run as soon as the blocks it
+// reads are final and the block it writes has received every earlier update).
+//
+// The matrix is a grid of nbt x nbt blocks of 128 (the last row / column of
+// blocks ragged); a pattern names the blocks of the upper triangle that exist
+// (all of them for a dense matrix).  For iteration k the paper's generators
+// emit
+//   CHOL(k):       A_kk := Chol(A_kk)
+//   TRSM(k, j):    A_kj := triu(A_kk)^{-T} A_kj          for existing A_kj, j > k
+//   UPD(k, i, j):  A_ij := A_ij - A_ki^T A_kj            for existing A_ki, A_kj
+//                  and existing A_ij, k < i <= j (HERK when i = j, GEMM else);
+// with a pattern that is not closed under this fill the update of a missing
+// block is dropped, which is the block form of an incomplete factorization.
+//
+// Futures (the paper's per-block task dependences) are per-block counters in
+// device memory: fin[i][j] = 1 once block (i, j) is final (after its CHOL or
+// TRSM), upd[i][j] = updates applied to it so far.  A task records how many
+// updates its output block must have received before it runs ("need"), so
+// the updates of one block are applied in iteration order (deterministic
+// results).  Tasks are listed in a static order in which every task comes
+// after all the tasks it depends on, with one iteration of lookahead:
+//   block of the list for iteration r (r >= 1):
+//     CHOL(r), TRSM(r, *), UPD(r-1, r+1, *), UPD(r, r+1, *), UPD(r-1, >= r+2, *)
+// so the diagonal and panel work of iteration r (and the updates of the next
+// block row) come before the bulk of iteration r-1's updates.  Workgroups
+// claim tasks in list order from an atomic counter and wait (bounded) for the
+// task's futures; since every dependence points to an earlier task, the
+// earliest unfinished task always belongs to a running workgroup whose
+// dependences are complete, so the launch always progresses, whatever the
+// number of resident workgroups.  A wait that gives up, or a breakdown, sets
+// an abort flag that every workgroup polls, so all of them exit.
+#include <algorithm>
+#include <vector>
+
+#include "chol_lds.h"
+#include "flame_internal.h"
+#include "trsm_rl.h"
+
+namespace flame {
+
+namespace {
+
+constexpr int kT = 128;                        // block order
+constexpr long long kDagSpin = 1LL << 26;      // s_sleep rounds before a wait gives up
+constexpr int kLdsChol = band_lds_size<kT>();  // doubles of the CHOL block in LDS
+constexpr int kLdsTrsm = 8 * 16 * 17 + 4 * 16 * 17;
+constexpr int kLdsDoubles = kLdsChol > kLdsTrsm ? kLdsChol : kLdsTrsm;
+
+struct DagP {
+    int64_t n;
+    double *A;
+    int64_t lda;
+    int nbt;              // blocks per side
+    const int4 *tasks;    // (type | k << 2, i, j, need)
+    int64_t ntasks;
+    int32_t *claim;       // next task to claim
+    int32_t *abort_flag;  // 1: a wait gave up, 2: breakdown
+    int32_t *fin;         // nbt x nbt
+    int32_t *upd;         // nbt x nbt
+    int32_t *info;
+};
+
+__device__ __forceinline__ int ld_acquire(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until *p >= want (bounded; false on abort or give-up).
+__device__ __forceinline__ bool wait_at_least(const int32_t *p, int want, int32_t *abort_flag) {
+    long long spins = 0;
+    while (ld_acquire(p) < want) {
+        if (ld_acquire(abort_flag) != 0) return false;
+        if (++spins > kDagSpin) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// C := C - X^T Y for one block (C M x N of a 128-grid, X and Y 128 x M / N,
+// columns contiguous in k), upper part only when `diag`.  Wavefront w owns the
+// 64 x 64 quarter (w / 2, w % 2) as 4 x 4 FP64 MFMA blocks; operand fragments
+// (4 consecutive k of one column) come straight from memory; the accumulator
+// starts from C and X enters negated.
+__device__ __forceinline__ void block_update(const double *__restrict__ X, const double *__restrict__ Y, double *C,
+                                             int64_t ld, int M, int N, bool diag) {
+    typedef double d4_t __attribute__((ext_vector_type(4)));
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int row0 = (wave >> 1) * 64, col0 = (wave & 1) * 64;
+    if (diag && row0 > col0) return;  // this quarter lies below the diagonal (wave-uniform)
+    if (row0 >= M || col0 >= N) return;
+    d4_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = min(row0 + 16 * a + r, M - 1), col = min(col0 + 16 * b + g + 4 * v, N - 1);
+                acc[a][b][v] = C[row + (int64_t)col * ld];
+            }
+    // lane (r, g) reads k = kc + 4 g .. kc + 4 g + 3 of its X and Y columns;
+    // MFMA e of the chunk takes element e of every lane, so both operands put
+    // the same k in each (g, e) slot
+    const double *xc[4], *yc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) xc[a] = X + (int64_t)min(row0 + 16 * a + r, M - 1) * ld + 4 * g;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) yc[b] = Y + (int64_t)min(col0 + 16 * b + r, N - 1) * ld + 4 * g;
+#pragma unroll 1
+    for (int kc = 0; kc < kT; kc += 16) {
+        double xa[4][4], yb[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xa[a][e] = xc[a][kc + e];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) yb[b][e] = yc[b][kc + e];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    // lane (r, g) ends with (X^T Y)(row r, column g + 4 v) of the 16 x 16 block
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[b][e], -xa[a][e], acc[a][b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = row0 + 16 * a + r, col = col0 + 16 * b + g + 4 * v;
+                if (row < M && col < N && (!diag || row <= col)) C[row + (int64_t)col * ld] = acc[a][b][v];
+            }
+}
+
+// The three task bodies are separate functions so that each gets its own
+// register allocation (inlined into one loop they spill).
+__device__ __noinline__ void task_chol(double *A, int64_t lda, int b, double *lds, int *s_bad, int k, int32_t *info,
+                                       int32_t *abort_flag) {
+    band_load<double, kT>(b, A, lda, lds);
+    __syncthreads();
+    const int bad = chol_lds_core2<double, kT>(b, lds, s_bad, A, lda);
+    if (bad != 0 && threadIdx.x == 0) {
+        atomicCAS(info, 0, (int32_t)((int64_t)k * kT + bad));
+        __hip_atomic_store(abort_flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ __noinline__ void task_trsm(const double *U, double *X, int64_t lda, int m, double *lds) {
+    auto Ds = reinterpret_cast<double (*)[16][17]>(lds);
+    auto Rt = reinterpret_cast<double (*)[17]>(lds + 8 * 16 * 17);
+    const int wave = threadIdx.x >> 6;
+    trsm_inverses<double, 8>(kT, U, lda, Ds);
+    __syncthreads();
+    for (int c0 = 0; c0 < m; c0 += 64) trsm_cols<double, 8>(kT, m, U, lda, X, lda, c0 + 16 * wave, Ds, Rt + 16 * wave);
+}
+
+__device__ __noinline__ void task_update(const double *X, const double *Y, double *C, int64_t ld, int M, int N,
+                                         bool diag) {
+    block_update(X, Y, C, ld, M, N, diag);
+}
+
+// Loop control is wave-uniform (readfirstlane) and thread 0 has ONE region
+// per iteration, publish of the finished task followed by the next claim,
+// with a barrier after it: with a claim region at the top of the loop and a
+// publish region at its end, both on thread 0, the compiler may thread the
+// one into the other across the back edge; the loop then has two entries and
+// its structurized form lets the other lanes of wavefront 0 run ahead of
+// thread 0 to the next barrier with the old task index.
+__global__ __launch_bounds__(256, 2) void k_by_blocks(DagP p) {
+    __shared__ __attribute__((aligned(16))) double lds[kLdsDoubles];
+    __shared__ int s_task, s_ok, s_bad;
+    const int tid = threadIdx.x;
+    const int nbt = p.nbt;
+    const int64_t lda = p.lda;
+    if (tid == 0) s_task = atomicAdd(p.claim, 1);
+    __syncthreads();
+    for (;;) {
+        const int t = __builtin_amdgcn_readfirstlane(s_task);
+        if (t >= p.ntasks) break;
+        const int4 d = p.tasks[t];
+        const int type = __builtin_amdgcn_readfirstlane(d.x) & 3, k = __builtin_amdgcn_readfirstlane(d.x) >> 2;
+        const int i = __builtin_amdgcn_readfirstlane(d.y), j = __builtin_amdgcn_readfirstlane(d.z);
+        const int need = __builtin_amdgcn_readfirstlane(d.w);
+        // wait for the futures of the task
+        if (tid == 0) {
+            bool ok = true;
+            if (type == 0) {
+                ok = wait_at_least(p.upd + (int64_t)k * nbt + k, need, p.abort_flag);
+            } else if (type == 1) {
+                ok = wait_at_least(p.fin + (int64_t)k * nbt + k, 1, p.abort_flag) &&
+                     wait_at_least(p.upd + (int64_t)k * nbt + j, need, p.abort_flag);
+            } else {
+                ok = wait_at_least(p.fin + (int64_t)k * nbt + i, 1, p.abort_flag) &&
+                     wait_at_least(p.fin + (int64_t)k * nbt + j, 1, p.abort_flag) &&
+                     wait_at_least(p.upd + (int64_t)i * nbt + j, need, p.abort_flag);
+            }
+            s_ok = ok ? 1 : 0;
+        }
+        __syncthreads();
+        if (__builtin_amdgcn_readfirstlane(s_ok) == 0) break;
+        // every wavefront takes an acquire of its own before reading the blocks
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        auto blk = [&](int bi, int bj) { return p.A + (int64_t)bi * kT + (int64_t)bj * kT * lda; };
+        auto width = [&](int b) { return (int)min((int64_t)kT, p.n - (int64_t)b * kT); };
+        if (type == 0)
+            task_chol(blk(k, k), lda, width(k), lds, &s_bad, k, p.info, p.abort_flag);
+        else if (type == 1)
+            task_trsm(blk(k, k), blk(k, j), lda, width(j), lds);
+        else
+            task_update(blk(k, i), blk(k, j), blk(i, j), lda, width(i), width(j), i == j);
+        // publish: stores visible at device scope, then the future; then the
+        // next claim (no claim once the launch is aborting)
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) {
+            if (type == 2)
+                __hip_atomic_store(p.upd + (int64_t)i * nbt + j, need + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                __hip_atomic_store(p.fin + (int64_t)k * nbt + (type == 0 ? k : j), 1, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            s_task = (ld_acquire(p.abort_flag) != 0) ? (int)p.ntasks : atomicAdd(p.claim, 1);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_dag_abort_info(const int32_t *abort_flag, int32_t *info) {
+    // a wait that gave up (not a breakdown): info = -1
+    if (threadIdx.x == 0 && *abort_flag == 1 && *info == 0) *info = -1;
+}
+
+}  // namespace
+
+// Task list of the by-blocks factorization (see the top of this file).
+// pattern: nbt x nbt, row-major, nonzero = block (i, j) exists (only i <= j
+// read; nullptr = dense).  Returns the tasks as (type | k << 2, i, j, need).
+std::vector<int4> by_blocks_tasks(int nbt, const uint8_t *pattern) {
+    auto ex = [&](int i, int j) -> bool { return i == j || pattern == nullptr || pattern[(int64_t)i * nbt + j] != 0; };
+    // need(k, i, j): updates of block (i, j) from iterations before k (k for a
+    // dense matrix)
+    auto need_at = [&](int k, int i, int j) {
+        if (pattern == nullptr) return k;
+        int c = 0;
+        for (int q = 0; q < k; ++q)
+            if (ex(q, i) && ex(q, j)) ++c;
+        return c;
+    };
+    std::vector<int4> out;
+    auto chol = [&](int r) { out.push_back(int4{0 | (r << 2), r, r, need_at(r, r, r)}); };
+    auto trsm = [&](int r) {
+        for (int j = r + 1; j < nbt; ++j)
+            if (ex(r, j)) out.push_back(int4{1 | (r << 2), r, j, need_at(r, r, j)});
+    };
+    auto upd_row = [&](int k, int i) {  // UPD(k, i, j >= i)
+        if (k < 0 || i >= nbt || !ex(k, i)) return;
+        for (int j = i; j < nbt; ++j)
+            if (ex(k, j) && ex(i, j)) out.push_back(int4{2 | (k << 2), i, j, need_at(k, i, j)});
+    };
+    for (int r = 0; r < nbt; ++r) {
+        chol(r);
+        trsm(r);
+        upd_row(r - 1, r + 1);
+        upd_row(r, r + 1);
+        for (int i = r + 2; i < nbt; ++i) upd_row(r - 1, i);
+    }
+    return out;
+}
+
+int launch_by_blocks(int64_t n, double *A, int64_t lda, const int4 *tasks, int64_t ntasks, int nbt, int32_t *ints,
+                     int32_t *info, hipStream_t s) {
+    // ints: claim, abort, fin[nbt^2], upd[nbt^2] (cleared here)
+    const int64_t nints = 2 + 2 * (int64_t)nbt * nbt;
+    int rc = launch_zero_i32(ints, nints, s);
+    if (rc) return rc;
+    rc = launch_zero_i32(info, 1, s);
+    if (rc) return rc;
+    if (n == 0 || ntasks == 0) return FLAME_OK;
+    static int grid_cache[64] = {};
+    int dev = 0;
+    FLAME_HIP(hipGetDevice(&dev));
+    int grid = (dev < 64) ? grid_cache[dev] : 0;
+    if (grid == 0) {
+        int cus = 0, per = 0;
+        FLAME_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        FLAME_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_by_blocks, 256, 0));
+        grid = std::max(1, cus * std::max(1, per));
+        if (dev < 64) grid_cache[dev] = grid;
+    }
+    DagP p;
+    p.n = n;
+    p.A = A;
+    p.lda = lda;
+    p.nbt = nbt;
+    p.tasks = tasks;
+    p.ntasks = ntasks;
+    p.claim = ints;
+    p.abort_flag = ints + 1;
+    p.fin = ints + 2;
+    p.upd = ints + 2 + (int64_t)nbt * nbt;
+    p.info = info;
+    const int tr = trace_begin(FLAME_KC_OTHER, s);
+    hipLaunchKernelGGL(k_by_blocks, dim3((unsigned)std::min<int64_t>(grid, ntasks)), dim3(256), 0, s, p);
+    FLAME_CHECK_LAUNCH();
+    const double dn = (double)n;
+    trace_end(tr, s, dn * dn * dn / 3.0, 16.0 * dn * dn);
+    hipLaunchKernelGGL(k_dag_abort_info, dim3(1), dim3(64), 0, s, p.abort_flag, info);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+}  // namespace flame
