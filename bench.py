@@ -421,7 +421,7 @@ def table_mode(args, dev, fl, inputs, torch) -> int:
     nbs = [int(v) for v in args.table_nbs.split(",") if v]
     seeds = [int(v) for v in args.table_seeds.split(",") if v]
     reps = max(1, args.steps)
-    names = {1: "bordered", 2: "left-looking", 3: "right-looking"}
+    names = {1: "bordered", 2: "left-looking", 3: "right-looking", 4: "by-blocks DAG"}
     stream = torch.cuda.current_stream()
     rows = []
     for n in ns:
@@ -446,19 +446,32 @@ def table_mode(args, dev, fl, inputs, torch) -> int:
                             return 1
                         if r > 0:
                             times[(nb, v)].append(e0.elapsed_time(e1))
+            # the by-blocks task DAG (its own 128-block grid, no nb)
+            for r in range(1 + reps):
+                W.copy_(P)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fl.factor_by_blocks(W, info=info)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if int(info.item()) != 0:
+                    log(f"breakdown n={n} by-blocks")
+                    return 1
+                if r > 0:
+                    times.setdefault((128, 4), []).append(e0.elapsed_time(e1))
             del P, W
             torch.cuda.empty_cache()
-        for nb in nbs:
-            for v in (1, 2, 3):
-                t = np.array(times[(nb, v)])
-                med = float(np.median(t))
-                tf = potrf_flops(n) / (med * 1e-3) / 1e12
-                rec = {"n": n, "nb": nb, "variant": names[v], "ms_median": round(med, 3),
-                       "ms_min": round(float(t.min()), 3), "ms_max": round(float(t.max()), 3),
-                       "tflops": round(tf, 2), "pct_fp64_peak": round(100 * tf / PEAK_F64_TFLOPS, 1),
-                       "samples": int(t.size)}
-                rows.append(rec)
-                print(json.dumps(rec), flush=True)
+        for nb, v in [(nb, v) for nb in nbs for v in (1, 2, 3)] + [(128, 4)]:
+            t = np.array(times[(nb, v)])
+            med = float(np.median(t))
+            tf = potrf_flops(n) / (med * 1e-3) / 1e12
+            rec = {"n": n, "nb": nb, "variant": names[v], "ms_median": round(med, 3),
+                   "ms_min": round(float(t.min()), 3), "ms_max": round(float(t.max()), 3),
+                   "tflops": round(tf, 2), "pct_fp64_peak": round(100 * tf / PEAK_F64_TFLOPS, 1),
+                   "samples": int(t.size)}
+            rows.append(rec)
+            print(json.dumps(rec), flush=True)
     print(f"\n| n | nb | variant | median ms | min ms | max ms | TFLOP/s | % FP64 peak |")
     print("|---|---|---|---|---|---|---|---|")
     for r in rows:

@@ -46,6 +46,7 @@ constexpr int kT = 128;                        // block order
 constexpr long long kDagSpin = 1LL << 26;      // s_sleep rounds before a wait gives up
 constexpr int kLdsChol = band_lds_size<kT>();  // doubles of the CHOL block in LDS
 constexpr int kLdsTrsm = 8 * 16 * 17 + 4 * 16 * 17;
+constexpr int kStages = 4;                      // update: chunks of 16 k staged at once (3 in flight)
 constexpr int kLdsDoubles = kLdsChol > kLdsTrsm ? kLdsChol : kLdsTrsm;
 
 struct DagP {
@@ -60,6 +61,7 @@ struct DagP {
     int32_t *fin;         // nbt x nbt
     int32_t *upd;         // nbt x nbt
     int32_t *info;
+    int stage;            // 1: operand columns 16-byte aligned (A and lda): LDS-staged updates
 };
 
 __device__ __forceinline__ int ld_acquire(const int32_t *p) {
@@ -80,15 +82,27 @@ __device__ __forceinline__ bool wait_at_least(const int32_t *p, int want, int32_
     return true;
 }
 
+// An update's result goes out with device-scope stores, which write through
+// to the device's coherence point: once every wavefront has waited for its
+// stores and the workgroup has passed a barrier, the block is visible to every
+// CU, and the future is published without a release fence.  (A release at
+// device scope writes back the whole L2 of the XCD; with a workgroup per CU
+// publishing an update every few tens of microseconds those writebacks
+// contend: a 128-block update took 59 us against 28 us this way.)
+__device__ __forceinline__ void store_dev(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // C := C - X^T Y for one block (C M x N of a 128-grid, X and Y 128 x M / N,
 // columns contiguous in k), upper part only when `diag`.  Wavefront w owns the
-// 64 x 64 quarter (w / 2, w % 2) as 4 x 4 FP64 MFMA blocks; operand fragments
-// (4 consecutive k of one column) come straight from memory; the accumulator
-// starts from C and X enters negated.
+// 64 x 64 quarter (w / 2, w % 2) as 4 x 4 FP64 MFMA blocks (lane (r, g) of
+// block (a, b) ends with row 16 a + r, columns 16 b + g + 4 v of the quarter);
+// the accumulator starts from C and X enters negated.  Operand fragments
+// straight from memory: the form for columns that are not 16-byte aligned.
 __device__ __forceinline__ void block_update(const double *__restrict__ X, const double *__restrict__ Y, double *C,
                                              int64_t ld, int M, int N, bool diag) {
     typedef double d4_t __attribute__((ext_vector_type(4)));
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r = lane & 15, g = lane >> 4;
     const int row0 = (wave >> 1) * 64, col0 = (wave & 1) * 64;
     if (diag && row0 > col0) return;  // this quarter lies below the diagonal (wave-uniform)
@@ -128,7 +142,6 @@ __device__ __forceinline__ void block_update(const double *__restrict__ X, const
             for (int b = 0; b < 4; ++b)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    // lane (r, g) ends with (X^T Y)(row r, column g + 4 v) of the 16 x 16 block
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[b][e], -xa[a][e], acc[a][b], 0, 0, 0);
     }
 #pragma unroll
@@ -138,14 +151,144 @@ __device__ __forceinline__ void block_update(const double *__restrict__ X, const
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = row0 + 16 * a + r, col = col0 + 16 * b + g + 4 * v;
-                if (row < M && col < N && (!diag || row <= col)) C[row + (int64_t)col * ld] = acc[a][b][v];
+                if (row < M && col < N && (!diag || row <= col)) store_dev(&C[row + (int64_t)col * ld], acc[a][b][v]);
             }
 }
 
-// The three task bodies are separate functions so that each gets its own
-// register allocation (inlined into one loop they spill).
-__device__ __noinline__ void task_chol(double *A, int64_t lda, int b, double *lds, int *s_bad, int k, int32_t *info,
-                                       int32_t *abort_flag) {
+// 16 bytes per lane from global memory straight into LDS (lane l's bytes land
+// at lds + 16 l; lds wavefront-uniform).
+__device__ __forceinline__ void copy16_to_lds(const char *gsrc, char *lds) {
+    __builtin_amdgcn_global_load_lds(gsrc, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+// byte offset of 16-byte unit `unit` (k = 2 unit, 2 unit + 1 of the chunk) of
+// operand column `col` in a staged chunk: units XOR-swizzled by (col mod 8) so
+// that the 16 lanes reading one unit of 16 consecutive columns hit different
+// banks
+__device__ __forceinline__ int slab_off(int col, int unit) { return col * 128 + ((unit ^ (col & 7)) << 4); }
+
+// LDS of the kernel, one object: a kernel with several LDS variables has
+// their accesses tagged with alias scopes, and the compiler then makes every
+// LDS read wait for all outstanding copies into LDS (which would serialize
+// the update's copy pipeline below); the waits those copies need are explicit.
+struct DagShared {
+    union {
+        double band[kLdsDoubles];                // CHOL block (band layout) or TRSM scratch
+        char stage[kStages][2][kT * 128];        // update: [chunk mod kStages][X or Y][column x 128 bytes]
+    } u;
+    int s_task, s_ok, s_bad;
+};
+
+// The same update with the operands staged through LDS, 16 k per chunk: the
+// workgroup copies the chunk's 128 columns of X and of Y (128 bytes each)
+// from global memory straight into LDS, three chunks ahead of the MFMAs
+// (kStages buffers, one barrier per chunk), so every operand element is read
+// once per workgroup with 16-byte loads and the copy latency is hidden behind
+// the MFMAs of the chunks before.  Needs 16-byte aligned columns.  Called by
+// the whole workgroup (barriers inside).
+__device__ __forceinline__ void block_update_lds(const double *__restrict__ X, const double *__restrict__ Y,
+                                                 double *C, int64_t ld, int M, int N, bool diag,
+                                                 char (*stage)[2][kT * 128]) {
+    typedef double d4_t __attribute__((ext_vector_type(4)));
+    typedef double d2_t __attribute__((ext_vector_type(2)));
+    typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+    constexpr int kChunks = kT / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = lane & 15, g = lane >> 4;
+    const int row0 = (wave >> 1) * 64, col0 = (wave & 1) * 64;
+    const bool active = row0 < M && col0 < N && !(diag && row0 > col0);  // wavefront-uniform
+    // copies: wavefront w takes columns 8 w + 32 j + lane / 8 (j < 4) of each
+    // operand; lane l's 16 bytes land in slot l % 8 of its column, so it
+    // fetches the unit the swizzle puts there (8 copy instructions a chunk)
+    const int unit = (lane & 7) ^ ((lane >> 3) & 7);
+    const char *xg[4], *yg[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = 8 * wave + 32 * j + (lane >> 3);
+        xg[j] = reinterpret_cast<const char *>(X + (int64_t)min(col, M - 1) * ld) + 16 * unit;
+        yg[j] = reinterpret_cast<const char *>(Y + (int64_t)min(col, N - 1) * ld) + 16 * unit;
+    }
+    auto copy = [&](int c) {
+        const int sb = c & (kStages - 1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            copy16_to_lds(xg[j] + 128 * c, &stage[sb][0][0] + (8 * wave + 32 * j) * 128);
+            copy16_to_lds(yg[j] + 128 * c, &stage[sb][1][0] + (8 * wave + 32 * j) * 128);
+        }
+    };
+    d4_t acc[4][4];
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = min(row0 + 16 * a + r, M - 1), col = min(col0 + 16 * b + g + 4 * v, N - 1);
+                    acc[a][b][v] = C[row + (int64_t)col * ld];
+                }
+    }
+    // the C loads are issued before the copies (the vmcnt counts below
+    // count copies only after them)
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int c = 0; c < kStages - 1; ++c) copy(c);
+#pragma unroll 1
+    for (int c = 0; c < kChunks; ++c) {
+        // chunk c landed: at most the copies of the chunks after it (8
+        // instructions each, up to two) still in flight
+        if (c + 2 < kChunks)
+            asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+        else if (c + 1 < kChunks)
+            asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+        else
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        // every wavefront's part of chunk c is in LDS, and every wavefront is
+        // done with chunk c - 1, whose buffer the copy of chunk c + 3 reuses
+        __syncthreads();
+        if (c + kStages - 1 < kChunks) copy(c + kStages - 1);
+        if (active) {
+            const char *xs = &stage[c & (kStages - 1)][0][0], *ys = &stage[c & (kStages - 1)][1][0];
+            // lane (r, g) takes units 2 g and 2 g + 1 (k = 4 g .. 4 g + 3) of
+            // its columns in turn; MFMA e of a unit takes element e of every
+            // lane, so both operands put the same k in each (g, e) slot
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                d2_t fa[4], fb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    fa[a] = __builtin_bit_cast(d2_t, *reinterpret_cast<const u4_t *>(xs + slab_off(row0 + 16 * a + r, 2 * g + h)) ^
+                                                         u4_t{0u, 0x80000000u, 0u, 0x80000000u});  // -X
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    fb[b] = __builtin_bit_cast(d2_t, *reinterpret_cast<const u4_t *>(ys + slab_off(col0 + 16 * b + r, 2 * g + h)));
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[b][0], fa[a][0], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[b][1], fa[a][1], acc[a][b], 0, 0, 0);
+                    }
+            }
+        }
+    }
+    __syncthreads();  // the staging buffers are free again (the next task may overwrite the LDS)
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = row0 + 16 * a + r, col = col0 + 16 * b + g + 4 * v;
+                    if (row < M && col < N && (!diag || row <= col)) store_dev(&C[row + (int64_t)col * ld], acc[a][b][v]);
+                }
+    }
+}
+
+// The task bodies, inlined into the persistent loop: called by the whole
+// workgroup; every LDS access goes to the kernel's own LDS array.
+__device__ __forceinline__ void task_chol(double *A, int64_t lda, int b, double *lds, int *s_bad, int k,
+                                          int32_t *info, int32_t *abort_flag) {
     band_load<double, kT>(b, A, lda, lds);
     __syncthreads();
     const int bad = chol_lds_core2<double, kT>(b, lds, s_bad, A, lda);
@@ -155,18 +298,13 @@ __device__ __noinline__ void task_chol(double *A, int64_t lda, int b, double *ld
     }
 }
 
-__device__ __noinline__ void task_trsm(const double *U, double *X, int64_t lda, int m, double *lds) {
+__device__ __forceinline__ void task_trsm(const double *U, double *X, int64_t lda, int m, double *lds) {
     auto Ds = reinterpret_cast<double (*)[16][17]>(lds);
     auto Rt = reinterpret_cast<double (*)[17]>(lds + 8 * 16 * 17);
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     trsm_inverses<double, 8>(kT, U, lda, Ds);
     __syncthreads();
     for (int c0 = 0; c0 < m; c0 += 64) trsm_cols<double, 8>(kT, m, U, lda, X, lda, c0 + 16 * wave, Ds, Rt + 16 * wave);
-}
-
-__device__ __noinline__ void task_update(const double *X, const double *Y, double *C, int64_t ld, int M, int N,
-                                         bool diag) {
-    block_update(X, Y, C, ld, M, N, diag);
 }
 
 // Loop control is wave-uniform (readfirstlane) and thread 0 has ONE region
@@ -176,9 +314,10 @@ __device__ __noinline__ void task_update(const double *X, const double *Y, doubl
 // one into the other across the back edge; the loop then has two entries and
 // its structurized form lets the other lanes of wavefront 0 run ahead of
 // thread 0 to the next barrier with the old task index.
-__global__ __launch_bounds__(256, 2) void k_by_blocks(DagP p) {
-    __shared__ __attribute__((aligned(16))) double lds[kLdsDoubles];
-    __shared__ int s_task, s_ok, s_bad;
+__global__ __launch_bounds__(256, 1) void k_by_blocks(DagP p) {
+    __shared__ __attribute__((aligned(16))) DagShared sh;
+    double *lds = sh.u.band;
+    int &s_task = sh.s_task, &s_ok = sh.s_ok, &s_bad = sh.s_bad;
     const int tid = threadIdx.x;
     const int nbt = p.nbt;
     const int64_t lda = p.lda;
@@ -216,15 +355,22 @@ __global__ __launch_bounds__(256, 2) void k_by_blocks(DagP p) {
             task_chol(blk(k, k), lda, width(k), lds, &s_bad, k, p.info, p.abort_flag);
         else if (type == 1)
             task_trsm(blk(k, k), blk(k, j), lda, width(j), lds);
+        else if (p.stage)
+            block_update_lds(blk(k, i), blk(k, j), blk(i, j), lda, width(i), width(j), i == j, sh.u.stage);
         else
-            task_update(blk(k, i), blk(k, j), blk(i, j), lda, width(i), width(j), i == j);
-        // publish: stores visible at device scope, then the future; then the
-        // next claim (no claim once the launch is aborting)
-        __threadfence();
+            block_update(blk(k, i), blk(k, j), blk(i, j), lda, width(i), width(j), i == j);
+        // publish: the block visible at device scope, then the future; then
+        // the next claim (no claim once the launch is aborting).  An update
+        // wrote through (store_dev): its stores complete, the future follows;
+        // CHOL and TRSM wrote through the L2 and release it.
+        if (type == 2)
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        else
+            __threadfence();
         __syncthreads();
         if (tid == 0) {
             if (type == 2)
-                __hip_atomic_store(p.upd + (int64_t)i * nbt + j, need + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(p.upd + (int64_t)i * nbt + j, need + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             else
                 __hip_atomic_store(p.fin + (int64_t)k * nbt + (type == 0 ? k : j), 1, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
@@ -308,6 +454,7 @@ int launch_by_blocks(int64_t n, double *A, int64_t lda, const int4 *tasks, int64
     p.fin = ints + 2;
     p.upd = ints + 2 + (int64_t)nbt * nbt;
     p.info = info;
+    p.stage = (((uintptr_t)A & 15) == 0 && (lda & 1) == 0) ? 1 : 0;
     const int tr = trace_begin(FLAME_KC_OTHER, s);
     hipLaunchKernelGGL(k_by_blocks, dim3((unsigned)std::min<int64_t>(grid, ntasks)), dim3(256), 0, s, p);
     FLAME_CHECK_LAUNCH();

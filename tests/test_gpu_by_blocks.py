@@ -24,19 +24,25 @@ def _rel(Ug, Uo):
     return float(np.max(np.abs(Ug - Uo)) / max(np.max(np.abs(Uo)), 1e-300))
 
 
+@pytest.mark.parametrize("aligned", [True, False])
 @pytest.mark.parametrize("n", [1, 5, 127, 128, 129, 300, 1000, 2600])
-def test_by_blocks_dense_vs_oracle(n):
-    print(f"[by_blocks] dense n={n}", flush=True)
+def test_by_blocks_dense_vs_oracle(n, aligned):
+    """Both forms of the block update: operands staged through LDS (even
+    leading dimension: 16-byte aligned columns) and read straight from
+    memory (odd leading dimension)."""
+    print(f"[by_blocks] dense n={n} aligned={aligned}", flush=True)
     A = inputs.spd_bbt(n, 50)
     Uo, io = oracle.potrf(A, threads=8)
-    Ad = to_dev(A, ld=n + 3)
+    ld = n + 2 + (n & 1) if aligned else n + 3 - (n & 1)
+    assert (ld % 2 == 0) == aligned
+    Ad = to_dev(A, ld=ld)
     info = fl.factor_by_blocks(Ad)
     Ug = to_host(Ad)
     assert int(info.item()) == io == 0
     assert _rel(Ug, Uo) <= 1e-13
     assert oracle.factor_backward_error(A, Ug) <= 1e-14
     # the strictly lower triangle is never written
-    assert np.array_equal(np.tril(Ug, -1), np.tril(to_host(to_dev(A, ld=n + 3)), -1))
+    assert np.array_equal(np.tril(Ug, -1), np.tril(to_host(to_dev(A, ld=ld)), -1))
 
 
 def test_by_blocks_through_flame_factor_variant():
