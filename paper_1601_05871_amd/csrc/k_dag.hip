@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "chol_lds.h"
+#include "dev_sync.h"
 #include "flame_internal.h"
 #include "trsm_rl.h"
 
@@ -64,34 +65,19 @@ struct DagP {
     int stage;            // 1: operand columns 16-byte aligned (A and lda): LDS-staged updates
 };
 
-__device__ __forceinline__ int ld_acquire(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Waits until *p >= want (bounded; false on abort or give-up).
+// Waits (bounded) until *p >= want; false on abort or give-up (which sets
+// the abort flag to 1).
 __device__ __forceinline__ bool wait_at_least(const int32_t *p, int want, int32_t *abort_flag) {
-    long long spins = 0;
-    while (ld_acquire(p) < want) {
-        if (ld_acquire(abort_flag) != 0) return false;
-        if (++spins > kDagSpin) {
-            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return true;
+    return poll_at_least(p, want, abort_flag, 1, kDagSpin);
 }
 
-// An update's result goes out with device-scope stores, which write through
-// to the device's coherence point: once every wavefront has waited for its
-// stores and the workgroup has passed a barrier, the block is visible to every
-// CU, and the future is published without a release fence.  (A release at
-// device scope writes back the whole L2 of the XCD; with a workgroup per CU
-// publishing an update every few tens of microseconds those writebacks
+// An update's result goes out with device-scope stores (store_dev), which
+// write through to the device's coherence point: once every wavefront has
+// waited for its stores and the workgroup has passed a barrier, the block is
+// visible to every CU and the future is set without a release.  (A release
+// at device scope writes back the XCD's whole L2; with a workgroup per CU
+// publishing an update every few tens of microseconds those write-backs
 // contend: a 128-block update took 59 us against 28 us this way.)
-__device__ __forceinline__ void store_dev(double *p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // C := C - X^T Y for one block (C M x N of a 128-grid, X and Y 128 x M / N,
 // columns contiguous in k), upper part only when `diag`.  Wavefront w owns the
@@ -348,7 +334,7 @@ __global__ __launch_bounds__(256, 1) void k_by_blocks(DagP p) {
         __syncthreads();
         if (__builtin_amdgcn_readfirstlane(s_ok) == 0) break;
         // every wavefront takes an acquire of its own before reading the blocks
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        acquire_dev();
         auto blk = [&](int bi, int bj) { return p.A + (int64_t)bi * kT + (int64_t)bj * kT * lda; };
         auto width = [&](int b) { return (int)min((int64_t)kT, p.n - (int64_t)b * kT); };
         if (type == 0)
@@ -364,17 +350,17 @@ __global__ __launch_bounds__(256, 1) void k_by_blocks(DagP p) {
         // wrote through (store_dev): its stores complete, the future follows;
         // CHOL and TRSM wrote through the L2 and release it.
         if (type == 2)
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            wait_stores();
         else
             __threadfence();
         __syncthreads();
         if (tid == 0) {
             if (type == 2)
-                __hip_atomic_store(p.upd + (int64_t)i * nbt + j, need + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                store_dev(p.upd + (int64_t)i * nbt + j, need + 1);
             else
                 __hip_atomic_store(p.fin + (int64_t)k * nbt + (type == 0 ? k : j), 1, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
-            s_task = (ld_acquire(p.abort_flag) != 0) ? (int)p.ntasks : atomicAdd(p.claim, 1);
+            s_task = (load_dev(p.abort_flag) != 0) ? (int)p.ntasks : atomicAdd(p.claim, 1);
         }
         __syncthreads();
     }

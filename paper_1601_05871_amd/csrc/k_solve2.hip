@@ -11,6 +11,7 @@
 // index order and wait only on lower indices, so the chain always makes
 // progress; every wait is bounded (a wait that gives up sets *err, writes
 // NaN over its block and lets the kernel finish).
+#include "dev_sync.h"
 #include "flame_internal.h"
 #include "tile_map.h"
 
@@ -36,29 +37,19 @@ int launch_identity_blocks(int64_t nblk, int bs, double *Dt, hipStream_t s) {
     return FLAME_OK;
 }
 
-// Waits (bounded) for a flag set with release semantics; false if it gave up.
+// Waits (bounded) for a block's flag; false if it gave up or another wait
+// did (*err).  The block itself is then read with device-scope loads.
 __device__ __forceinline__ bool wait_flag(const int32_t *flag, int32_t *err) {
-    long long spins = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        if (++spins > kSpinLimit) {
-            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    return true;
+    return poll_at_least(flag, 1, err, 1, kSpinLimit);
 }
 
-__device__ __forceinline__ double load_coherent(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Publishes this workgroup's block: stores, device-scope fence, release flag.
+// Publishes this workgroup's block: device-scope stores, completed by every
+// wavefront before the barrier, then the flag.
 __device__ __forceinline__ void publish(double *xi, int tid, int w, double v, bool bad, int32_t *flag) {
-    if (tid < w) xi[tid] = bad ? __builtin_nan("") : v;
-    __threadfence();
+    if (tid < w) store_dev(xi + tid, bad ? __builtin_nan("") : v);
+    wait_stores();
     __syncthreads();
-    if (tid == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) store_dev(flag, 1);
 }
 
 // U^T y = b in place on x (n x 1).  Thread (c, h): column c of the block,
@@ -92,7 +83,7 @@ __global__ __launch_bounds__(256) void k_trsv1_fwd(int64_t n, const double *__re
         for (int k = 0; k < 64; ++k) u[k] = Ucol[q * kTb + k];
         if (tid == 0 && !wait_flag(flags + q, err)) bad = 1;
         __syncthreads();
-        if (tid < kTb) xs[tid] = load_coherent(x + q * kTb + tid);  // block q < i is full
+        if (tid < kTb) xs[tid] = load_dev(x + q * kTb + tid);  // block q < i is full
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 64; ++k) acc += u[k] * xs[64 * h + k];
@@ -144,7 +135,7 @@ __global__ __launch_bounds__(256) void k_trsv1_bwd(int64_t n, const double *__re
         const int wq = (int)min((int64_t)kTb, n - q * kTb);
         if (tid == 0 && !wait_flag(flags + q, err)) bad = 1;
         __syncthreads();
-        if (tid < kTb) xs[tid] = (tid < wq) ? load_coherent(x + q * kTb + tid) : 0.0;
+        if (tid < kTb) xs[tid] = (tid < wq) ? load_dev(x + q * kTb + tid) : 0.0;
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 64; ++k) acc += u[k] * xs[64 * h + k];

@@ -26,6 +26,7 @@
 // 16 x 16 block.
 #include <algorithm>
 
+#include "dev_sync.h"
 #include "flame_internal.h"
 #include "trsm_rl.h"
 
@@ -36,22 +37,16 @@ namespace {
 constexpr int kTc = 128;                  // row block
 constexpr long long kSpinCap = 1LL << 26;  // s_sleep rounds before a wait gives up
 
+// Waits (bounded) for a block's flag; false if it gave up or another wait
+// did (*err).
 __device__ __forceinline__ bool wait_set(const int32_t *flag, int32_t *err) {
-    long long spins = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        if (++spins > kSpinCap) {
-            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    return true;
+    return poll_at_least(flag, 1, err, 1, kSpinCap);
 }
 
-// After a barrier behind thread 0's acquire of a flag: every wavefront takes
-// an acquire fence at device scope of its own, so that its ordinary (batched)
-// loads of the data published before that flag see it.
-__device__ __forceinline__ void acquire_all() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// After the barrier behind thread 0's wait: every wavefront invalidates its
+// view of device memory, so that its ordinary (batched) loads of the block
+// published before the flag see it.
+__device__ __forceinline__ void acquire_all() { acquire_dev(); }
 
 // Operand of row block h of this wavefront for all 32 k slots, from a
 // column-major matrix M: TRANS = false reads element (row, k) at
@@ -191,11 +186,12 @@ __global__ __launch_bounds__(256) void k_trsm_chain(int64_t n, int64_t nrhs_all,
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 32 * wave + 16 * h + r, col = 16 * cb + g + 4 * v;
-                if (row < w && col < nrhs) X[i0 + row + (int64_t)col * ldx] = bad ? __builtin_nan("") : y[h][cb][v];
+                if (row < w && col < nrhs) store_dev(&X[i0 + row + (int64_t)col * ldx], bad ? __builtin_nan("") : y[h][cb][v]);
             }
-    __threadfence();
+    // publish: the stores completed by every wavefront, then the flag
+    wait_stores();
     __syncthreads();
-    if (tid == 0) __hip_atomic_store(flags + i, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) store_dev(flags + i, 1);
 }
 
 }  // namespace
