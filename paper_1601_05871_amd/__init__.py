@@ -90,15 +90,17 @@ class MixedOpts(ctypes.Structure):
 _lib = None
 
 
-def lib() -> ctypes.CDLL:
-    """Loads libflame.so (built by ``python -m paper_1601_05871_amd.build``)."""
+def lib(path: str | None = None) -> ctypes.CDLL:
+    """Loads libflame.so (built by ``python -m paper_1601_05871_amd.build``),
+    or, on the first call, the library build at ``path`` (the sanitized one)."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_05871_amd.build` "
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1601_05871_amd.build` "
                            "(the HIP library is required; there is no fallback)")
-    L = ctypes.CDLL(LIB_PATH)
+    L = ctypes.CDLL(path)
     i32, i64, vp, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
     L.flame_factor.argtypes = [i32, i64, vp, i64, ctypes.POINTER(Opts), vp, vp]
     L.flame_solve.argtypes = [i32, i64, i64, vp, i64, vp, i64, ctypes.POINTER(Refine),
