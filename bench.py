@@ -64,6 +64,9 @@ def main() -> int:
     ap.add_argument("--table", action="store_true",
                     help="instead of the default run: time every (n, nb, variant, seed) cell of the "
                          "single-matrix FP64 sweep and print a markdown table")
+    ap.add_argument("--dag", action="store_true",
+                    help="instead of the default run: the by-blocks task DAG (flame_factor_by_blocks) against "
+                         "the default right-looking loop at each n of --table-ns, one JSON line per order")
     ap.add_argument("--table-ns", default="4096,8192,16384")
     ap.add_argument("--table-nbs", default="64,128,256")
     ap.add_argument("--table-seeds", default="0,1,2")
@@ -91,6 +94,8 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.table:
         return table_mode(args, dev, fl, inputs, torch)
+    if args.dag:
+        return dag_mode(args, dev, fl, inputs, torch)
     if args.copy_probe_gib > 0:
         words = int(args.copy_probe_gib * (1 << 30)) // 8
         src = torch.ones(words, dtype=torch.float64, device=dev)
@@ -477,6 +482,47 @@ def table_mode(args, dev, fl, inputs, torch) -> int:
     for r in rows:
         print(f"| {r['n']} | {r['nb']} | {r['variant']} | {r['ms_median']} | {r['ms_min']} | {r['ms_max']} | "
               f"{r['tflops']} | {r['pct_fp64_peak']} |")
+    return 0
+
+
+def dag_mode(args, dev, fl, inputs, torch) -> int:
+    """The by-blocks task DAG (one persistent launch over 128-blocks) against
+    the default right-looking loop (nb = 512 schedule, lookahead 2) on the same
+    seeded matrix: median of --steps factorizations after --warmup, each on a
+    resident copy restored outside the timed region; the factor of each is
+    checked against the other's (same U up to rounding)."""
+    stream = torch.cuda.current_stream()
+    for n in [int(v) for v in args.table_ns.split(",") if v]:
+        P = inputs.spd_bbt_torch(n, 0, dev)
+        W = torch.empty_strided((n, n), (1, n), dtype=torch.float64, device=dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        res, U = {}, {}
+        for name, fn in (("loop", lambda: fl.factor(W, variant=fl.VAR_RIGHT, nb=512, lookahead=2, info=info)),
+                         ("dag", lambda: fl.factor_by_blocks(W, info=info))):
+            ts = []
+            for r in range(args.warmup + args.steps):
+                W.copy_(P)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if int(info.item()) != 0:
+                    log(f"breakdown n={n} {name}")
+                    return 1
+                if r >= args.warmup:
+                    ts.append(e0.elapsed_time(e1))
+            res[name] = float(np.median(ts))
+            U[name] = torch.triu(W).clone()
+        rel = float((U["dag"] - U["loop"]).abs().max() / U["loop"].abs().max())
+        rec = {"n": n, "loop_ms": round(res["loop"], 3), "dag_ms": round(res["dag"], 3),
+               "dag_tflops": round(potrf_flops(n) / (res["dag"] * 1e-3) / 1e12, 2),
+               "loop_tflops": round(potrf_flops(n) / (res["loop"] * 1e-3) / 1e12, 2),
+               "dag_over_loop": round(res["dag"] / res["loop"], 3), "max_rel_diff_of_factors": rel}
+        print(json.dumps(rec), flush=True)
+        del P, W, U
+        torch.cuda.empty_cache()
     return 0
 
 

@@ -38,8 +38,15 @@ def gemm_source_hash() -> str:
 
 
 def short(name: str, width: int = 72) -> str:
-    s = name.split("(")[0] if "(" in name and "<" not in name.split("(")[0][-1:] else name
-    s = s.replace("void ", "").replace("flame::", "")
+    s = name
+    if s.endswith(")"):  # drop the parameter list (the parenthesis matching the last one)
+        depth = 0
+        for i in range(len(s) - 1, -1, -1):
+            depth += {")": 1, "(": -1}.get(s[i], 0)
+            if depth == 0:
+                s = s[:i]
+                break
+    s = s.replace("void ", "").replace("(anonymous namespace)::", "").replace("flame::", "")
     return s if len(s) <= width else s[:width - 3] + "..."
 
 
