@@ -240,3 +240,48 @@ def _batch_from(g, sizes):
         A[np.diag_indices(n)] += float(n)
         out.append(_symmetrize_upper(A))
     return out
+
+
+def laplacian_grid(dims, stencil: int = 0, shift: float = 0.0):
+    """Discrete Laplacian of a structured grid with Dirichlet boundary, full
+    symmetric rows (CSR: rp int64[n + 1], ci int32, val float64) in natural
+    order (x fastest).  2-D: stencil 5 (default) or 9; 3-D: 7 (default) or 27.
+    Off-diagonal entries -1 for every neighbor of the stencil, diagonal the
+    number of stencil neighbors (so the matrix is irreducibly diagonally
+    dominant, hence SPD) plus ``shift``.  These stand in for the paper's
+    sparse test matrices (nnz per row about 5-9 and about 27)."""
+    import itertools
+
+    dims = tuple(int(d) for d in dims)
+    nd = len(dims)
+    if nd not in (2, 3):
+        raise ValueError("2-D or 3-D grids")
+    stencil = stencil or (5 if nd == 2 else 7)
+    if stencil in (5, 7):
+        offs = [o for o in itertools.product((-1, 0, 1), repeat=nd) if sum(abs(v) for v in o) == 1]
+    elif stencil in (9, 27):
+        offs = [o for o in itertools.product((-1, 0, 1), repeat=nd) if any(o)]
+    else:
+        raise ValueError("stencil 5 / 9 (2-D) or 7 / 27 (3-D)")
+    strides = [1]
+    for d in dims[:-1]:
+        strides.append(strides[-1] * d)
+    n = int(np.prod(dims))
+    coords = np.stack(np.unravel_index(np.arange(n), dims[::-1])[::-1], axis=1)  # (x, y[, z])
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [np.full(n, float(len(offs)) + shift)]
+    for o in offs:
+        c = coords + np.asarray(o)
+        ok = np.all((c >= 0) & (c < np.asarray(dims)), axis=1)
+        src = np.nonzero(ok)[0]
+        dst = (c[ok] * np.asarray(strides)).sum(axis=1)
+        rows.append(src)
+        cols.append(dst)
+        vals.append(np.full(len(src), -1.0))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = np.concatenate(vals)
+    o = np.lexsort((c, r))
+    r, c, v = r[o], c[o], v[o]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, r + 1, 1)
+    return np.cumsum(rp), c.astype(np.int32), v.astype(np.float64)

@@ -43,6 +43,10 @@ def load(path: str) -> ctypes.CDLL:
         L.oracle_solve_upper.restype = None
         L.oracle_max_threads.argtypes = []
         L.oracle_max_threads.restype = i32
+        L.oracle_fill_pattern.argtypes = [i64, dp, dp, i32, dp, dp, dp, i64]
+        L.oracle_fill_pattern.restype = i64
+        L.oracle_ichol_rows.argtypes = [i64, dp, dp, dp]
+        L.oracle_ichol_rows.restype = i32
     return L
 
 

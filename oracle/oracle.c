@@ -253,3 +253,163 @@ void oracle_solve_upper(int64_t n, int64_t nrhs, const double *U, int64_t ldu, d
         }
     }
 }
+
+/*
+ * O6: level(k) fill pattern of the upper factor (Sec. "Symbolic
+ * factorization"; the level of an entry is set during elimination: the
+ * entries of A have level 0, and eliminating k gives entry (i, j), k < i <= j,
+ * the level lev(k,i) + lev(k,j) + 1 when that is lower; entries whose level
+ * would exceed K are not created and take no part in later eliminations).
+ *
+ * Input: the upper pattern of the (already reordered) symmetric matrix as
+ * rows: arp[n + 1], aci (row i holds its columns j >= i, any order; the
+ * diagonal is added if missing).  Row i of U receives contributions only from
+ * the rows k < i that hold column i, and those are final when row i is
+ * formed, so rows are formed in increasing order: a dense work row holds the
+ * levels of row i, and column lists record, for each column j, the rows k < j
+ * holding it (with the position of (k, j) in row k).
+ * Output: rp[n + 1], ci and lev (row i: columns increasing, the diagonal
+ * first, with their levels), written when the entry count fits `cap`;
+ * returns the entry count (call again with a larger cap when it exceeds
+ * cap), -1 on allocation failure.
+ */
+typedef struct {
+    int64_t k, pos;
+} kpos_t;
+
+static int cmp_i32(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+int64_t oracle_fill_pattern(int64_t n, const int64_t *arp, const int32_t *aci, int32_t K, int64_t *rp, int32_t *ci,
+                            int32_t *lev, int64_t cap) {
+    const int32_t INF = 0x7fffffff;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t *w = (int32_t *)malloc(sizeof(int32_t) * nn);
+    int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * nn);
+    int64_t *urp = (int64_t *)malloc(sizeof(int64_t) * (nn + 1));
+    int64_t ucap = 8 * (int64_t)nn, ucount = 0;
+    int32_t *uci = (int32_t *)malloc(sizeof(int32_t) * (size_t)ucap);
+    int32_t *ulev = (int32_t *)malloc(sizeof(int32_t) * (size_t)ucap);
+    kpos_t **col = (kpos_t **)calloc(nn, sizeof(kpos_t *));
+    int64_t *ccnt = (int64_t *)calloc(nn, sizeof(int64_t));
+    int64_t *ccap = (int64_t *)calloc(nn, sizeof(int64_t));
+    int64_t result = -1;
+    if (!w || !touched || !urp || !uci || !ulev || !col || !ccnt || !ccap) goto done;
+    for (int64_t j = 0; j < n; ++j) w[j] = INF;
+    urp[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t nt = 0;
+        w[i] = 0; /* the diagonal always exists */
+        touched[nt++] = (int32_t)i;
+        for (int64_t e = arp[i]; e < arp[i + 1]; ++e) {
+            int32_t j = aci[e];
+            if (j <= i) continue;
+            if (w[j] == INF) touched[nt++] = j;
+            w[j] = 0;
+        }
+        /* eliminate every k < i whose row holds column i */
+        for (int64_t q = 0; q < ccnt[i]; ++q) {
+            const int64_t k = col[i][q].k, pos = col[i][q].pos;
+            const int32_t lki = ulev[pos];
+            for (int64_t e = pos + 1; e < urp[k + 1]; ++e) { /* columns j > i of row k */
+                const int32_t j = uci[e];
+                const int64_t cand = (int64_t)lki + ulev[e] + 1;
+                if (cand <= K && cand < w[j]) {
+                    if (w[j] == INF) touched[nt++] = j;
+                    w[j] = (int32_t)cand;
+                }
+            }
+        }
+        qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+        if (ucount + nt > ucap) {
+            while (ucount + nt > ucap) ucap *= 2;
+            int32_t *a = (int32_t *)realloc(uci, sizeof(int32_t) * (size_t)ucap);
+            if (!a) goto done;
+            uci = a;
+            int32_t *b = (int32_t *)realloc(ulev, sizeof(int32_t) * (size_t)ucap);
+            if (!b) goto done;
+            ulev = b;
+        }
+        for (int64_t t = 0; t < nt; ++t) {
+            const int32_t j = touched[t];
+            uci[ucount] = j;
+            ulev[ucount] = w[j];
+            if (j > i) { /* row i holds column j: record it for row j */
+                if (ccnt[j] == ccap[j]) {
+                    ccap[j] = ccap[j] ? 2 * ccap[j] : 8;
+                    kpos_t *c = (kpos_t *)realloc(col[j], sizeof(kpos_t) * (size_t)ccap[j]);
+                    if (!c) goto done;
+                    col[j] = c;
+                }
+                col[j][ccnt[j]].k = i;
+                col[j][ccnt[j]].pos = ucount;
+                ++ccnt[j];
+            }
+            w[j] = INF;
+            ++ucount;
+        }
+        urp[i + 1] = ucount;
+    }
+    if (ucount <= cap) {
+        for (int64_t i = 0; i <= n; ++i) rp[i] = urp[i];
+        for (int64_t e = 0; e < ucount; ++e) {
+            ci[e] = uci[e];
+            lev[e] = ulev[e];
+        }
+    }
+    result = ucount;
+done:
+    if (col)
+        for (int64_t j = 0; j < n; ++j) free(col[j]);
+    free(w); free(touched); free(urp); free(uci); free(ulev); free(col); free(ccnt); free(ccap);
+    return result;
+}
+
+/*
+ * O7: level(k) incomplete Cholesky, A ~= U^T U on a fixed pattern (the
+ * numeric factorization the paper runs by blocks, Sec. "Numeric
+ * factorization: Cholesky-by-blocks", on the pattern of O6): the loop of
+ * O1 (b = 1), where every update whose target is not in the pattern is
+ * dropped.  Pattern and values as rows: rp[n + 1], ci (row i: columns
+ * increasing, the diagonal first), val (A's upper entries on the pattern, 0
+ * on fill), overwritten with U.  Step k: u_kk := sqrt(a_kk); u_kj := a_kj /
+ * u_kk for j in row k; a_ij -= u_ki u_kj for i <= j, both in row k, (i, j) in
+ * the pattern (found by bisection in row i).  With the complete pattern these
+ * are O1's operations in O1's order.  Returns 0 or the 1-based column of the
+ * first pivot that is not > 0.
+ */
+int oracle_ichol_rows(int64_t n, const int64_t *rp, const int32_t *ci, double *val) {
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t b = rp[k], e = rp[k + 1];
+        if (e <= b || ci[b] != k) return -1; /* the diagonal must lead the row */
+        const double a = val[b];
+        if (!(a > 0.0)) return (int)(k + 1);
+        const double piv = sqrt(a);
+        val[b] = piv;
+        for (int64_t q = b + 1; q < e; ++q) val[q] = val[q] / piv;
+        for (int64_t qc = b + 1; qc < e; ++qc) {
+            const int32_t c = ci[qc];
+            const double ukc = val[qc];
+            for (int64_t qi = b + 1; qi <= qc; ++qi) {
+                const int32_t i = ci[qi];
+                /* (i, c) in row i? */
+                int64_t lo = rp[i], hi = rp[i + 1] - 1;
+                while (lo <= hi) {
+                    const int64_t mid = (lo + hi) / 2;
+                    if (ci[mid] < c)
+                        lo = mid + 1;
+                    else if (ci[mid] > c)
+                        hi = mid - 1;
+                    else {
+                        double p = val[qi] * ukc;
+                        val[mid] = val[mid] - p;
+                        break;
+                    }
+                }
+            }
+        }
+    }
+    return 0;
+}
