@@ -431,6 +431,77 @@ int flame_probe(int32_t kind, int64_t work, int32_t wg_per_cu, void *buf, int64_
  * could not be synchronized (the state is released anyway). */
 int flame_shutdown(void);
 
+/* ---- level(k) incomplete Cholesky by blocks ----------------------------------
+ * The paper's own method (Sec. "Symbolic factorization", Alg. symb_fact;
+ * Sec. "2D sparse partitioned-block matrix"; the numeric Cholesky-by-blocks
+ * of Fig. "sparse-chol"): A ~= U^T U for a sparse SPD A, U restricted to the
+ * level-k fill pattern (the entries of A have level 0; eliminating a pivot
+ * gives (i, j) the level lev(k,i) + lev(k,j) + 1; entries above level k are
+ * dropped).
+ *
+ * flame_ichol_analyze (host only, no device call): the symbolic phase.  The
+ * plan's device memory (block pool, masks, task list, entry maps) is
+ * allocated on the device current at its first flame_ichol_factor /
+ * flame_ichol_values, which binds the plan to that device.
+ *   n          order of A.
+ *   rp, ci     host CSR of A's pattern: rp[n + 1] (int64), ci[rp[n]] (int32);
+ *              both triangles or one, any column order, no duplicate
+ *              entries; the same arrays (and value order) are the input of
+ *              flame_ichol_factor.
+ *   level      k >= 0 (a large k gives the complete factor of the ordered A).
+ *   order      host int64[n], order[new] = old index, or NULL: the library's
+ *              nested dissection (breadth-first level-structure bisection,
+ *              leaves of at most `leaf` vertices).
+ *   bounds     host int64[nranges + 1] (0 = bounds[0] < ... = n): the ranges
+ *              of the 2D block layout in the new numbering; NULL with an
+ *              `order`: ranges of 128.  Ranges longer than 128 are cut.
+ *   leaf       leaf size of the dissection (0 = 128).
+ *   plan       receives the plan (free it with flame_ichol_destroy).
+ * Returns 0, -i for an invalid argument (an `order` that is not a
+ * permutation: -5; bounds that do not tile [0, n): -6), FLAME_ERR_UNSUPPORTED
+ * beyond 4096 blocks per side, FLAME_ERR_NOMEM. */
+typedef struct flame_ichol_plan_s *flame_ichol_plan;
+int flame_ichol_analyze(int64_t n, const int64_t *rp, const int32_t *ci, int32_t level, const int64_t *order,
+                        const int64_t *bounds, int64_t nranges, int32_t leaf, flame_ichol_plan *plan);
+
+/* Sizes of a plan (host): nnz_u = entries of U's pattern, nbt = blocks per
+ * side, nblocks = existing blocks (upper), ntasks = tasks of the DAG,
+ * pool_bytes = device bytes of the block pool, flops = the factorization's
+ * floating-point operations (a multiply and a subtraction per update whose
+ * target is in the pattern, the row scalings and square roots). */
+typedef struct {
+    int64_t n, nnz_a, nnz_u, nbt, nblocks, ntasks, pool_bytes;
+    double flops;
+} flame_ichol_stats_t;
+int flame_ichol_stats(flame_ichol_plan plan, flame_ichol_stats_t *stats);
+
+/* Copies the plan's structure to host arrays (each may be NULL): order[n],
+ * bounds[nbt + 1], U's pattern in the new numbering urp[n + 1] / uci[nnz_u]
+ * (rows, columns increasing, the diagonal first), the block pattern
+ * pattern[nbt * nbt] (row-major, upper), the task list tasks[4 * ntasks]
+ * (type 0 CHOL / 1 TRSM / 2 HERK-GEMM, k, i, j per task, in claim order). */
+int flame_ichol_structure(flame_ichol_plan plan, int64_t *order, int64_t *bounds, int64_t *urp, int32_t *uci,
+                          uint8_t *pattern, int32_t *tasks);
+
+/* The numeric phase on `stream`: A's values vals[rp[n]] (device, float64, in
+ * the order of the ci given to flame_ichol_analyze; only the entries with
+ * new row <= new column are read) are scattered into the plan's block pool
+ * and the task DAG runs there (one persistent launch; CHOL and TRSM of a
+ * block drop fill outside the pattern as each row of U becomes final).
+ * info (device int32): 0, the 1-based new-numbering column of the first
+ * pivot that is not > 0, or -1 if a wait gave up.  The plan holds U until the
+ * next call; calls on one plan must not overlap.  FLAME_ERR_UNSUPPORTED if
+ * the current device is not the plan's. */
+int flame_ichol_factor(flame_ichol_plan plan, const double *vals, int32_t *info, void *stream);
+/* (FLAME_ERR_NOMEM if the plan's first upload fails.) */
+
+/* U's values on its pattern (device uvals[nnz_u], the order of
+ * flame_ichol_structure's urp / uci), from the last flame_ichol_factor. */
+int flame_ichol_values(flame_ichol_plan plan, double *uvals, void *stream);
+
+/* Frees a plan (synchronizes nothing: no call on it may be in flight). */
+int flame_ichol_destroy(flame_ichol_plan plan);
+
 /* ---- status -------------------------------------------------------------- */
 const char *flame_status_string(int status);
 const char *flame_version(void);

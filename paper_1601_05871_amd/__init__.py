@@ -40,6 +40,8 @@ EXPORTS = (
     "flame_trace_enable", "flame_trace_collect", "flame_status_string", "flame_version",
     "flame_solve_mixed", "flame_shutdown", "flame_batched_factor_noalloc", "flame_trace_busy", "flame_probe",
     "flame_select_class", "flame_factor_by_blocks", "flame_by_blocks_tasks",
+    "flame_ichol_analyze", "flame_ichol_stats", "flame_ichol_structure", "flame_ichol_factor", "flame_ichol_values",
+    "flame_ichol_destroy",
 )
 PROBE = {"mfma_f64": 0, "mfma_f32": 1, "mfma_bf16": 2, "copy": 3}
 NOALLOC_MAX_BATCH = 262144
@@ -66,6 +68,12 @@ class Refine(ctypes.Structure):
 class SolveReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("method", ctypes.c_int32), ("eta_max", ctypes.c_double),
                 ("shift", ctypes.c_double), ("factor_info", ctypes.c_int32), ("attempts", ctypes.c_int32)]
+
+
+class IcholStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz_a", ctypes.c_int64), ("nnz_u", ctypes.c_int64), ("nbt", ctypes.c_int64),
+                ("nblocks", ctypes.c_int64), ("ntasks", ctypes.c_int64), ("pool_bytes", ctypes.c_int64),
+                ("flops", ctypes.c_double)]
 
 
 class Choice(ctypes.Structure):
@@ -123,6 +131,12 @@ def lib(path: str | None = None) -> ctypes.CDLL:
     L.flame_shutdown.argtypes = []
     L.flame_factor_by_blocks.argtypes = [i32, i64, vp, i64, vp, vp, vp]
     L.flame_by_blocks_tasks.argtypes = [i64, vp, vp, i64, ctypes.POINTER(i64)]
+    L.flame_ichol_analyze.argtypes = [i64, vp, vp, i32, vp, vp, i64, i32, ctypes.POINTER(vp)]
+    L.flame_ichol_stats.argtypes = [vp, ctypes.POINTER(IcholStats)]
+    L.flame_ichol_structure.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.flame_ichol_factor.argtypes = [vp, vp, vp, vp]
+    L.flame_ichol_values.argtypes = [vp, vp, vp]
+    L.flame_ichol_destroy.argtypes = [vp]
     L.flame_batched_factor_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, vp]
     L.flame_status_string.argtypes = [ctypes.c_int]
     L.flame_status_string.restype = ctypes.c_char_p
@@ -532,3 +546,81 @@ def op_gemm_tn(C, X, Y, upper: bool, trail="native", dtype=None):
                                 _colmajor_ld(X), Y.data_ptr(), _colmajor_ld(Y), C.data_ptr(), _colmajor_ld(C),
                                 _stream_ptr())
     _check("flame_op_gemm_tn", rc)
+
+
+# ---- level(k) incomplete Cholesky by blocks (flame_ichol_*) --------------------
+
+class IcholPlan:
+    """A plan of the level(k) incomplete Cholesky-by-blocks (flame_ichol_*):
+    the symbolic phase on construction (host CSR pattern ``rp`` / ``ci``, numpy
+    int64 / int32), then ``factor(vals)`` with A's values on the device in the
+    same entry order.  ``order`` / ``bounds``: optional ordering (new -> old)
+    and block ranges; ``leaf``: leaf size of the library's dissection."""
+
+    def __init__(self, n: int, rp, ci, level: int, order=None, bounds=None, leaf: int = 0):
+        import numpy as np
+
+        self._rp = np.ascontiguousarray(rp, dtype=np.int64)
+        self._ci = np.ascontiguousarray(ci, dtype=np.int32)
+        self._order = None if order is None else np.ascontiguousarray(order, dtype=np.int64)
+        self._bounds = None if bounds is None else np.ascontiguousarray(bounds, dtype=np.int64)
+        if self._rp.shape != (n + 1,):
+            raise ValueError("rp must have n + 1 entries")
+        if self._ci.shape != (int(self._rp[-1]),):
+            raise ValueError("ci must have rp[n] entries")
+        if self._order is not None and self._order.shape != (n,):
+            raise ValueError("order must have n entries")
+        self._h = ctypes.c_void_p()
+        nr = 0 if self._bounds is None else len(self._bounds) - 1
+        _check("flame_ichol_analyze", lib().flame_ichol_analyze(
+            n, self._rp.ctypes.data, self._ci.ctypes.data, int(level),
+            None if self._order is None else self._order.ctypes.data,
+            None if self._bounds is None else self._bounds.ctypes.data, nr, int(leaf), ctypes.byref(self._h)))
+        st = IcholStats()
+        _check("flame_ichol_stats", lib().flame_ichol_stats(self._h, ctypes.byref(st)))
+        self.stats = {f: getattr(st, f) for f, _ in IcholStats._fields_}
+        self.n = n
+
+    def structure(self) -> dict:
+        """order, bounds, U's pattern (urp, uci, new numbering), the block
+        pattern and the task list, as numpy arrays."""
+        import numpy as np
+
+        st = self.stats
+        out = {"order": np.zeros(self.n, dtype=np.int64), "bounds": np.zeros(st["nbt"] + 1, dtype=np.int64),
+               "urp": np.zeros(self.n + 1, dtype=np.int64), "uci": np.zeros(st["nnz_u"], dtype=np.int32),
+               "pattern": np.zeros((st["nbt"], st["nbt"]), dtype=np.uint8),
+               "tasks": np.zeros((st["ntasks"], 4), dtype=np.int32)}
+        _check("flame_ichol_structure", lib().flame_ichol_structure(
+            self._h, *[out[k].ctypes.data for k in ("order", "bounds", "urp", "uci", "pattern", "tasks")]))
+        return out
+
+    def factor(self, vals, info=None):
+        """Numeric phase on the current stream; returns the device int32 info."""
+        torch = _torch()
+        if vals.dtype != torch.float64 or not vals.is_cuda or vals.numel() != self.stats["nnz_a"]:
+            raise ValueError("vals must be a float64 device tensor with one value per entry of A")
+        vals = vals.contiguous()
+        if info is None:
+            info = torch.zeros(1, dtype=torch.int32, device=vals.device)
+        _check("flame_ichol_factor", lib().flame_ichol_factor(self._h, vals.data_ptr(), info.data_ptr(),
+                                                              _stream_ptr()))
+        return info
+
+    def values(self):
+        """U's values on its pattern (device float64, nnz_u)."""
+        torch = _torch()
+        out = torch.empty(self.stats["nnz_u"], dtype=torch.float64, device="cuda")
+        _check("flame_ichol_values", lib().flame_ichol_values(self._h, out.data_ptr(), _stream_ptr()))
+        return out
+
+    def close(self) -> None:
+        if self._h:
+            lib().flame_ichol_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

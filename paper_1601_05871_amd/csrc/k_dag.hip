@@ -63,6 +63,18 @@ struct DagP {
     int32_t *upd;         // nbt x nbt
     int32_t *info;
     int stage;            // 1: operand columns 16-byte aligned (A and lda): LDS-staged updates
+    // block-sparse form (the incomplete factorization): A is a pool of
+    // 128 x 128 tiles (leading dimension 128), block (i, j) at A + boff[i nbt + j]
+    // (-1: missing), of order bstart[i + 1] - bstart[i] x bstart[j + 1] - bstart[j];
+    // masks: per tile (in pool order) 128 columns x 128 bits, bit r of column c
+    // set when (r, c) is in the pattern of the factor
+    const int64_t *boff;
+    const int32_t *bstart;
+    const uint64_t *masks;
+    // breakdowns of the block-sparse form: max of INT32_MAX - column (so the
+    // lowest column wins and 0 means none); independent blocks may break down
+    // in any order, so a breakdown does not stop the launch
+    int32_t *bad_enc;
 };
 
 // Waits (bounded) until *p >= want; false on abort or give-up (which sets
@@ -160,7 +172,10 @@ struct DagShared {
     union {
         double band[kLdsDoubles];                // CHOL block (band layout) or TRSM scratch
         char stage[kStages][2][kT * 128];        // update: [chunk mod kStages][X or Y][column x 128 bytes]
+        double tile[kT * kT];                    // masked TRSM: the diagonal block's factor
     } u;
+    double row[kT];                              // masked CHOL / TRSM: the row just finalized
+    double piv;
     int s_task, s_ok, s_bad;
 };
 
@@ -293,6 +308,120 @@ __device__ __forceinline__ void task_trsm(const double *U, double *X, int64_t ld
     for (int c0 = 0; c0 < m; c0 += 64) trsm_cols<double, 8>(kT, m, U, lda, X, lda, c0 + 16 * wave, Ds, Rt + 16 * wave);
 }
 
+// ---- the incomplete factorization's block operations ------------------------
+// Level(k) incomplete Cholesky drops every update whose target lies outside
+// the pattern.  A dropped entry is never used as a multiplier, so it suffices
+// to drop it when its row of U becomes final: the CHOL and TRSM of a block
+// zero each row's entries outside the pattern as soon as the row is
+// computed, before it updates the rows below; the HERK / GEMM updates write
+// the whole block (their entries outside the pattern are dropped when that
+// block's own rows become final).  The element form is kept: thread (c, h)
+// holds column c, rows 64 h .. 64 h + 63 of the block in registers; row j is
+// finalized by the 128 threads of half j / 64 and broadcast through LDS.
+// Register indices are compile-time: row j of a thread's 64 is selected by
+// comparison, not by indexing.
+
+// Selects / replaces element `idx` (wave-uniform) of a thread's 64 values.
+__device__ __forceinline__ double pick64(const double (&v)[64], int idx) {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < 64; ++i) r = (i == idx) ? v[i] : r;
+    return r;
+}
+__device__ __forceinline__ void put64(double (&v)[64], int idx, double x) {
+#pragma unroll
+    for (int i = 0; i < 64; ++i) v[i] = (i == idx) ? x : v[i];
+}
+
+// Incomplete CHOL of the b x b diagonal tile (leading dimension 128, the
+// whole 128 x 128 tile readable); returns 0 or the 1-based position of the
+// first pivot that is not > 0 (uniform).  Writes the upper triangle.
+__device__ __forceinline__ int task_chol_masked(double *A, int b, const uint64_t *mask, DagShared &sh) {
+    const int tid = threadIdx.x, c = tid & (kT - 1), h = tid >> 7;
+    const uint64_t m = mask[2 * c + h];  // bit i: row 64 h + i of column c in the pattern
+    double a[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) a[i] = A[64 * h + i + (int64_t)c * kT];
+    int bad = 0;
+    for (int j = 0; j < b; ++j) {
+        const int hj = j >> 6, ij = j & 63;
+        const double v = pick64(a, ij);
+        if (h == hj && c == j) sh.piv = v;
+        __syncthreads();
+        const double d = sh.piv;
+        if (__builtin_amdgcn_readfirstlane(d > 0.0 ? 1 : 0) == 0) {  // uniform: every thread read the same pivot
+            bad = j + 1;
+            break;
+        }
+        const double p = sqrt(d);
+        if (h == hj && c >= j && c < b) {
+            const double u = (c == j) ? p : (((m >> ij) & 1) ? v / p : 0.0);
+            put64(a, ij, u);
+            sh.row[c] = u;
+        }
+        __syncthreads();
+        if (c > j && c < b) {
+            const double ujc = sh.row[c];
+#pragma unroll
+            for (int i = 0; i < 64; ++i) {
+                const int r = 64 * h + i;
+                if (r > j && r <= c) a[i] -= sh.row[r] * ujc;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        const int r = 64 * h + i;
+        if (r <= c && c < b) A[r + (int64_t)c * kT] = a[i];
+    }
+    return bad;
+}
+
+// Incomplete TRSM X := triu(U)^{-T} X for the bk x m tile X of the block row
+// whose diagonal factor is U (both tiles of leading dimension 128, readable
+// whole): forward substitution row by row, each row dropped outside the
+// pattern as soon as it is computed.
+__device__ __forceinline__ void task_trsm_masked(const double *U, double *X, int bk, int m, const uint64_t *mask,
+                                                 DagShared &sh) {
+    const int tid = threadIdx.x, c = tid & (kT - 1), h = tid >> 7;
+    typedef double d2_t __attribute__((ext_vector_type(2)));
+    // the diagonal factor into LDS (column-major, as the tile)
+    const d2_t *U2 = reinterpret_cast<const d2_t *>(U);
+    d2_t *T2 = reinterpret_cast<d2_t *>(sh.u.tile);
+#pragma unroll 4
+    for (int e = tid; e < kT * kT / 2; e += 256) T2[e] = U2[e];
+    const uint64_t mk = mask[2 * c + h];
+    double x[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) x[i] = X[64 * h + i + (int64_t)c * kT];
+    __syncthreads();
+    const double *Ut = sh.u.tile;
+    for (int r = 0; r < bk; ++r) {
+        const int hr = r >> 6, ir = r & 63;
+        if (h == hr && c < m) {
+            const double v = pick64(x, ir);
+            const double u = ((mk >> ir) & 1) ? v / Ut[r + r * kT] : 0.0;
+            put64(x, ir, u);
+            sh.row[c] = u;
+        }
+        __syncthreads();
+        if (c < m) {
+            const double xr = sh.row[c];
+#pragma unroll
+            for (int i = 0; i < 64; ++i) {
+                const int rr = 64 * h + i;
+                if (rr > r && rr < bk) x[i] -= Ut[r + rr * kT] * xr;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        const int rr = 64 * h + i;
+        if (rr < bk && c < m) X[rr + (int64_t)c * kT] = x[i];
+    }
+}
+
 // Loop control is wave-uniform (readfirstlane) and thread 0 has ONE region
 // per iteration, publish of the finished task followed by the next claim,
 // with a barrier after it: with a claim region at the top of the loop and a
@@ -300,13 +429,14 @@ __device__ __forceinline__ void task_trsm(const double *U, double *X, int64_t ld
 // one into the other across the back edge; the loop then has two entries and
 // its structurized form lets the other lanes of wavefront 0 run ahead of
 // thread 0 to the next barrier with the old task index.
+template <bool SPARSE>
 __global__ __launch_bounds__(256, 1) void k_by_blocks(DagP p) {
     __shared__ __attribute__((aligned(16))) DagShared sh;
     double *lds = sh.u.band;
     int &s_task = sh.s_task, &s_ok = sh.s_ok, &s_bad = sh.s_bad;
     const int tid = threadIdx.x;
     const int nbt = p.nbt;
-    const int64_t lda = p.lda;
+    const int64_t lda = SPARSE ? kT : p.lda;
     if (tid == 0) s_task = atomicAdd(p.claim, 1);
     __syncthreads();
     for (;;) {
@@ -335,13 +465,29 @@ __global__ __launch_bounds__(256, 1) void k_by_blocks(DagP p) {
         if (__builtin_amdgcn_readfirstlane(s_ok) == 0) break;
         // every wavefront takes an acquire of its own before reading the blocks
         acquire_dev();
-        auto blk = [&](int bi, int bj) { return p.A + (int64_t)bi * kT + (int64_t)bj * kT * lda; };
-        auto width = [&](int b) { return (int)min((int64_t)kT, p.n - (int64_t)b * kT); };
-        if (type == 0)
+        auto blk = [&](int bi, int bj) {
+            if constexpr (SPARSE)
+                return p.A + p.boff[(int64_t)bi * nbt + bj];
+            else
+                return p.A + (int64_t)bi * kT + (int64_t)bj * kT * lda;
+        };
+        auto width = [&](int b) {
+            if constexpr (SPARSE)
+                return (int)(p.bstart[b + 1] - p.bstart[b]);
+            else
+                return (int)min((int64_t)kT, p.n - (int64_t)b * kT);
+        };
+        auto mask = [&](int bi, int bj) { return p.masks + (p.boff[(int64_t)bi * nbt + bj] / (kT * kT)) * (2 * kT); };
+        if (SPARSE && type == 0) {
+            const int bad = task_chol_masked(blk(k, k), width(k), mask(k, k), sh);
+            if (bad != 0 && tid == 0) atomicMax(p.bad_enc, (int32_t)(0x7fffffff - (p.bstart[k] + bad)));
+        } else if (SPARSE && type == 1) {
+            task_trsm_masked(blk(k, k), blk(k, j), width(k), width(j), mask(k, j), sh);
+        } else if (type == 0)
             task_chol(blk(k, k), lda, width(k), lds, &s_bad, k, p.info, p.abort_flag);
         else if (type == 1)
             task_trsm(blk(k, k), blk(k, j), lda, width(j), lds);
-        else if (p.stage)
+        else if (SPARSE || p.stage)
             block_update_lds(blk(k, i), blk(k, j), blk(i, j), lda, width(i), width(j), i == j, sh.u.stage);
         else
             block_update(blk(k, i), blk(k, j), blk(i, j), lda, width(i), width(j), i == j);
@@ -424,7 +570,7 @@ int launch_by_blocks(int64_t n, double *A, int64_t lda, const int4 *tasks, int64
     if (grid == 0) {
         int cus = 0, per = 0;
         FLAME_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        FLAME_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_by_blocks, 256, 0));
+        FLAME_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_by_blocks<false>, 256, 0));
         grid = std::max(1, cus * std::max(1, per));
         if (dev < 64) grid_cache[dev] = grid;
     }
@@ -441,12 +587,108 @@ int launch_by_blocks(int64_t n, double *A, int64_t lda, const int4 *tasks, int64
     p.upd = ints + 2 + (int64_t)nbt * nbt;
     p.info = info;
     p.stage = (((uintptr_t)A & 15) == 0 && (lda & 1) == 0) ? 1 : 0;
+    p.boff = nullptr;
+    p.bstart = nullptr;
+    p.masks = nullptr;
+    p.bad_enc = nullptr;
     const int tr = trace_begin(FLAME_KC_OTHER, s);
-    hipLaunchKernelGGL(k_by_blocks, dim3((unsigned)std::min<int64_t>(grid, ntasks)), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_by_blocks<false>, dim3((unsigned)std::min<int64_t>(grid, ntasks)), dim3(256), 0, s, p);
     FLAME_CHECK_LAUNCH();
     const double dn = (double)n;
     trace_end(tr, s, dn * dn * dn / 3.0, 16.0 * dn * dn);
     hipLaunchKernelGGL(k_dag_abort_info, dim3(1), dim3(64), 0, s, p.abort_flag, info);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+// ---- level(k) incomplete Cholesky-by-blocks on a tile pool -----------------
+
+namespace {
+
+__global__ void k_zero_f64(double *p, int64_t count) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0.0;
+}
+
+// pool[map[e]] = vals[e] for the upper entries of A (map[e] < 0: lower, skipped)
+__global__ void k_scatter_vals(int64_t nnz, const int64_t *__restrict__ map, const double *__restrict__ vals,
+                               double *__restrict__ pool) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = map[e];
+        if (o >= 0) pool[o] = vals[e];
+    }
+}
+
+__global__ void k_gather_vals(int64_t nnz, const int64_t *__restrict__ map, const double *__restrict__ pool,
+                              double *__restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = pool[map[e]];
+}
+
+// info: -1 when a wait gave up, else the lowest breakdown column, else 0
+__global__ void k_ichol_info(const int32_t *abort_flag, const int32_t *bad_enc, int32_t *info) {
+    if (threadIdx.x == 0) *info = (*abort_flag == 1) ? -1 : (*bad_enc > 0 ? 0x7fffffff - *bad_enc : 0);
+}
+
+unsigned grid_for(int64_t count) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 65536)); }
+
+}  // namespace
+
+// Zeroes the pool, scatters A's upper entries into it, runs the task DAG of
+// the block pattern on it (masked CHOL / TRSM, staged updates) and sets info
+// (-1: a wait gave up; else the lowest breakdown column).  ints: claim,
+// abort, fin[nbt^2], upd[nbt^2], breakdown (cleared here).
+int launch_ichol_dag(double *pool, int64_t pool_elems, const double *vals, int64_t nnz_a, const int64_t *amap,
+                     const int64_t *boff, const int32_t *bstart, const uint64_t *masks, int nbt, const int4 *tasks,
+                     int64_t ntasks, int32_t *ints, int32_t *info, hipStream_t s) {
+    const int64_t nints = 3 + 2 * (int64_t)nbt * nbt;
+    int rc = launch_zero_i32(ints, nints, s);
+    if (rc) return rc;
+    rc = launch_zero_i32(info, 1, s);
+    if (rc) return rc;
+    if (pool_elems > 0) {
+        hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(pool_elems)), dim3(256), 0, s, pool, pool_elems);
+        FLAME_CHECK_LAUNCH();
+    }
+    if (nnz_a > 0) {
+        hipLaunchKernelGGL(k_scatter_vals, dim3(grid_for(nnz_a)), dim3(256), 0, s, nnz_a, amap, vals, pool);
+        FLAME_CHECK_LAUNCH();
+    }
+    if (ntasks == 0) return FLAME_OK;
+    int dev = 0, cus = 0, per = 0;
+    FLAME_HIP(hipGetDevice(&dev));
+    FLAME_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    FLAME_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_by_blocks<true>, 256, 0));
+    const int64_t grid = std::max(1, cus * std::max(1, per));
+    DagP p;
+    p.n = 0;
+    p.A = pool;
+    p.lda = kT;
+    p.nbt = nbt;
+    p.tasks = tasks;
+    p.ntasks = ntasks;
+    p.claim = ints;
+    p.abort_flag = ints + 1;
+    p.fin = ints + 2;
+    p.upd = ints + 2 + (int64_t)nbt * nbt;
+    p.info = info;
+    p.stage = 1;
+    p.boff = boff;
+    p.bstart = bstart;
+    p.masks = masks;
+    p.bad_enc = ints + 2 + 2 * (int64_t)nbt * nbt;
+    const int tr = trace_begin(FLAME_KC_OTHER, s);
+    hipLaunchKernelGGL(k_by_blocks<true>, dim3((unsigned)std::min<int64_t>(grid, ntasks)), dim3(256), 0, s, p);
+    FLAME_CHECK_LAUNCH();
+    trace_end(tr, s, 0.0, 0.0);
+    hipLaunchKernelGGL(k_ichol_info, dim3(1), dim3(64), 0, s, p.abort_flag, p.bad_enc, info);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int launch_gather_vals(int64_t nnz, const int64_t *map, const double *pool, double *out, hipStream_t s) {
+    if (nnz <= 0) return FLAME_OK;
+    hipLaunchKernelGGL(k_gather_vals, dim3(grid_for(nnz)), dim3(256), 0, s, nnz, map, pool, out);
     FLAME_CHECK_LAUNCH();
     return FLAME_OK;
 }

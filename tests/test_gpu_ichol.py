@@ -1,0 +1,111 @@
+"""Level(k) incomplete Cholesky-by-blocks on the device (flame_ichol_factor)
+against the oracle's element-by-element incomplete factor (oracle/ichol.py)
+on the same ordering and pattern: 2-D and 3-D grid Laplacians, levels 0-3,
+the oracle's nested dissection ranges and plain 128-ranges, the complete
+factor, breakdown, determinism, and the library's own ordering (checked by
+the defining property (U^T U)_ij = A_ij on the pattern)."""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+import oracle.ichol as oi
+import paper_1601_05871_amd as fl
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _plan_and_factor(dims, stencil, k, leaf=24, ranges=True, shift=0.0, order=None):
+    rp, ci, v = inputs.laplacian_grid(dims, stencil, shift)
+    n = len(rp) - 1
+    if order is None:
+        order, rr = oi.nd_grid(dims, leaf=leaf)
+        bounds = [0] + [e for _, e in rr] if ranges else None
+    else:
+        bounds = None
+    P = fl.IcholPlan(n, rp, ci, k, order=order, bounds=bounds)
+    info = P.factor(torch.from_numpy(v).to(DEV))
+    U = P.values().cpu().numpy()
+    return rp, ci, v, n, order, P, int(info.item()), U
+
+
+def _oracle(rp, ci, v, n, order, k):
+    urp, uci, uv = oi.permute_upper(n, rp, ci, v, order)
+    prp, pci, _ = oi.fill_pattern(n, urp, uci, k)
+    U, info = oi.ichol(prp, pci, oi.values_on(prp, pci, urp, uci, uv))
+    return prp, pci, U, info, (urp, uci, uv)
+
+
+@pytest.mark.parametrize("dims,stencil", [((24, 23), 5), ((20, 19), 9), ((9, 8, 8), 7), ((7, 7, 6), 27)])
+@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("ranges", [True, False])
+def test_ichol_vs_oracle(dims, stencil, k, ranges):
+    print(f"[ichol] {dims} stencil={stencil} k={k} ranges={ranges}", flush=True)
+    rp, ci, v, n, order, P, info, U = _plan_and_factor(dims, stencil, k, ranges=ranges)
+    prp, pci, Uo, io, _ = _oracle(rp, ci, v, n, order, k)
+    st = P.structure()
+    assert np.array_equal(st["urp"], prp) and np.array_equal(st["uci"], pci)
+    assert info == io == 0
+    assert np.max(np.abs(U - Uo)) <= 1e-13 * np.max(np.abs(Uo))
+
+
+def test_ichol_level3_and_larger_grid():
+    print("[ichol] 2-D 64 x 60, k = 3", flush=True)
+    rp, ci, v, n, order, P, info, U = _plan_and_factor((64, 60), 5, 3, leaf=64)
+    prp, pci, Uo, io, _ = _oracle(rp, ci, v, n, order, 3)
+    assert info == io == 0
+    assert np.max(np.abs(U - Uo)) <= 1e-13 * np.max(np.abs(Uo))
+
+
+def test_ichol_complete_equals_dense_factor():
+    """k = n: no fill dropped, the factor is the complete Cholesky factor of
+    the ordered matrix (the oracle's unblocked loop on the dense matrix)."""
+    dims = (18, 17)
+    rp, ci, v, n, order, P, info, U = _plan_and_factor(dims, 5, 10 ** 6, leaf=20)
+    assert info == 0
+    st = P.structure()
+    urp, uci, uv = oi.permute_upper(n, rp, ci, v, order)
+    W, i1 = oracle.potrf(np.asfortranarray(oi.to_dense(urp, uci, uv)))
+    D = oi.to_dense(st["urp"], st["uci"], U)
+    assert i1 == 0
+    assert np.max(np.abs(D - np.triu(W))) <= 1e-13 * np.max(np.abs(W))
+
+
+def test_ichol_breakdown_column():
+    """A negative shift makes A indefinite: info is the oracle's pivot (new
+    numbering), and the next call on a good matrix is clean."""
+    dims = (20, 20)
+    rp, ci, v, n, order, P, info, U = _plan_and_factor(dims, 5, 1, shift=-3.5)
+    _, _, _, io, _ = _oracle(rp, ci, v, n, order, 1)
+    assert io > 0 and info == io
+    rp2, ci2, v2 = inputs.laplacian_grid(dims, 5)
+    info2 = P.factor(torch.from_numpy(v2).to(DEV))
+    assert int(info2.item()) == 0
+    _, _, Uo, _, _ = _oracle(rp2, ci2, v2, n, order, 1)
+    assert np.max(np.abs(P.values().cpu().numpy() - Uo)) <= 1e-13 * np.max(np.abs(Uo))
+
+
+def test_ichol_deterministic():
+    rp, ci, v, n, order, P, info, U = _plan_and_factor((30, 30), 9, 2)
+    P.factor(torch.from_numpy(v).to(DEV))
+    assert np.array_equal(P.values().cpu().numpy(), U)
+
+
+@pytest.mark.parametrize("dims,stencil,k", [((40, 40), 5, 1), ((12, 12, 12), 7, 1), ((8, 8, 8), 27, 0)])
+def test_ichol_library_ordering_property(dims, stencil, k):
+    """The library's own dissection: the factor satisfies (U^T U)_ij = A_ij
+    on its pattern (the incomplete factor's defining property)."""
+    rp, ci, v = inputs.laplacian_grid(dims, stencil)
+    n = len(rp) - 1
+    P = fl.IcholPlan(n, rp, ci, k, leaf=48)
+    info = P.factor(torch.from_numpy(v).to(DEV))
+    assert int(info.item()) == 0
+    st = P.structure()
+    D = oi.to_dense(st["urp"], st["uci"], P.values().cpu().numpy())
+    urp, uci, uv = oi.permute_upper(n, rp, ci, v, st["order"])
+    A = oi.to_dense(urp, uci, uv)
+    R = D.T @ D - (A + np.triu(A, 1).T)
+    mask = oi.to_dense(st["urp"], st["uci"], np.ones(len(st["uci"]))) > 0
+    assert np.max(np.abs(R[mask])) <= 1e-13 * np.max(np.abs(A))
