@@ -67,6 +67,9 @@ def main() -> int:
     ap.add_argument("--dag", action="store_true",
                     help="instead of the default run: the by-blocks task DAG (flame_factor_by_blocks) against "
                          "the default right-looking loop at each n of --table-ns, one JSON line per order")
+    ap.add_argument("--ichol", action="store_true",
+                    help="instead of the default run: level(k) incomplete Cholesky-by-blocks (flame_ichol_*) on "
+                         "grid Laplacians, with the oracle's sequential incomplete factor timed beside it")
     ap.add_argument("--table-ns", default="4096,8192,16384")
     ap.add_argument("--table-nbs", default="64,128,256")
     ap.add_argument("--table-seeds", default="0,1,2")
@@ -96,6 +99,8 @@ def main() -> int:
         return table_mode(args, dev, fl, inputs, torch)
     if args.dag:
         return dag_mode(args, dev, fl, inputs, torch)
+    if args.ichol:
+        return ichol_mode(args, dev, fl, inputs, torch)
     if args.copy_probe_gib > 0:
         words = int(args.copy_probe_gib * (1 << 30)) // 8
         src = torch.ones(words, dtype=torch.float64, device=dev)
@@ -522,6 +527,70 @@ def dag_mode(args, dev, fl, inputs, torch) -> int:
                "dag_over_loop": round(res["dag"] / res["loop"], 3), "max_rel_diff_of_factors": rel}
         print(json.dumps(rec), flush=True)
         del P, W, U
+        torch.cuda.empty_cache()
+    return 0
+
+
+ICHOL_WORKLOADS = (((512, 512), 5, 0), ((512, 512), 5, 1), ((512, 512), 5, 2), ((64, 64, 64), 7, 0),
+                   ((64, 64, 64), 7, 1), ((40, 40, 40), 27, 0), ((40, 40, 40), 27, 1))
+
+
+def ichol_mode(args, dev, fl, inputs, torch) -> int:
+    """Level(k) incomplete Cholesky of grid Laplacians (2-D 5-point 512^2 and
+    3-D 7-point 64^3, about 5-7 entries per row, and 3-D 27-point 40^3, 27 per
+    row, standing in for the paper's two classes of sparse matrices): the
+    library's symbolic phase (host) with its own nested dissection, then the
+    numeric phase on the device, median of --steps after --warmup (A's values
+    resident on the device, the pool cleared and refilled inside each timed
+    call); beside it the oracle's sequential incomplete factor (its own grid
+    dissection and symbolic phase, untimed) on the host, one run.  One JSON
+    line per workload."""
+    import time
+
+    import oracle.ichol as oi
+
+    stream = torch.cuda.current_stream()
+    for dims, stencil, k in ICHOL_WORKLOADS:
+        rp, ci, v = inputs.laplacian_grid(dims, stencil)
+        n = len(rp) - 1
+        t0 = time.perf_counter()
+        P = fl.IcholPlan(n, rp, ci, k, leaf=256)
+        t_an = time.perf_counter() - t0
+        vals = torch.from_numpy(v).to(dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        ts = []
+        for r in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            P.factor(vals, info=info)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if int(info.item()) != 0:
+                log(f"ichol breakdown {dims} k={k}: {int(info.item())}")
+                return 1
+            if r >= args.warmup:
+                ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        st = P.stats
+        # the oracle, sequential C, on its own ordering of the same matrix
+        order, _ = oi.nd_grid(dims, leaf=256)
+        urp, uci, uv = oi.permute_upper(n, rp, ci, v, order)
+        prp, pci, _ = oi.fill_pattern(n, urp, uci, k)
+        ov = oi.values_on(prp, pci, urp, uci, uv)
+        t0 = time.perf_counter()
+        _, oinfo = oi.ichol(prp, pci, ov)
+        cpu_ms = (time.perf_counter() - t0) * 1e3
+        rec = {"workload": f"{len(dims)}-D {stencil}-point grid {'x'.join(map(str, dims))}", "n": n, "level": k,
+               "nnz_a_upper": int((len(ci) + n) // 2), "nnz_u": st["nnz_u"], "blocks_per_side": st["nbt"],
+               "blocks": st["nblocks"], "tasks": st["ntasks"], "gflop": round(st["flops"] / 1e9, 4),
+               "analyze_host_ms": round(t_an * 1e3, 1), "factor_ms": round(ms, 3),
+               "gflops": round(st["flops"] / (ms * 1e-3) / 1e9, 3),
+               "oracle_cpu": {"ms": round(cpu_ms, 3), "nnz_u": int(len(pci)), "threads": 1, "info": oinfo},
+               "gpu_over_cpu_speedup": round(cpu_ms / ms, 2)}
+        print(json.dumps(rec), flush=True)
+        P.close()
+        del vals
         torch.cuda.empty_cache()
     return 0
 

@@ -25,14 +25,15 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <queue>
 #include <vector>
 
 #include "flame_internal.h"
 
 namespace flame {
 int launch_ichol_dag(double *pool, int64_t pool_elems, const double *vals, int64_t nnz_a, const int64_t *amap,
-                     const int64_t *boff, const int32_t *bstart, const uint64_t *masks, int nbt, const int4 *tasks,
-                     int64_t ntasks, int32_t *ints, int32_t *info, hipStream_t s);
+                     const int64_t *boff, const int32_t *bstart, const uint64_t *masks, const uint64_t *rowocc, int nbt,
+                     const int4 *tasks, int64_t ntasks, int32_t *ints, int32_t *info, hipStream_t s);
 int launch_gather_vals(int64_t nnz, const int64_t *map, const double *pool, double *out, hipStream_t s);
 }  // namespace flame
 
@@ -227,6 +228,94 @@ std::vector<int4> sparse_tasks(int nbt, const std::vector<std::vector<int32_t>> 
     return out;
 }
 
+// The claim order for a sparse pattern.  Any order in which every task
+// follows the tasks it waits for keeps the launch progressing; for a nested
+// dissection the by-iteration order above leaves workgroups waiting on
+// separator tasks claimed long before their subtrees are done.  So the list is
+// reordered by a simulated list schedule: tasks with estimated costs (`cost`,
+// per type) on `workers` workgroups, a ready task with the longest remaining
+// path to the end first, listed by simulated start time.  The per-block update
+// chains keep their iteration order (each update waits for the previous one).
+std::vector<int4> schedule_order(const std::vector<int4> &tasks, int nbt, const std::vector<int32_t> &bid,
+                                 int64_t nblocks, int workers, const double cost[3]) {
+    const int64_t T = (int64_t)tasks.size();
+    std::vector<int64_t> chol_of(nbt, -1);
+    std::vector<std::vector<int64_t>> deps(T);
+    // per existing block: its TRSM and the updates into it, by need
+    auto id = [&](int i, int j) { return bid[(size_t)i * nbt + j]; };
+    std::vector<std::vector<std::pair<int32_t, int64_t>>> upd_into(nblocks);
+    std::vector<int64_t> trsm_of(nblocks, -1);
+    for (int64_t t = 0; t < T; ++t) {
+        const int type = tasks[t].x & 3, k = tasks[t].x >> 2;
+        if (type == 0) chol_of[k] = t;
+        else if (type == 1) trsm_of[id(k, tasks[t].z)] = t;
+        else upd_into[id(tasks[t].y, tasks[t].z)].push_back({tasks[t].w, t});
+    }
+    for (auto &v : upd_into) std::sort(v.begin(), v.end());
+    auto last_upd = [&](int i, int j) -> int64_t {
+        const auto &v = upd_into[id(i, j)];
+        return v.empty() ? -1 : v.back().second;
+    };
+    for (int64_t t = 0; t < T; ++t) {
+        const int type = tasks[t].x & 3, k = tasks[t].x >> 2, i = tasks[t].y, j = tasks[t].z;
+        auto add = [&](int64_t d) {
+            if (d >= 0) deps[t].push_back(d);
+        };
+        if (type == 0) {
+            add(last_upd(k, k));
+        } else if (type == 1) {
+            add(chol_of[k]);
+            add(last_upd(k, j));
+        } else {
+            add(trsm_of[id(k, i)]);
+            add(trsm_of[id(k, j)]);
+            const int need = tasks[t].w;
+            if (need > 0) add(upd_into[id(i, j)][need - 1].second);
+        }
+    }
+    std::vector<std::vector<int64_t>> succ(T);
+    std::vector<int32_t> indeg(T, 0);
+    for (int64_t t = 0; t < T; ++t)
+        for (int64_t d : deps[t]) {
+            succ[d].push_back(t);
+            ++indeg[t];
+        }
+    // longest path to the end (the list is already a topological order)
+    std::vector<double> bl(T, 0.0);
+    for (int64_t t = T - 1; t >= 0; --t) {
+        double m = 0.0;
+        for (int64_t q : succ[t]) m = std::max(m, bl[q]);
+        bl[t] = cost[tasks[t].x & 3] + m;
+    }
+    // list scheduling
+    typedef std::pair<double, int64_t> Item;
+    std::priority_queue<Item> ready;  // highest remaining path first
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> running;  // by finish time
+    for (int64_t t = 0; t < T; ++t)
+        if (indeg[t] == 0) ready.push({bl[t], -t});
+    std::vector<int4> out;
+    out.reserve(T);
+    double now = 0.0;
+    int busy = 0;
+    while ((int64_t)out.size() < T) {
+        while (busy < workers && !ready.empty()) {
+            const int64_t t = -ready.top().second;
+            ready.pop();
+            out.push_back(tasks[t]);
+            running.push({now + cost[tasks[t].x & 3], t});
+            ++busy;
+        }
+        if (running.empty()) break;  // (cannot happen for a valid list)
+        const Item f = running.top();
+        running.pop();
+        --busy;
+        now = f.first;
+        for (int64_t q : succ[f.second])
+            if (--indeg[q] == 0) ready.push({bl[q], -q});
+    }
+    return out;
+}
+
 }  // namespace
 
 struct flame_ichol_plan_s {
@@ -241,11 +330,12 @@ struct flame_ichol_plan_s {
     std::vector<uint8_t> pattern;  // nbt x nbt, upper
     std::vector<int4> tasks;
     // host copies of what goes to the device
-    std::vector<uint64_t> h_masks;
+    std::vector<uint64_t> h_masks, h_rowocc;
     std::vector<int64_t> h_boff, h_amap, h_umap;
     std::vector<int32_t> h_bstart;
     double *pool = nullptr;
     uint64_t *masks = nullptr;
+    uint64_t *rowocc = nullptr;
     int64_t *boff = nullptr;
     int32_t *bstart = nullptr;
     int4 *dtasks = nullptr;
@@ -264,7 +354,7 @@ void free_plan(flame_ichol_plan_s *p) {
     }
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess && cur != p->dev) (void)hipSetDevice(p->dev);
-    for (void *q : {(void *)p->pool, (void *)p->masks, (void *)p->boff, (void *)p->bstart, (void *)p->dtasks,
+    for (void *q : {(void *)p->pool, (void *)p->masks, (void *)p->rowocc, (void *)p->boff, (void *)p->bstart, (void *)p->dtasks,
                     (void *)p->ints, (void *)p->amap, (void *)p->umap})
         if (q != nullptr) (void)hipFree(q);
     if (cur != p->dev) (void)hipSetDevice(cur);
@@ -291,6 +381,7 @@ int ensure_device(flame_ichol_plan_s *p) {
     const size_t pool_bytes = std::max<int64_t>(1, p->nblocks) * (size_t)kT * kT * sizeof(double);
     if (hipMalloc((void **)&p->pool, pool_bytes) != hipSuccess) rc = FLAME_ERR_NOMEM;
     if (!rc) rc = upload(&p->masks, p->h_masks);
+    if (!rc) rc = upload(&p->rowocc, p->h_rowocc);
     if (!rc) rc = upload(&p->boff, p->h_boff);
     if (!rc) rc = upload(&p->bstart, p->h_bstart);
     if (!rc) rc = upload(&p->dtasks, p->tasks);
@@ -299,7 +390,7 @@ int ensure_device(flame_ichol_plan_s *p) {
     if (!rc && hipMalloc((void **)&p->ints, (3 + 2 * (size_t)p->nbt * p->nbt) * sizeof(int32_t)) != hipSuccess)
         rc = FLAME_ERR_NOMEM;
     if (rc) {  // back to unbound: a later call tries again
-        for (void **q : {(void **)&p->pool, (void **)&p->masks, (void **)&p->boff, (void **)&p->bstart,
+        for (void **q : {(void **)&p->pool, (void **)&p->masks, (void **)&p->rowocc, (void **)&p->boff, (void **)&p->bstart,
                          (void **)&p->dtasks, (void **)&p->ints, (void **)&p->amap, (void **)&p->umap})
             if (*q != nullptr) {
                 (void)hipFree(*q);
@@ -439,7 +530,11 @@ int flame_ichol_analyze(int64_t n, const int64_t *rp, const int32_t *ci, int32_t
                 if (bj > bi) rows[bi].push_back(bj);
             }
     p->nblocks = nblocks;
-    p->tasks = sparse_tasks(nbt, rows, bid);
+    {
+        // estimated microseconds per task on one workgroup: CHOL, TRSM, update
+        const double cost[3] = {100.0, 60.0, 30.0};
+        p->tasks = schedule_order(sparse_tasks(nbt, rows, bid), nbt, bid, nblocks, 256, cost);
+    }
     // tile offsets, masks, maps
     std::vector<int64_t> boff((size_t)nbt * nbt, -1);
     for (size_t q = 0; q < bid.size(); ++q)
@@ -462,6 +557,13 @@ int flame_ichol_analyze(int64_t n, const int64_t *rp, const int32_t *ci, int32_t
             if (i > j) continue;
             const int bi = blk[i], bj = blk[j];
             amap[e] = boff[(size_t)bi * nbt + bj] + (i - p->bounds[bi]) + (j - p->bounds[bj]) * kT;
+        }
+    // row occupancy per tile: the OR of its columns' mask words
+    p->h_rowocc.assign((size_t)nblocks * 2, 0);
+    for (int64_t t = 0; t < nblocks; ++t)
+        for (int c = 0; c < kT; ++c) {
+            p->h_rowocc[2 * t] |= masks[(size_t)t * 2 * kT + 2 * c];
+            p->h_rowocc[2 * t + 1] |= masks[(size_t)t * 2 * kT + 2 * c + 1];
         }
     p->h_masks.swap(masks);
     p->h_boff.swap(boff);
@@ -529,7 +631,7 @@ int flame_ichol_factor(flame_ichol_plan plan, const double *vals, int32_t *info,
     const int rc = ensure_device(plan);
     if (rc) return rc;
     return launch_ichol_dag(plan->pool, plan->nblocks * (int64_t)kT * kT, vals, plan->nnz_a, plan->amap, plan->boff,
-                            plan->bstart, plan->masks, plan->nbt, plan->dtasks, (int64_t)plan->tasks.size(),
+                            plan->bstart, plan->masks, plan->rowocc, plan->nbt, plan->dtasks, (int64_t)plan->tasks.size(),
                             plan->ints, info, static_cast<hipStream_t>(stream));
 }
 

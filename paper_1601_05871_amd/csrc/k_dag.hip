@@ -71,6 +71,7 @@ struct DagP {
     const int64_t *boff;
     const int32_t *bstart;
     const uint64_t *masks;
+    const uint64_t *rowocc;  // per tile: 2 words, bit r set when row r has an entry of the pattern
     // breakdowns of the block-sparse form: max of INT32_MAX - column (so the
     // lowest column wins and 0 means none); independent blocks may break down
     // in any order, so a breakdown does not stop the launch
@@ -174,8 +175,9 @@ struct DagShared {
         char stage[kStages][2][kT * 128];        // update: [chunk mod kStages][X or Y][column x 128 bytes]
         double tile[kT * kT];                    // masked TRSM: the diagonal block's factor
     } u;
-    double row[kT];                              // masked CHOL / TRSM: the row just finalized
-    double piv;
+    double row[2][kT];                           // masked CHOL / TRSM: the row of the step (double-buffered)
+    double piv[2];                               // masked CHOL: the pivot of the step
+    double diag[kT];                             // masked TRSM: the diagonal of the block's factor
     int s_task, s_ok, s_bad;
 };
 
@@ -321,51 +323,66 @@ __device__ __forceinline__ void task_trsm(const double *U, double *X, int64_t ld
 // Register indices are compile-time: row j of a thread's 64 is selected by
 // comparison, not by indexing.
 
-// Selects / replaces element `idx` (wave-uniform) of a thread's 64 values.
-__device__ __forceinline__ double pick64(const double (&v)[64], int idx) {
-    double r = 0.0;
-#pragma unroll
-    for (int i = 0; i < 64; ++i) r = (i == idx) ? v[i] : r;
-    return r;
+// Element 16 q + t of a thread's 64 values (t compile-time, q wave-uniform),
+// read and written with constant indices only (the four candidates pass an
+// empty asm first, so the choice is a select of register values, never a load
+// through a chosen address, which would put the array in scratch memory).
+__device__ __forceinline__ double pick16(const double (&v)[64], int q, int t) {
+    double v0 = v[t], v1 = v[16 + t], v2 = v[32 + t], v3 = v[48 + t];
+    asm volatile("" : "+v"(v0), "+v"(v1), "+v"(v2), "+v"(v3));
+    return q == 0 ? v0 : q == 1 ? v1 : q == 2 ? v2 : v3;
 }
-__device__ __forceinline__ void put64(double (&v)[64], int idx, double x) {
-#pragma unroll
-    for (int i = 0; i < 64; ++i) v[i] = (i == idx) ? x : v[i];
+__device__ __forceinline__ void put16(double (&v)[64], int q, int t, double x) {
+    v[t] = q == 0 ? x : v[t];
+    v[16 + t] = q == 1 ? x : v[16 + t];
+    v[32 + t] = q == 2 ? x : v[32 + t];
+    v[48 + t] = q == 3 ? x : v[48 + t];
 }
 
 // Incomplete CHOL of the b x b diagonal tile (leading dimension 128, the
-// whole 128 x 128 tile readable); returns 0 or the 1-based position of the
-// first pivot that is not > 0 (uniform).  Writes the upper triangle.
+// whole 128 x 128 tile readable, zero below the diagonal and outside b);
+// returns 0 or the 1-based position of the first pivot that is not > 0
+// (uniform).  Writes the upper triangle.  Step j: the owners of row j
+// publish the pivot and the row unscaled (v_c for c > j in the pattern, 0
+// elsewhere); after one barrier every thread forms w = v_c / d for its column
+// and subtracts v_r w from its rows r (the zeros leave finished rows alone),
+// and the owners store u_jc = v_c / sqrt(d).  Row and pivot are
+// double-buffered, so one barrier per step suffices.
 __device__ __forceinline__ int task_chol_masked(double *A, int b, const uint64_t *mask, DagShared &sh) {
-    const int tid = threadIdx.x, c = tid & (kT - 1), h = tid >> 7;
+    const int tid = threadIdx.x, c = tid & (kT - 1);
+    const int h = __builtin_amdgcn_readfirstlane(tid >> 7);
     const uint64_t m = mask[2 * c + h];  // bit i: row 64 h + i of column c in the pattern
     double a[64];
 #pragma unroll
     for (int i = 0; i < 64; ++i) a[i] = A[64 * h + i + (int64_t)c * kT];
     int bad = 0;
-    for (int j = 0; j < b; ++j) {
-        const int hj = j >> 6, ij = j & 63;
-        const double v = pick64(a, ij);
-        if (h == hj && c == j) sh.piv = v;
-        __syncthreads();
-        const double d = sh.piv;
-        if (__builtin_amdgcn_readfirstlane(d > 0.0 ? 1 : 0) == 0) {  // uniform: every thread read the same pivot
-            bad = j + 1;
-            break;
-        }
-        const double p = sqrt(d);
-        if (h == hj && c >= j && c < b) {
-            const double u = (c == j) ? p : (((m >> ij) & 1) ? v / p : 0.0);
-            put64(a, ij, u);
-            sh.row[c] = u;
-        }
-        __syncthreads();
-        if (c > j && c < b) {
-            const double ujc = sh.row[c];
+    for (int jq = 0; jq < kT / 16 && 16 * jq < b && bad == 0; ++jq) {
+        const int jb = jq >> 2, q = jq & 3;
 #pragma unroll
-            for (int i = 0; i < 64; ++i) {
-                const int r = 64 * h + i;
-                if (r > j && r <= c) a[i] -= sh.row[r] * ujc;
+        for (int t = 0; t < 16; ++t) {
+            const int j = 16 * jq + t;
+            if (j < b && bad == 0) {
+                const int buf = t & 1;
+                if (h == jb) {
+                    const double v = pick16(a, q, t);
+                    if (c == j) sh.piv[buf] = v;
+                    sh.row[buf][c] = (c > j && ((m >> (16 * q + t)) & 1)) ? v : 0.0;
+                }
+                __syncthreads();
+                const double d = sh.piv[buf];
+                if (__builtin_amdgcn_readfirstlane(d > 0.0 ? 1 : 0) == 0) {
+                    bad = j + 1;
+                } else {
+                    const double p = sqrt(d);
+                    const double vc = sh.row[buf][c];
+                    const double w = vc / d;
+                    if (h == jb) {
+                        const double u = (c == j) ? p : vc / p;
+                        put16(a, q, t, u);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 64; ++i) a[i] = __builtin_fma(-sh.row[buf][64 * h + i], w, a[i]);
+                }
             }
         }
     }
@@ -378,14 +395,24 @@ __device__ __forceinline__ int task_chol_masked(double *A, int b, const uint64_t
 }
 
 // Incomplete TRSM X := triu(U)^{-T} X for the bk x m tile X of the block row
-// whose diagonal factor is U (both tiles of leading dimension 128, readable
-// whole): forward substitution row by row, each row dropped outside the
-// pattern as soon as it is computed.
+// whose diagonal factor is U (tiles of leading dimension 128, readable whole,
+// U zero below its diagonal and outside bk): forward substitution row by
+// row, each row dropped outside the pattern as soon as it is computed.  U is
+// copied to LDS with its diagonal moved aside, so the update of every row by
+// the row just computed is unconditional (U's zeros leave the rows above it
+// alone).
 __device__ __forceinline__ void task_trsm_masked(const double *U, double *X, int bk, int m, const uint64_t *mask,
-                                                 DagShared &sh) {
-    const int tid = threadIdx.x, c = tid & (kT - 1), h = tid >> 7;
+                                                 const uint64_t *occ, DagShared &sh) {
+    (void)m;  // columns >= m are outside the pattern (mask bits 0)
+    // rows of X without an entry of the pattern stay zero and update nothing:
+    // their steps are skipped (the decision is uniform)
+    const uint64_t occ0 = __builtin_amdgcn_readfirstlane((unsigned)(occ[0] & 0xffffffffu)) |
+                          ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(occ[0] >> 32)) << 32);
+    const uint64_t occ1 = __builtin_amdgcn_readfirstlane((unsigned)(occ[1] & 0xffffffffu)) |
+                          ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(occ[1] >> 32)) << 32);
+    const int tid = threadIdx.x, c = tid & (kT - 1);
+    const int h = __builtin_amdgcn_readfirstlane(tid >> 7);
     typedef double d2_t __attribute__((ext_vector_type(2)));
-    // the diagonal factor into LDS (column-major, as the tile)
     const d2_t *U2 = reinterpret_cast<const d2_t *>(U);
     d2_t *T2 = reinterpret_cast<d2_t *>(sh.u.tile);
 #pragma unroll 4
@@ -395,30 +422,38 @@ __device__ __forceinline__ void task_trsm_masked(const double *U, double *X, int
 #pragma unroll
     for (int i = 0; i < 64; ++i) x[i] = X[64 * h + i + (int64_t)c * kT];
     __syncthreads();
-    const double *Ut = sh.u.tile;
-    for (int r = 0; r < bk; ++r) {
-        const int hr = r >> 6, ir = r & 63;
-        if (h == hr && c < m) {
-            const double v = pick64(x, ir);
-            const double u = ((mk >> ir) & 1) ? v / Ut[r + r * kT] : 0.0;
-            put64(x, ir, u);
-            sh.row[c] = u;
-        }
-        __syncthreads();
-        if (c < m) {
-            const double xr = sh.row[c];
+    double *Ut = sh.u.tile;
+    if (tid < kT) {
+        sh.diag[tid] = Ut[tid + tid * kT];
+        Ut[tid + tid * kT] = 0.0;
+    }
+    __syncthreads();
+    for (int rq = 0; rq < kT / 16 && 16 * rq < bk; ++rq) {
+        const int rb = rq >> 2, q = rq & 3;
 #pragma unroll
-            for (int i = 0; i < 64; ++i) {
-                const int rr = 64 * h + i;
-                if (rr > r && rr < bk) x[i] -= Ut[r + rr * kT] * xr;
+        for (int t = 0; t < 16; ++t) {
+            const int r = 16 * rq + t;
+            if (r < bk && (((rb ? occ1 : occ0) >> (16 * q + t)) & 1)) {
+                const int buf = t & 1;
+                if (h == rb) {
+                    const double v = pick16(x, q, t);
+                    const double u = ((mk >> (16 * q + t)) & 1) ? v / sh.diag[r] : 0.0;
+                    put16(x, q, t, u);
+                    sh.row[buf][c] = u;
+                }
+                __syncthreads();
+                const double xr = sh.row[buf][c];
+#pragma unroll
+                for (int i = 0; i < 64; ++i) x[i] = __builtin_fma(-Ut[r + (64 * h + i) * kT], xr, x[i]);
             }
         }
-        __syncthreads();
     }
+    // stored through the mask: a skipped (empty) row still holds what the rows
+    // above it subtracted from it, and must leave as zeros
 #pragma unroll
     for (int i = 0; i < 64; ++i) {
         const int rr = 64 * h + i;
-        if (rr < bk && c < m) X[rr + (int64_t)c * kT] = x[i];
+        if (rr < bk) X[rr + (int64_t)c * kT] = ((mk >> i) & 1) ? x[i] : 0.0;
     }
 }
 
@@ -482,7 +517,8 @@ __global__ __launch_bounds__(256, 1) void k_by_blocks(DagP p) {
             const int bad = task_chol_masked(blk(k, k), width(k), mask(k, k), sh);
             if (bad != 0 && tid == 0) atomicMax(p.bad_enc, (int32_t)(0x7fffffff - (p.bstart[k] + bad)));
         } else if (SPARSE && type == 1) {
-            task_trsm_masked(blk(k, k), blk(k, j), width(k), width(j), mask(k, j), sh);
+            task_trsm_masked(blk(k, k), blk(k, j), width(k), width(j), mask(k, j),
+                             p.rowocc + (p.boff[(int64_t)k * nbt + j] / (kT * kT)) * 2, sh);
         } else if (type == 0)
             task_chol(blk(k, k), lda, width(k), lds, &s_bad, k, p.info, p.abort_flag);
         else if (type == 1)
@@ -590,6 +626,7 @@ int launch_by_blocks(int64_t n, double *A, int64_t lda, const int4 *tasks, int64
     p.boff = nullptr;
     p.bstart = nullptr;
     p.masks = nullptr;
+    p.rowocc = nullptr;
     p.bad_enc = nullptr;
     const int tr = trace_begin(FLAME_KC_OTHER, s);
     hipLaunchKernelGGL(k_by_blocks<false>, dim3((unsigned)std::min<int64_t>(grid, ntasks)), dim3(256), 0, s, p);
@@ -639,8 +676,8 @@ unsigned grid_for(int64_t count) { return (unsigned)std::max<int64_t>(1, std::mi
 // (-1: a wait gave up; else the lowest breakdown column).  ints: claim,
 // abort, fin[nbt^2], upd[nbt^2], breakdown (cleared here).
 int launch_ichol_dag(double *pool, int64_t pool_elems, const double *vals, int64_t nnz_a, const int64_t *amap,
-                     const int64_t *boff, const int32_t *bstart, const uint64_t *masks, int nbt, const int4 *tasks,
-                     int64_t ntasks, int32_t *ints, int32_t *info, hipStream_t s) {
+                     const int64_t *boff, const int32_t *bstart, const uint64_t *masks, const uint64_t *rowocc, int nbt,
+                     const int4 *tasks, int64_t ntasks, int32_t *ints, int32_t *info, hipStream_t s) {
     const int64_t nints = 3 + 2 * (int64_t)nbt * nbt;
     int rc = launch_zero_i32(ints, nints, s);
     if (rc) return rc;
@@ -676,6 +713,7 @@ int launch_ichol_dag(double *pool, int64_t pool_elems, const double *vals, int64
     p.boff = boff;
     p.bstart = bstart;
     p.masks = masks;
+    p.rowocc = rowocc;
     p.bad_enc = ints + 2 + 2 * (int64_t)nbt * nbt;
     const int tr = trace_begin(FLAME_KC_OTHER, s);
     hipLaunchKernelGGL(k_by_blocks<true>, dim3((unsigned)std::min<int64_t>(grid, ntasks)), dim3(256), 0, s, p);

@@ -109,3 +109,14 @@ def test_ichol_library_ordering_property(dims, stencil, k):
     R = D.T @ D - (A + np.triu(A, 1).T)
     mask = oi.to_dense(st["urp"], st["uci"], np.ones(len(st["uci"]))) > 0
     assert np.max(np.abs(R[mask])) <= 1e-13 * np.max(np.abs(A))
+
+
+def test_ichol_bench_size_vs_oracle():
+    """The bench's 2-D workload (512 x 512, level 1) on the oracle's ordering:
+    every entry of U against the oracle's."""
+    print("[ichol] 2-D 512 x 512, k = 1", flush=True)
+    rp, ci, v, n, order, P, info, U = _plan_and_factor((512, 512), 5, 1, leaf=256)
+    prp, pci, Uo, io, _ = _oracle(rp, ci, v, n, order, 1)
+    assert info == io == 0
+    assert np.array_equal(P.structure()["uci"], pci)
+    assert np.max(np.abs(U - Uo)) <= 1e-13 * np.max(np.abs(Uo))

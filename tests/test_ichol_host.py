@@ -60,9 +60,19 @@ def test_block_pattern_and_task_list(dims, stencil):
     assert np.array_equal(st["pattern"], expect)
     assert P.stats["nblocks"] == int(np.triu(expect).sum())
     tasks = [tuple(int(x) for x in t) for t in st["tasks"]]
-    assert tasks == fl.by_blocks_tasks(nbt, expect)
+    # the tasks of the block pattern (the by-blocks generators), each once, in a
+    # claim order (a simulated list schedule) where every task follows the
+    # tasks it waits for
+    ref = fl.by_blocks_tasks(nbt, expect)
+    assert len(tasks) == len(set(tasks)) == len(ref) and set(tasks) == set(ref)
     assert P.stats["ntasks"] == len(tasks)
     _check_order(tasks, lambda i, j: i == j or bool(expect[i][j]))
+    # the updates of each block keep their iteration order
+    seen = {}
+    for ty, k, i, j in tasks:
+        if ty == 2:
+            assert seen.get((i, j), -1) < k
+            seen[(i, j)] = k
 
 
 def test_flop_count():
