@@ -499,6 +499,36 @@ int flame_ichol_factor(flame_ichol_plan plan, const double *vals, int32_t *info,
  * flame_ichol_structure's urp / uci), from the last flame_ichol_factor. */
 int flame_ichol_values(flame_ichol_plan plan, double *uvals, void *stream);
 
+/* z := M^{-1} r with M = P^T U^T U P, the incomplete factor of the last
+ * flame_ichol_factor (P the plan's ordering): device vectors of n doubles in
+ * the original numbering (r and z may not overlap).  One forward and one
+ * backward block-triangular solve, each a single launch over the blocks. */
+int flame_ichol_apply(flame_ichol_plan plan, const double *r, double *z, void *stream);
+
+/* Preconditioned conjugate gradients for A x = b with M (the paper's use of
+ * the incomplete factor, Sec. "Introduction": a preconditioner for SPD
+ * systems).  vals: A's values (device, the order of the analysed ci); the
+ * analysed pattern must hold both triangles (else FLAME_ERR_UNSUPPORTED:
+ * the product uses every stored entry).  b, x: device n-vectors, x the
+ * starting guess on entry, the solution on exit.  Stops when
+ * ||b - A x||_2 <= tol ||b||_2 (recursive residual) or after max_iter
+ * iterations (report->status = FLAME_ERR_NOT_CONVERGED, the return value
+ * stays 0).  Call flame_ichol_factor on the same values first.
+ * Synchronizes `stream` once per iteration. */
+typedef struct {
+    double tol;          /* > 0; default 1e-10 when opts is NULL */
+    int32_t max_iter;    /* >= 0; default 1000 */
+    int32_t reserved[2]; /* must be 0 */
+} flame_pcg_opts_t;
+typedef struct {
+    int32_t iters;  /* iterations taken */
+    int32_t status; /* FLAME_OK or FLAME_ERR_NOT_CONVERGED */
+    double relres;  /* ||r||_2 / ||b||_2 at exit */
+    double bnorm;   /* ||b||_2 */
+} flame_pcg_report_t;
+int flame_ichol_pcg(flame_ichol_plan plan, const double *vals, const double *b, double *x, const flame_pcg_opts_t *opts,
+                    flame_pcg_report_t *report, void *stream);
+
 /* Frees a plan (synchronizes nothing: no call on it may be in flight). */
 int flame_ichol_destroy(flame_ichol_plan plan);
 

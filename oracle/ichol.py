@@ -145,3 +145,58 @@ def to_dense(rp: np.ndarray, ci: np.ndarray, val: np.ndarray) -> np.ndarray:
     rows = np.repeat(np.arange(n), np.diff(rp))
     D[rows, ci] = val
     return D
+
+
+def triangular_apply(rp: np.ndarray, ci: np.ndarray, U: np.ndarray, order: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """z = P^T (U^T U)^{-1} P r for the incomplete factor U (rows of the
+    ordered matrix) and the ordering order[new] = old: forward substitution
+    with U^T, back substitution with U (scipy's sparse triangular solves)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+
+    n = len(rp) - 1
+    Um = sp.csr_matrix((U, ci, rp), shape=(n, n))
+    t = np.asarray(r, dtype=np.float64)[order]
+    y = sla.spsolve_triangular(Um.T.tocsr(), t, lower=True)
+    zt = sla.spsolve_triangular(Um, y, lower=False)
+    z = np.empty(n)
+    z[order] = zt
+    return z
+
+
+def pcg(rp: np.ndarray, ci: np.ndarray, val: np.ndarray, b: np.ndarray, precond=None, tol: float = 1e-10,
+        max_iter: int = 1000, x0=None):
+    """Preconditioned conjugate gradients for A x = b, A given by its full
+    symmetric rows (rp, ci, val); ``precond(r)`` returns M^{-1} r (None: M =
+    I).  The textbook recurrences: r = b - A x, z = M^{-1} r, p = z; then
+    q = A p, alpha = (r, z) / (p, q), x += alpha p, r -= alpha q, stop when
+    ||r|| <= tol ||b||, z = M^{-1} r, beta = (r, z)_new / (r, z)_old,
+    p = z + beta p.  Returns (x, iterations, ||r|| / ||b||)."""
+    import scipy.sparse as sp
+
+    n = len(rp) - 1
+    A = sp.csr_matrix((val, ci, rp), shape=(n, n))
+    M = precond if precond is not None else (lambda v: v.copy())
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    r = b - A @ x
+    nb = float(np.linalg.norm(b))
+    if nb == 0.0 or np.linalg.norm(r) <= tol * nb:
+        return x, 0, (float(np.linalg.norm(r)) / nb if nb else 0.0)
+    z = M(r)
+    p = z.copy()
+    rz = float(r @ z)
+    it = 0
+    while it < max_iter:
+        q = A @ p
+        alpha = rz / float(p @ q)
+        x += alpha * p
+        r -= alpha * q
+        it += 1
+        rel = float(np.linalg.norm(r)) / nb
+        if rel <= tol:
+            return x, it, rel
+        z = M(r)
+        rz_new = float(r @ z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, it, float(np.linalg.norm(r)) / nb

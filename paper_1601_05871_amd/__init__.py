@@ -41,7 +41,7 @@ EXPORTS = (
     "flame_solve_mixed", "flame_shutdown", "flame_batched_factor_noalloc", "flame_trace_busy", "flame_probe",
     "flame_select_class", "flame_factor_by_blocks", "flame_by_blocks_tasks",
     "flame_ichol_analyze", "flame_ichol_stats", "flame_ichol_structure", "flame_ichol_factor", "flame_ichol_values",
-    "flame_ichol_destroy",
+    "flame_ichol_destroy", "flame_ichol_apply", "flame_ichol_pcg",
 )
 PROBE = {"mfma_f64": 0, "mfma_f32": 1, "mfma_bf16": 2, "copy": 3}
 NOALLOC_MAX_BATCH = 262144
@@ -74,6 +74,15 @@ class IcholStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz_a", ctypes.c_int64), ("nnz_u", ctypes.c_int64), ("nbt", ctypes.c_int64),
                 ("nblocks", ctypes.c_int64), ("ntasks", ctypes.c_int64), ("pool_bytes", ctypes.c_int64),
                 ("flops", ctypes.c_double)]
+
+
+class PcgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
+class PcgReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("relres", ctypes.c_double),
+                ("bnorm", ctypes.c_double)]
 
 
 class Choice(ctypes.Structure):
@@ -137,6 +146,8 @@ def lib(path: str | None = None) -> ctypes.CDLL:
     L.flame_ichol_factor.argtypes = [vp, vp, vp, vp]
     L.flame_ichol_values.argtypes = [vp, vp, vp]
     L.flame_ichol_destroy.argtypes = [vp]
+    L.flame_ichol_apply.argtypes = [vp, vp, vp, vp]
+    L.flame_ichol_pcg.argtypes = [vp, vp, vp, vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), vp]
     L.flame_batched_factor_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, vp]
     L.flame_status_string.argtypes = [ctypes.c_int]
     L.flame_status_string.restype = ctypes.c_char_p
@@ -613,6 +624,36 @@ class IcholPlan:
         out = torch.empty(self.stats["nnz_u"], dtype=torch.float64, device="cuda")
         _check("flame_ichol_values", lib().flame_ichol_values(self._h, out.data_ptr(), _stream_ptr()))
         return out
+
+    def apply(self, r):
+        """z = M^{-1} r with M = P^T U^T U P (device float64 n-vectors)."""
+        torch = _torch()
+        if r.dtype != torch.float64 or not r.is_cuda or r.numel() != self.n:
+            raise ValueError("r must be a float64 device vector of n entries")
+        r = r.contiguous()
+        z = torch.empty_like(r)
+        _check("flame_ichol_apply", lib().flame_ichol_apply(self._h, r.data_ptr(), z.data_ptr(), _stream_ptr()))
+        return z
+
+    def pcg(self, vals, b, x=None, tol: float = 1e-10, max_iter: int = 1000):
+        """Preconditioned CG for A x = b (factor first); returns (x, report)
+        with report = iters, status, relres, bnorm.  Synchronizes."""
+        torch = _torch()
+        for name, t in (("vals", vals), ("b", b)):
+            if t.dtype != torch.float64 or not t.is_cuda:
+                raise ValueError(f"{name} must be a float64 device tensor")
+        if vals.numel() != self.stats["nnz_a"] or b.numel() != self.n:
+            raise ValueError("vals must hold one value per entry of A and b n entries")
+        vals, b = vals.contiguous(), b.contiguous()
+        x = torch.zeros_like(b) if x is None else x
+        if x.dtype != torch.float64 or not x.is_cuda or x.numel() != self.n or not x.is_contiguous():
+            raise ValueError("x must be a contiguous float64 device vector of n entries")
+        o = PcgOpts()
+        o.tol, o.max_iter = float(tol), int(max_iter)
+        rep = PcgReport()
+        _check("flame_ichol_pcg", lib().flame_ichol_pcg(self._h, vals.data_ptr(), b.data_ptr(), x.data_ptr(),
+                                                        ctypes.byref(o), ctypes.byref(rep), _stream_ptr()))
+        return x, {"iters": rep.iters, "status": rep.status, "relres": rep.relres, "bnorm": rep.bnorm}
 
     def close(self) -> None:
         if self._h:

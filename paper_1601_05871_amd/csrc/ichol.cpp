@@ -23,6 +23,7 @@
 // pool of 128 x 128 tiles; A's upper entries are scattered into it, and the
 // task DAG of the block pattern runs with element masks (dropped fill).
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <queue>
@@ -35,6 +36,11 @@ int launch_ichol_dag(double *pool, int64_t pool_elems, const double *vals, int64
                      const int64_t *boff, const int32_t *bstart, const uint64_t *masks, const uint64_t *rowocc, int nbt,
                      const int4 *tasks, int64_t ntasks, int32_t *ints, int32_t *info, hipStream_t s);
 int launch_gather_vals(int64_t nnz, const int64_t *map, const double *pool, double *out, hipStream_t s);
+int launch_bsolve(bool forward, const double *pool, const int64_t *boff, const int32_t *bstart, int nbt,
+                  const int32_t *lptr, const int32_t *lblk, double *y, int32_t *flags, int32_t *err, hipStream_t s);
+int launch_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x, const double *b,
+                double *y, hipStream_t s);
+int launch_permute(int64_t n, const int64_t *order, const double *src, double *dst, bool gather, hipStream_t s);
 }  // namespace flame
 
 using namespace flame;
@@ -331,6 +337,12 @@ struct flame_ichol_plan_s {
     std::vector<int4> tasks;
     // host copies of what goes to the device
     std::vector<uint64_t> h_masks, h_rowocc;
+    // the input pattern (for the sparse product of PCG) and the block lists of
+    // the triangular solves
+    std::vector<int64_t> h_rp;
+    std::vector<int32_t> h_ci;
+    bool full_sym = false;  // both triangles stored (needed by the product)
+    std::vector<int32_t> h_fptr, h_fblk, h_bptr, h_bblk;
     std::vector<int64_t> h_boff, h_amap, h_umap;
     std::vector<int32_t> h_bstart;
     double *pool = nullptr;
@@ -342,6 +354,11 @@ struct flame_ichol_plan_s {
     int32_t *ints = nullptr;
     int64_t *amap = nullptr;
     int64_t *umap = nullptr;
+    // solves and PCG (allocated with the rest)
+    int64_t *d_order = nullptr, *d_rp = nullptr;
+    int32_t *d_ci = nullptr, *d_fptr = nullptr, *d_fblk = nullptr, *d_bptr = nullptr, *d_bblk = nullptr;
+    int32_t *d_flags = nullptr, *d_err = nullptr;
+    double *d_vec = nullptr;  // r, z, p, q, t (n each) and scalars rho, rho_old, pq, rr
 };
 
 namespace {
@@ -354,8 +371,10 @@ void free_plan(flame_ichol_plan_s *p) {
     }
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess && cur != p->dev) (void)hipSetDevice(p->dev);
-    for (void *q : {(void *)p->pool, (void *)p->masks, (void *)p->rowocc, (void *)p->boff, (void *)p->bstart, (void *)p->dtasks,
-                    (void *)p->ints, (void *)p->amap, (void *)p->umap})
+    for (void *q : {(void *)p->pool, (void *)p->masks, (void *)p->rowocc, (void *)p->boff, (void *)p->bstart,
+                    (void *)p->dtasks, (void *)p->ints, (void *)p->amap, (void *)p->umap, (void *)p->d_order,
+                    (void *)p->d_rp, (void *)p->d_ci, (void *)p->d_fptr, (void *)p->d_fblk, (void *)p->d_bptr,
+                    (void *)p->d_bblk, (void *)p->d_flags, (void *)p->d_err, (void *)p->d_vec})
         if (q != nullptr) (void)hipFree(q);
     if (cur != p->dev) (void)hipSetDevice(cur);
     delete p;
@@ -389,9 +408,23 @@ int ensure_device(flame_ichol_plan_s *p) {
     if (!rc) rc = upload(&p->umap, p->h_umap);
     if (!rc && hipMalloc((void **)&p->ints, (3 + 2 * (size_t)p->nbt * p->nbt) * sizeof(int32_t)) != hipSuccess)
         rc = FLAME_ERR_NOMEM;
+    if (!rc) rc = upload(&p->d_order, p->order);
+    if (!rc) rc = upload(&p->d_rp, p->h_rp);
+    if (!rc) rc = upload(&p->d_ci, p->h_ci);
+    if (!rc) rc = upload(&p->d_fptr, p->h_fptr);
+    if (!rc) rc = upload(&p->d_fblk, p->h_fblk);
+    if (!rc) rc = upload(&p->d_bptr, p->h_bptr);
+    if (!rc) rc = upload(&p->d_bblk, p->h_bblk);
+    if (!rc && hipMalloc((void **)&p->d_flags, std::max(1, p->nbt) * sizeof(int32_t)) != hipSuccess) rc = FLAME_ERR_NOMEM;
+    if (!rc && hipMalloc((void **)&p->d_err, sizeof(int32_t)) != hipSuccess) rc = FLAME_ERR_NOMEM;
+    if (!rc && hipMalloc((void **)&p->d_vec, (5 * (size_t)std::max<int64_t>(1, p->n) + 8) * sizeof(double)) != hipSuccess)
+        rc = FLAME_ERR_NOMEM;
     if (rc) {  // back to unbound: a later call tries again
-        for (void **q : {(void **)&p->pool, (void **)&p->masks, (void **)&p->rowocc, (void **)&p->boff, (void **)&p->bstart,
-                         (void **)&p->dtasks, (void **)&p->ints, (void **)&p->amap, (void **)&p->umap})
+        for (void **q : {(void **)&p->pool, (void **)&p->masks, (void **)&p->rowocc, (void **)&p->boff,
+                         (void **)&p->bstart, (void **)&p->dtasks, (void **)&p->ints, (void **)&p->amap,
+                         (void **)&p->umap, (void **)&p->d_order, (void **)&p->d_rp, (void **)&p->d_ci,
+                         (void **)&p->d_fptr, (void **)&p->d_fblk, (void **)&p->d_bptr, (void **)&p->d_bblk,
+                         (void **)&p->d_flags, (void **)&p->d_err, (void **)&p->d_vec})
             if (*q != nullptr) {
                 (void)hipFree(*q);
                 *q = nullptr;
@@ -447,6 +480,14 @@ int flame_ichol_analyze(int64_t n, const int64_t *rp, const int32_t *ci, int32_t
     p->n = n;
     p->nnz_a = rp[n];
     p->level = level;
+    p->h_rp.assign(rp, rp + n + 1);
+    p->h_ci.assign(ci, ci + rp[n]);
+    {
+        int64_t offdiag = 0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e) offdiag += (ci[e] != i);
+        p->full_sym = (offdiag == (int64_t)g.adj.size());  // every edge stored in both directions
+    }
     // 1. ordering and ranges
     std::vector<int64_t> ends;
     if (order != nullptr) {
@@ -530,6 +571,21 @@ int flame_ichol_analyze(int64_t n, const int64_t *rp, const int32_t *ci, int32_t
                 if (bj > bi) rows[bi].push_back(bj);
             }
     p->nblocks = nblocks;
+    // block lists of the solves: forward, for block column i the q < i with
+    // (q, i); backward, for block row i the j > i with (i, j)
+    {
+        std::vector<std::vector<int32_t>> cols(nbt);
+        for (int bi = 0; bi < nbt; ++bi)
+            for (int bj : rows[bi]) cols[bj].push_back(bi);
+        p->h_fptr.assign(1, 0);
+        p->h_bptr.assign(1, 0);
+        for (int b = 0; b < nbt; ++b) {
+            p->h_fblk.insert(p->h_fblk.end(), cols[b].begin(), cols[b].end());
+            p->h_fptr.push_back((int32_t)p->h_fblk.size());
+            p->h_bblk.insert(p->h_bblk.end(), rows[b].begin(), rows[b].end());
+            p->h_bptr.push_back((int32_t)p->h_bblk.size());
+        }
+    }
     {
         // estimated microseconds per task on one workgroup: CHOL, TRSM, update
         const double cost[3] = {100.0, 60.0, 30.0};
@@ -641,6 +697,103 @@ int flame_ichol_values(flame_ichol_plan plan, double *uvals, void *stream) {
     const int rc = ensure_device(plan);
     if (rc) return rc;
     return launch_gather_vals(plan->nnz_u, plan->umap, plan->pool, uvals, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+// z := P^T (U^T U)^{-1} P r (device vectors, original numbering) through t.
+int apply_precond(flame_ichol_plan_s *p, const double *r, double *z, double *t, hipStream_t s) {
+    int rc = launch_permute(p->n, p->d_order, r, t, true, s);
+    if (!rc) rc = launch_bsolve(true, p->pool, p->boff, p->bstart, p->nbt, p->d_fptr, p->d_fblk, t, p->d_flags,
+                                p->d_err, s);
+    if (!rc) rc = launch_bsolve(false, p->pool, p->boff, p->bstart, p->nbt, p->d_bptr, p->d_bblk, t, p->d_flags,
+                                p->d_err, s);
+    if (!rc) rc = launch_permute(p->n, p->d_order, t, z, false, s);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int flame_ichol_apply(flame_ichol_plan plan, const double *r, double *z, void *stream) {
+    if (plan == nullptr) return -1;
+    if (r == nullptr && plan->n > 0) return -2;
+    if (z == nullptr && plan->n > 0) return -3;
+    int rc = ensure_device(plan);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = launch_zero_i32(plan->d_err, 1, s);
+    if (rc) return rc;
+    return apply_precond(plan, r, z, plan->d_vec + 4 * plan->n, s);
+}
+
+int flame_ichol_pcg(flame_ichol_plan plan, const double *vals, const double *b, double *x, const flame_pcg_opts_t *opts,
+                    flame_pcg_report_t *report, void *stream) {
+    if (plan == nullptr) return -1;
+    const int64_t n = plan->n;
+    if (vals == nullptr && plan->nnz_a > 0) return -2;
+    if (b == nullptr && n > 0) return -3;
+    if (x == nullptr && n > 0) return -4;
+    const double tol = opts ? opts->tol : 1e-10;
+    const int32_t max_iter = opts ? opts->max_iter : 1000;
+    if (!(tol > 0.0) || max_iter < 0) return -5;
+    if (opts && (opts->reserved[0] || opts->reserved[1])) return -5;
+    if (!plan->full_sym) return FLAME_ERR_UNSUPPORTED;
+    int rc = ensure_device(plan);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    flame_pcg_report_t rep{0, FLAME_OK, 0.0, 0.0};
+    if (n == 0) {
+        if (report) *report = rep;
+        return FLAME_OK;
+    }
+    double *r = plan->d_vec, *z = r + n, *pv = z + n, *q = pv + n, *t = q + n;
+    double *sc = t + n;  // rho, rho_old, pq, rr, bb
+    double *rho = sc, *rho_old = sc + 1, *pq = sc + 2, *rr = sc + 3, *bb = sc + 4;
+    rc = launch_zero_i32(plan->d_err, 1, s);
+    if (!rc) rc = launch_dot_cols(n, 1, b, n, b, n, bb, s);
+    if (!rc) rc = launch_spmv(n, plan->d_rp, plan->d_ci, vals, x, b, r, s);  // r = b - A x
+    if (!rc) rc = launch_dot_cols(n, 1, r, n, r, n, rr, s);
+    double host[2] = {0.0, 0.0};
+    if (!rc) FLAME_HIP(hipMemcpyAsync(host, rr, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!rc) FLAME_HIP(hipStreamSynchronize(s));
+    if (rc) return rc;
+    const double nb = std::sqrt(host[1]);
+    rep.bnorm = nb;
+    rep.relres = nb > 0.0 ? std::sqrt(host[0]) / nb : 0.0;
+    if (nb == 0.0 || rep.relres <= tol) {
+        if (report) *report = rep;
+        return FLAME_OK;
+    }
+    bool first = true;
+    int32_t it = 0;
+    while (it < max_iter) {
+        rc = apply_precond(plan, r, z, t, s);
+        if (!rc && !first) FLAME_HIP(hipMemcpyAsync(rho_old, rho, sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (!rc) rc = launch_dot_cols(n, 1, r, n, z, n, rho, s);
+        if (!rc) rc = launch_cg_direction(n, 1, z, n, pv, n, rho, rho_old, first, s);
+        if (!rc) rc = launch_spmv(n, plan->d_rp, plan->d_ci, vals, pv, nullptr, q, s);
+        if (!rc) rc = launch_dot_cols(n, 1, pv, n, q, n, pq, s);
+        if (!rc) rc = launch_cg_step(n, 1, x, n, r, n, pv, n, q, n, rho, pq, s);
+        if (!rc) rc = launch_dot_cols(n, 1, r, n, r, n, rr, s);
+        int32_t err = 0;
+        if (!rc) FLAME_HIP(hipMemcpyAsync(host, rr, sizeof(double), hipMemcpyDeviceToHost, s));
+        if (!rc) FLAME_HIP(hipMemcpyAsync(&err, plan->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (!rc) FLAME_HIP(hipStreamSynchronize(s));
+        if (rc) return rc;
+        if (err != 0) return FLAME_ERR_HIP;  // a solve gave up waiting
+        first = false;
+        ++it;
+        rep.relres = std::sqrt(host[0]) / nb;
+        if (!(rep.relres > tol)) break;  // converged (or NaN: reported below)
+    }
+    rep.iters = it;
+    rep.status = (rep.relres <= tol) ? FLAME_OK : FLAME_ERR_NOT_CONVERGED;
+    if (report) *report = rep;
+    return FLAME_OK;
 }
 
 int flame_ichol_destroy(flame_ichol_plan plan) {

@@ -120,3 +120,78 @@ def test_ichol_bench_size_vs_oracle():
     assert info == io == 0
     assert np.array_equal(P.structure()["uci"], pci)
     assert np.max(np.abs(U - Uo)) <= 1e-13 * np.max(np.abs(Uo))
+
+
+# ---- preconditioned conjugate gradients (flame_ichol_apply / flame_ichol_pcg) ----
+
+def _oracle_factor(rp, ci, v, n, order, k):
+    urp, uci, uv = oi.permute_upper(n, rp, ci, v, order)
+    prp, pci, _ = oi.fill_pattern(n, urp, uci, k)
+    U, _ = oi.ichol(prp, pci, oi.values_on(prp, pci, urp, uci, uv))
+    return prp, pci, U
+
+
+@pytest.mark.parametrize("dims,stencil,k", [((40, 38), 5, 0), ((40, 38), 5, 2), ((10, 9, 9), 7, 1), ((7, 7, 7), 27, 1)])
+def test_apply_vs_oracle(dims, stencil, k):
+    print(f"[ichol apply] {dims} {stencil} k={k}", flush=True)
+    rp, ci, v, n, order, P, info, U = _plan_and_factor(dims, stencil, k)
+    assert info == 0
+    prp, pci, Uo = _oracle_factor(rp, ci, v, n, order, k)
+    r = np.random.default_rng(11).standard_normal(n)
+    z = P.apply(torch.from_numpy(r).to(DEV)).cpu().numpy()
+    zo = oi.triangular_apply(prp, pci, Uo, order, r)
+    assert np.max(np.abs(z - zo)) <= 1e-12 * np.max(np.abs(zo))
+
+
+@pytest.mark.parametrize("dims,stencil,k", [((48, 46), 5, 0), ((48, 46), 5, 1), ((11, 10, 10), 7, 1)])
+def test_pcg_vs_oracle(dims, stencil, k):
+    """Same ordering, same factor up to rounding: the device PCG takes the
+    oracle's iteration count (within one) and reaches its solution."""
+    import scipy.sparse as sp
+
+    print(f"[ichol pcg] {dims} {stencil} k={k}", flush=True)
+    rp, ci, v, n, order, P, info, U = _plan_and_factor(dims, stencil, k)
+    assert info == 0
+    prp, pci, Uo = _oracle_factor(rp, ci, v, n, order, k)
+    b = np.random.default_rng(12).standard_normal(n)
+    xo, ito, _ = oi.pcg(rp, ci, v, b, precond=lambda r: oi.triangular_apply(prp, pci, Uo, order, r), tol=1e-10)
+    x, rep = P.pcg(torch.from_numpy(v).to(DEV), torch.from_numpy(b).to(DEV), tol=1e-10)
+    x = x.cpu().numpy()
+    assert rep["status"] == 0 and rep["relres"] <= 1e-10
+    assert abs(rep["iters"] - ito) <= 1
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    assert np.linalg.norm(b - A @ x) <= 1e-9 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+def test_pcg_library_ordering_and_warm_start():
+    import scipy.sparse as sp
+
+    dims = (16, 16, 16)
+    rp, ci, v = inputs.laplacian_grid(dims, 7)
+    n = len(rp) - 1
+    P = fl.IcholPlan(n, rp, ci, 1, leaf=64)
+    vals = torch.from_numpy(v).to(DEV)
+    assert int(P.factor(vals).item()) == 0
+    b = np.random.default_rng(13).standard_normal(n)
+    x, rep = P.pcg(vals, torch.from_numpy(b).to(DEV), tol=1e-11)
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    assert rep["status"] == 0 and np.linalg.norm(b - A @ x.cpu().numpy()) <= 1e-10 * np.linalg.norm(b)
+    # a warm start at the solution needs no iteration
+    _, rep2 = P.pcg(vals, torch.from_numpy(b).to(DEV), x=x, tol=1e-9)
+    assert rep2["iters"] == 0
+    # a budget of 2 iterations is reported, not raised
+    _, rep3 = P.pcg(vals, torch.from_numpy(b).to(DEV), tol=1e-14, max_iter=2)
+    assert rep3["iters"] == 2 and rep3["status"] == fl.FLAME_ERR_NOT_CONVERGED
+
+
+def test_pcg_needs_both_triangles():
+    rp, ci, v = inputs.laplacian_grid((10, 10))
+    n = 100
+    urp, uci, uv = oi.permute_upper(n, rp, ci, v, np.arange(n))
+    P = fl.IcholPlan(n, urp, uci, 0)
+    vals = torch.from_numpy(uv).to(DEV)
+    assert int(P.factor(vals).item()) == 0
+    with pytest.raises(fl.FlameError) as e:
+        P.pcg(vals, torch.ones(n, dtype=torch.float64, device=DEV))
+    assert e.value.status == fl.FLAME_ERR_UNSUPPORTED

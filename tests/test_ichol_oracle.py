@@ -248,3 +248,58 @@ def test_ichol_mutant_fails_a_pin(name, tmp_path):
         f.write(src.replace(old, new))
     lpath = build(mpath, os.path.join(tmp_path, f"liboracle_{name}.so"))
     assert not _ichol_pins_pass(oracle.load(lpath))
+
+
+# ---- preconditioned conjugate gradients (the factor as a preconditioner) ----
+
+def test_pcg_without_preconditioner_follows_scipy_cg():
+    """M = I: the oracle's recurrences give scipy's CG iterates (same
+    algorithm, independent code), iteration by iteration."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+
+    rp, ci, v = inputs.laplacian_grid((14, 13))
+    n = len(rp) - 1
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    b = np.random.default_rng(3).standard_normal(n)
+    for m in (1, 5, 20):
+        x, it, _ = oi.pcg(rp, ci, v, b, tol=1e-300, max_iter=m)
+        xs, _ = sla.cg(A, b, rtol=1e-300, atol=0.0, maxiter=m)
+        assert it == m
+        assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_pcg_with_complete_factor_takes_one_step():
+    rp, ci, v = inputs.laplacian_grid((12, 11))
+    n = len(rp) - 1
+    order, _ = oi.nd_grid((12, 11), leaf=16)
+    urp, uci, uv = oi.permute_upper(n, rp, ci, v, order)
+    prp, pci, _ = oi.fill_pattern(n, urp, uci, n)
+    U, _ = oi.ichol(prp, pci, oi.values_on(prp, pci, urp, uci, uv))
+    b = np.random.default_rng(4).standard_normal(n)
+    x, it, rel = oi.pcg(rp, ci, v, b, precond=lambda r: oi.triangular_apply(prp, pci, U, order, r), tol=1e-12)
+    assert it == 1 and rel <= 1e-12
+
+
+@pytest.mark.parametrize("dims,stencil", [((24, 22), 5), ((8, 8, 7), 7)])
+def test_pcg_converges_and_higher_levels_help(dims, stencil):
+    import scipy.sparse as sp
+
+    rp, ci, v = inputs.laplacian_grid(dims, stencil)
+    n = len(rp) - 1
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    b = np.random.default_rng(5).standard_normal(n)
+    order, _ = oi.nd_grid(dims, leaf=20)
+    urp, uci, uv = oi.permute_upper(n, rp, ci, v, order)
+    its = []
+    for k in (None, 0, 1, 2):
+        M = None
+        if k is not None:
+            prp, pci, _ = oi.fill_pattern(n, urp, uci, k)
+            U, _ = oi.ichol(prp, pci, oi.values_on(prp, pci, urp, uci, uv))
+            M = (lambda P, C, UU: (lambda r: oi.triangular_apply(P, C, UU, order, r)))(prp, pci, U)
+        x, it, rel = oi.pcg(rp, ci, v, b, precond=M, tol=1e-10)
+        assert rel <= 1e-10
+        assert np.linalg.norm(b - A @ x) <= 1e-9 * np.linalg.norm(b)  # the true residual
+        its.append(it)
+    assert its[0] > its[1] >= its[2] >= its[3]
