@@ -543,8 +543,10 @@ def ichol_mode(args, dev, fl, inputs, torch) -> int:
     numeric phase on the device, median of --steps after --warmup (A's values
     resident on the device, the pool cleared and refilled inside each timed
     call); beside it the oracle's sequential incomplete factor (its own grid
-    dissection and symbolic phase, untimed) on the host, one run.  One JSON
-    line per workload."""
+    dissection and symbolic phase, untimed) on the host, one run; then the
+    time to solution of A x = b by PCG with the factor (factor + iterations to
+    ||r|| <= 1e-10 ||b||), beside the oracle's PCG on the smaller workloads.
+    One JSON line per workload."""
     import time
 
     import oracle.ichol as oi
@@ -581,13 +583,30 @@ def ichol_mode(args, dev, fl, inputs, torch) -> int:
         t0 = time.perf_counter()
         _, oinfo = oi.ichol(prp, pci, ov)
         cpu_ms = (time.perf_counter() - t0) * 1e3
+        # PCG with the factor (time to solution of A x = b, b seeded, tol 1e-10)
+        b = inputs.rhs(n, 1, 0)[:, 0]
+        bd = torch.from_numpy(b).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.factor(vals, info=info)
+        _, rep = P.pcg(vals, bd, tol=1e-10)
+        pcg_ms = (time.perf_counter() - t0) * 1e3
+        pcg_cpu = None
+        if n * (k + 1) <= 300000:  # the oracle's PCG (scipy triangular solves) on the smaller workloads
+            Uo, _ = oi.ichol(prp, pci, ov)
+            t0 = time.perf_counter()
+            _, oit, orel = oi.pcg(rp, ci, v, b, precond=lambda r: oi.triangular_apply(prp, pci, Uo, order, r),
+                                  tol=1e-10)
+            pcg_cpu = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "iters": oit, "relres": orel}
         rec = {"workload": f"{len(dims)}-D {stencil}-point grid {'x'.join(map(str, dims))}", "n": n, "level": k,
                "nnz_a_upper": int((len(ci) + n) // 2), "nnz_u": st["nnz_u"], "blocks_per_side": st["nbt"],
                "blocks": st["nblocks"], "tasks": st["ntasks"], "gflop": round(st["flops"] / 1e9, 4),
                "analyze_host_ms": round(t_an * 1e3, 1), "factor_ms": round(ms, 3),
                "gflops": round(st["flops"] / (ms * 1e-3) / 1e9, 3),
                "oracle_cpu": {"ms": round(cpu_ms, 3), "nnz_u": int(len(pci)), "threads": 1, "info": oinfo},
-               "gpu_over_cpu_speedup": round(cpu_ms / ms, 2)}
+               "gpu_over_cpu_speedup": round(cpu_ms / ms, 2),
+               "pcg": {"factor_plus_solve_ms": round(pcg_ms, 2), "iters": rep["iters"], "relres": rep["relres"],
+                       "status": rep["status"], "oracle_cpu": pcg_cpu}}
         print(json.dumps(rec), flush=True)
         P.close()
         del vals
