@@ -99,8 +99,15 @@ typedef struct {
 } flame_opts_t;
 
 /* opts.flags: FLAME_OPT_FIXED_NB runs every block of the RIGHT loop at
- * min(nb, n - k), without the smaller blocks of the last columns. */
+ * min(nb, n - k), without the smaller blocks of the last columns.
+ * FLAME_OPT_LOWER: lower storage, A = L L^T (the "lower" variant the paper's
+ * conclusion lists beside the upper one): the lower triangle of A is the
+ * input and receives L; the strictly upper triangle is neither used nor
+ * changed (it is swapped with the lower one, in place, before and after the
+ * factorization of the upper triangle, which is the same factorization of
+ * the transpose).  Breakdown columns as for upper storage. */
 #define FLAME_OPT_FIXED_NB 1
+#define FLAME_OPT_LOWER 2
 
 /* ---- factorization ------------------------------------------------------ */
 

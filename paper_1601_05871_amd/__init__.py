@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libflame.so")
 
 F64, F32 = 0, 1
 OPT_FIXED_NB = 1
+OPT_LOWER = 2
 VAR_AUTO, VAR_BORDERED, VAR_LEFT, VAR_RIGHT, VAR_BY_BLOCKS = 0, 1, 2, 3, 4
 BY_BLOCKS_TILE = 128
 TRAIL = {"native": 0, "f32": 1, "bf16": 2}
@@ -234,8 +235,9 @@ def _opts(variant, nb, trail, lookahead, graph, fixed_nb=False) -> Opts:
 
 
 def factor(A, variant: int = VAR_RIGHT, nb: int = 128, trail="native", lookahead: int = 0, graph: int = 0,
-           info=None, fixed_nb: bool = False):
-    """A := Chol(A) in place (upper triangle).  Returns the device int32
+           info=None, fixed_nb: bool = False, lower: bool = False):
+    """A := Chol(A) in place (upper triangle; ``lower``: A = L L^T in the
+    lower triangle, the upper one left as it is).  Returns the device int32
     ``info`` tensor (0, or the 1-based column of the first non-positive pivot).
     Asynchronous on the current stream.  ``fixed_nb``: the right-looking loop
     runs every block at ``nb`` (no smaller blocks in the last columns)."""
@@ -249,6 +251,8 @@ def factor(A, variant: int = VAR_RIGHT, nb: int = 128, trail="native", lookahead
     elif info.dtype != torch.int32 or info.numel() < 1 or not info.is_cuda:
         raise ValueError("info must be a device int32 tensor with at least one element")
     o = _opts(variant, nb, trail, lookahead, graph, fixed_nb)
+    if lower:
+        o.flags |= OPT_LOWER
     rc = lib().flame_factor(_dtype_code(A), n, A.data_ptr(), lda, ctypes.byref(o), info.data_ptr(), _stream_ptr())
     _check("flame_factor", rc)
     return info

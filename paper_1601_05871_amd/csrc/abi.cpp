@@ -29,7 +29,7 @@ int normalize_opts(const flame_opts_t *in, int32_t dtype, int64_t n, flame_opts_
     if (o->trail < FLAME_TRAIL_NATIVE || o->trail > FLAME_TRAIL_BF16) return -5;
     if (o->lookahead < -1 || o->lookahead > 2) return -5;
     if (o->graph < 0 || o->graph > 1) return -5;
-    if ((o->flags & ~FLAME_OPT_FIXED_NB) != 0) return -5;
+    if ((o->flags & ~(FLAME_OPT_FIXED_NB | FLAME_OPT_LOWER)) != 0) return -5;
     if (o->reserved[0] != 0 || o->reserved[1] != 0) return -5;
     if (o->variant == FLAME_VAR_AUTO) choose_variant(dtype, n, 1, o);
     if (o->nb == 0) o->nb = kDefaultNb;
@@ -53,7 +53,17 @@ int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opt
     if (o.trail != FLAME_TRAIL_NATIVE && (dtype != FLAME_F64 || o.variant != FLAME_VAR_RIGHT))
         return FLAME_ERR_UNSUPPORTED;
     if (o.variant == FLAME_VAR_BY_BLOCKS && dtype != FLAME_F64) return FLAME_ERR_UNSUPPORTED;
-    return factor_dispatch(dtype, n, A, lda, o, info, as_stream(stream));
+    if ((o.flags & FLAME_OPT_LOWER) == 0) return factor_dispatch(dtype, n, A, lda, o, info, as_stream(stream));
+    // lower storage: the transpose's upper triangle, factored as usual
+    hipStream_t s = as_stream(stream);
+    o.flags &= ~FLAME_OPT_LOWER;
+    rc = dtype == FLAME_F64 ? launch_swap_triangles<double>(n, static_cast<double *>(A), lda, s)
+                            : launch_swap_triangles<float>(n, static_cast<float *>(A), lda, s);
+    if (rc) return rc;
+    rc = factor_dispatch(dtype, n, A, lda, o, info, s);
+    if (rc) return rc;
+    return dtype == FLAME_F64 ? launch_swap_triangles<double>(n, static_cast<double *>(A), lda, s)
+                              : launch_swap_triangles<float>(n, static_cast<float *>(A), lda, s);
 }
 
 int flame_op_chol(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, int64_t info_base, void *stream) {

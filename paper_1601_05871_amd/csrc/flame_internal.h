@@ -47,6 +47,9 @@ void trace_end(int id, hipStream_t s, double flops, double bytes);
 
 // info[0] := 0 (a fill kernel, so that the loop can be captured in a graph).
 int launch_zero_i32(int32_t *p, int64_t count, hipStream_t s);
+// Swaps the strict lower and upper triangles of A in place (lower storage).
+template <typename T>
+int launch_swap_triangles(int64_t n, T *A, int64_t lda, hipStream_t s);
 
 // Diagonal block A := Chol(A), n <= 256, one workgroup.  Skips all work if
 // *info != 0 on entry; on breakdown at local column j writes

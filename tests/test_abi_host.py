@@ -163,8 +163,9 @@ def test_tile_enumeration_is_a_bijection(tmp_path):
 
 
 def test_factor_unknown_flag_bits():
-    o = _opts(flags=2)
-    assert fl.lib().flame_factor(0, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == -5
+    for bits in (4, 2 | 4, 1 << 30):  # 1 = FIXED_NB and 2 = LOWER are known
+        o = _opts(flags=bits)
+        assert fl.lib().flame_factor(0, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == -5
 
 
 def test_refine_method_must_be_known():
