@@ -128,26 +128,70 @@ __device__ __forceinline__ void band_scale(T (&a)[16], bool diag_lane, int c, T 
 
 // LDS layout of the band factorization: the upper block triangle in 16 x 16
 // tiles, tile (bi, bj), bi <= bj, at (bj (bj + 1) / 2 + bi) 256 elements; a
-// tile is stored in the order of a matrix-core accumulator (element of item v
-// of lane l at 64 v + l), so that the update reads and writes a tile as 4
-// contiguous 64-element runs.  FP64 accumulators hold (row l % 16, column
+// tile is stored in the order of a matrix-core accumulator (item v of lane l
+// in the run of 64 elements at 64 v), so that the update reads and writes a
+// tile as 4 runs of 64.  FP64 accumulators hold (row l % 16, column
 // l / 16 + 4 v), FP32 ones (row 4 (l / 16) + v, column l % 16).  Entries
 // below the diagonal of a diagonal tile are never written or read as data.
+//
+// Inside each run the elements are permuted so that the three access
+// patterns of the factorization hit distinct LDS banks (64 banks of 4 bytes):
+//   (a) accumulator runs (the update's C tiles): any permutation inside a run
+//       keeps these free of conflicts;
+//   (b) operand reads of the update: lane (r, g) reads element (k, r) of one
+//       tile for its k slot of a matrix-core step (FP64: k = g + 4 t in step
+//       t; FP32: k = 4 g + t);
+//   (c) the elimination: each 16-lane group reads (and writes) one column,
+//       row by row, of its own tile, the four groups of a wavefront in four
+//       different tiles.
+// FP64 (64-bit accesses, 32 lanes at a time; 128-bit ones 16 at a time): the
+// row index is XORed with h = 2 (column bits 2-3) + 8 (column bit 1), an even
+// number, so rows 2 i and 2 i + 1 stay side by side and (c) reads a column as
+// eight 128-bit pairs; in (b) each half-wavefront then covers 32 distinct
+// banks pairs.  Unpermuted, 8 lanes shared a bank in (b) and 16 in (c).
+// FP32 (32-bit accesses, 64 lanes at a time): (a) and (b) read consecutive
+// addresses; for (c) bits 2-3 of the row index (the 16-element quarter of a
+// run) are XORed with a key of the tile's distance d = bj - bi from the
+// diagonal, 0 for d = 0, else 1 + (d - 1) mod 3, which puts the four groups
+// (distances 0, 1 + 3 w, 2 + 3 w, 3 + 3 w in wavefront w) in different
+// quarters (tabulated for d <= 15: blocks of up to 256).
 template <int NMAX>
 constexpr int band_lds_size() {
     return (NMAX / 16) * (NMAX / 16 + 1) / 2 * 256;
 }
-__device__ __forceinline__ int tile_base(int bi, int bj) { return ((bj * (bj + 1)) >> 1) * 256 + bi * 256; }
 template <typename T>
-__device__ __forceinline__ int tile_pos(int rr, int cc) {
+__device__ __forceinline__ int tile_key(int d) {
     if constexpr (sizeof(T) == 8)
-        return (cc >> 2) * 64 + (cc & 3) * 16 + rr;
+        return 0;
     else
-        return (rr & 3) * 64 + (rr >> 2) * 16 + cc;
+        return (int)((0xE79E79E4u >> (2 * d)) & 3u);
+}
+__device__ __forceinline__ int tile_base(int bi, int bj) { return ((bj * (bj + 1)) >> 1) * 256 + bi * 256; }
+// FP64: the XOR applied to row indices of column cc (even)
+__device__ __forceinline__ int row_xor64(int cc) { return ((cc >> 2) << 1) | ((cc & 2) << 2); }
+template <typename T>
+__device__ __forceinline__ int tile_pos(int rr, int cc, int key) {
+    if constexpr (sizeof(T) == 8)
+        return (cc >> 2) * 64 + (cc & 3) * 16 + (rr ^ row_xor64(cc));
+    else
+        return (rr & 3) * 64 + (((rr >> 2) ^ key) << 4) + cc;
+}
+// the row of k slot (g, t) in the update's operand reads
+template <typename T>
+__device__ __forceinline__ int k_slot(int g, int t) {
+    return sizeof(T) == 8 ? g + 4 * t : 4 * g + t;
+}
+// position of accumulator item v of lane l in a tile with this key
+template <typename T>
+__device__ __forceinline__ int acc_pos(int l, int v, int key) {
+    if constexpr (sizeof(T) == 8)
+        return tile_pos<T>(l & 15, (l >> 4) + 4 * v, key);
+    else
+        return tile_pos<T>(4 * (l >> 4) + v, l & 15, key);
 }
 template <typename T>
 __device__ __forceinline__ int band_at(int row, int col) {
-    return tile_base(row >> 4, col >> 4) + tile_pos<T>(row & 15, col & 15);
+    return tile_base(row >> 4, col >> 4) + tile_pos<T>(row & 15, col & 15, tile_key<T>((col >> 4) - (row >> 4)));
 }
 
 // Workgroup barrier for LDS traffic only: outstanding global stores stay in
@@ -182,6 +226,7 @@ __device__ __forceinline__ void band_load(int n, const T *__restrict__ A, int64_
 #pragma unroll
         for (int e = 0; e < NMAX / 4; ++e) {
             const int col = 4 * e + wave;
+            // rows (row, row + 1) stay side by side, in order (row_xor64 is even)
             if (row <= col) *reinterpret_cast<u4 *>(L + band_at<T>(row, col)) = v[e];
         }
         return;
@@ -232,15 +277,18 @@ __device__ __forceinline__ void band_update_tiles(T *L, int sb, int w) {
     T x[M][4], y[M][4];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        const T *t = L + tile_base(o16 + bi[m], o16 + bj[m]) + lane;
+        const T *t = L + tile_base(o16 + bi[m], o16 + bj[m]);
+        const int kc = tile_key<T>(bj[m] - bi[m]);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[m][v] = t[64 * v];
+        for (int v = 0; v < 4; ++v) acc[m][v] = t[acc_pos<T>(lane, v, kc)];
+        // the band's tiles (sb, o16 + b) lie at distance 1 + b from the diagonal
         const T *pi = L + tile_base(sb, o16 + bi[m]);
         const T *pj = L + tile_base(sb, o16 + bj[m]);
+        const int ki = tile_key<T>(1 + bi[m]), kj = tile_key<T>(1 + bj[m]);
 #pragma unroll
         for (int t4 = 0; t4 < 4; ++t4) {
-            x[m][t4] = pi[tile_pos<T>(4 * g + t4, r)];
-            y[m][t4] = pj[tile_pos<T>(4 * g + t4, r)];
+            x[m][t4] = pi[tile_pos<T>(k_slot<T>(g, t4), r, ki)];
+            y[m][t4] = pj[tile_pos<T>(k_slot<T>(g, t4), r, kj)];
         }
     }
 #pragma unroll
@@ -249,9 +297,10 @@ __device__ __forceinline__ void band_update_tiles(T *L, int sb, int w) {
         for (int m = 0; m < M; ++m) acc[m] = mma_rc(-x[m][t4], y[m][t4], acc[m]);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        T *t = L + tile_base(o16 + bi[m], o16 + bj[m]) + lane;
+        T *t = L + tile_base(o16 + bi[m], o16 + bj[m]);
+        const int kc = tile_key<T>(bj[m] - bi[m]);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) t[64 * v] = acc[m][v];
+        for (int v = 0; v < 4; ++v) t[acc_pos<T>(lane, v, kc)] = acc[m][v];
     }
 }
 
@@ -266,13 +315,11 @@ template <typename T, int NMAX, bool TS = false>
 __device__ int chol_lds_core2(int n, T *L, int *s_bad, T *__restrict__ A, int64_t lda,
                               unsigned long long *ts = nullptr) {
     static_assert(NMAX - 16 <= 192, "four wavefronts take 192 panel columns");
-    typedef typename TrsmAcc<T>::type acc_t;
     const int np = (n + 15) / 16 * 16;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lrow = lane >> 4;
-    const int r = lane & 15, g = lane >> 4;
     // 16-byte stores of a panel column's 16 entries when every column start
     // is 16-byte aligned
     const bool wide = ((lda & (16 / (int64_t)sizeof(T) - 1)) == 0) && (((uintptr_t)A & 15) == 0);
@@ -289,8 +336,21 @@ __device__ int chol_lds_core2(int n, T *L, int *s_bad, T *__restrict__ A, int64_
         const int col = (diag_lane || rest == 0) ? r0 + c : r0 + 16 + min(pc, rest - 1);
         T a[16];
         T *const acol = L + tile_base(r0 >> 4, col >> 4);  // this column's tile in the band
+        const int akey = tile_key<T>((col >> 4) - (r0 >> 4));
+        // i > c on the diagonal: unused
+        if constexpr (sizeof(T) == 8) {
+            const T *cp = acol + ((col & 15) >> 2) * 64 + ((col & 15) & 3) * 16;  // row 0 before the XOR
+            const int hx = row_xor64(col & 15);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) a[i] = acol[tile_pos<T>(i, col & 15)];  // i > c on the diagonal: unused
+            for (int i = 0; i < 16; i += 2) {
+                const double2 pr = *reinterpret_cast<const double2 *>(cp + (i ^ hx));
+                a[i] = pr.x;
+                a[i + 1] = pr.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) a[i] = acol[tile_pos<T>(i, col & 15, akey)];
+        }
         int bad = 0;
         T dme = T(1), rep, nt;
         band_pivot_setup<0>(a, c, bad, dme, rep, nt);
@@ -311,8 +371,15 @@ __device__ int chol_lds_core2(int n, T *L, int *s_bad, T *__restrict__ A, int64_
                     if (i <= c) out[i] = a[i];
             }
         } else if (pvalid) {
+            if constexpr (sizeof(T) == 8) {
+                T *cp = acol + ((col & 15) >> 2) * 64 + ((col & 15) & 3) * 16;
+                const int hx = row_xor64(col & 15);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) acol[tile_pos<T>(i, col & 15)] = a[i];
+                for (int i = 0; i < 16; i += 2) *reinterpret_cast<double2 *>(cp + (i ^ hx)) = double2{a[i], a[i + 1]};
+            } else {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acol[tile_pos<T>(i, col & 15, akey)] = a[i];
+            }
             if (col < n) {
                 if (wide) {
                     typedef uint32_t u4 __attribute__((ext_vector_type(4)));
