@@ -311,7 +311,11 @@ __device__ __forceinline__ void band_update_tiles(T *L, int sb, int w) {
 // then holds a partial result).  s_bad: one int.  TS (instrumentation): the cycle counter at the end of sub-block s's
 // elimination in wavefront w goes to ts[8 s + w], after its phases to
 // ts[8 s + 4 .. 8 s + 6] (thread 0).
-template <typename T, int NMAX, bool TS = false>
+// KEEP_DIAG: the diagonal 16 x 16 tiles of U also go back into their LDS
+// tiles (wavefront 0, after the band's barrier: every wavefront reads the
+// diagonal tile in its elimination), so that L ends up holding all of U in
+// band layout.
+template <typename T, int NMAX, bool TS = false, bool KEEP_DIAG = false>
 __device__ int chol_lds_core2(int n, T *L, int *s_bad, T *__restrict__ A, int64_t lda,
                               unsigned long long *ts = nullptr) {
     static_assert(NMAX - 16 <= 192, "four wavefronts take 192 panel columns");
@@ -364,13 +368,7 @@ __device__ int chol_lds_core2(int n, T *L, int *s_bad, T *__restrict__ A, int64_
         // U rows r0 .. r0 + 15 are final: straight to A; the panel also back
         // into its band tiles, where the update reads it
         T *__restrict__ out = A + (int64_t)r0 + (int64_t)col * lda;
-        if (diag_lane) {
-            if (wave == 0 && col < n) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    if (i <= c) out[i] = a[i];
-            }
-        } else if (pvalid) {
+        auto to_tile = [&]() {
             if constexpr (sizeof(T) == 8) {
                 T *cp = acol + ((col & 15) >> 2) * 64 + ((col & 15) & 3) * 16;
                 const int hx = row_xor64(col & 15);
@@ -380,6 +378,17 @@ __device__ int chol_lds_core2(int n, T *L, int *s_bad, T *__restrict__ A, int64_
 #pragma unroll
                 for (int i = 0; i < 16; ++i) acol[tile_pos<T>(i, col & 15, akey)] = a[i];
             }
+        };
+        if (diag_lane) {
+            if (wave == 0) {
+                if (col < n) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (i <= c) out[i] = a[i];
+                }
+            }
+        } else if (pvalid) {
+            to_tile();
             if (col < n) {
                 if (wide) {
                     typedef uint32_t u4 __attribute__((ext_vector_type(4)));
@@ -397,6 +406,10 @@ __device__ int chol_lds_core2(int n, T *L, int *s_bad, T *__restrict__ A, int64_
         }
         if (tid == 0) *s_bad = bad;
         lds_barrier();
+        // every wavefront has read the diagonal tile of this band: it can take U
+        if constexpr (KEEP_DIAG) {
+            if (diag_lane && wave == 0) to_tile();
+        }
         if constexpr (TS) {
             if (tid == 0) ts[r0 / 2 + 4] = __builtin_amdgcn_s_memtime();
         }

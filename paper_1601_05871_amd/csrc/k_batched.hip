@@ -10,16 +10,17 @@
 // One workgroup (4 wavefronts) factors one matrix with the right-looking loop
 // of Fig. "dense-chol" at block size kBB = 128, on the matrix in HBM / L2:
 //   CHOL  the 128 x 128 diagonal block in LDS as 16 x 16 tiles, factored
-//         band by band with matrix-core trailing updates (chol_lds.h), U11
-//         stored as each band is done;
-//   TRSM  the 128-row panel on matrix cores, 16 columns per wavefront
-//         (trsm_rl.h);
-//   SYRK  the upper 32 x 32 tiles of A22 are spread over the wavefronts; each
-//         tile is a 2 x 2 set of 16 x 16 matrix-core products (FP64 or FP32
-//         MFMA, K = 128) accumulated onto the tile of A22.
-// The diagonal block's LDS tiles and the TRSM scratch share one union (73.7 KB
-// in FP64), so two workgroups fit on a CU.  A matrix of order <= 128 is one
-// CHOL step.
+//         band by band with matrix-core trailing updates (chol_lds.h); U11
+//         stored as each band is done and left in LDS;
+//   TRSM  from LDS: the eight diagonal tiles of U11 inverted in place, then
+//         each wavefront solves 16-column strips of the panel block by block
+//         on matrix cores, reading U11's tiles from LDS;
+//   SYRK  per 64-column block of A22, the panel's 64 columns staged in LDS;
+//         each wavefront updates 16 rows x 64 columns of A22 (FP64 or FP32
+//         MFMA, K = 128) with its own 16 panel columns in registers.
+// LDS holds one union of the CHOL / TRSM tiles (73.7 KB in FP64) and the
+// staged SYRK columns, so two workgroups fit on a CU.  A matrix of order
+// <= 128 is one CHOL step.
 // A breakdown stops that matrix only (info[i] = first bad column, 1-based).
 #include "chol_lds.h"
 #include "flame_internal.h"
@@ -67,81 +68,207 @@ __device__ __forceinline__ int acc_col(int r, int g, int v) {
     return sizeof(T) == 8 ? g + 4 * v : r;
 }
 
-// C := C - P^T P on the upper triangle of the m x m matrix C, P is kBB x m.
-// Upper 32 x 32 tiles, column by column, are handed to the wavefronts in turn.
+// One matrix-core step acc += M^T A over a k slot, where the lane's memory
+// operand is element (k, r) of a 16 x 16 block M and the lane's accumulator
+// operand is item t of another accumulator of the same layout (FP64 operands
+// in swapped roles, see below).  Both precisions keep a 16-column strip of a
+// panel with lane r on column r and item v on row k_slot(g, v) of each 16-row
+// block (FP64: g + 4 v, the transposed FP64 accumulator; FP32: 4 g + v, the
+// FP32 accumulator as it is).
+__device__ __forceinline__ bd4 mma_ma(double memop, double accop, bd4 acc) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(memop, accop, acc, 0, 0, 0);
+}
+__device__ __forceinline__ bf4 mma_ma(float memop, float accop, bf4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(memop, accop, acc, 0, 0, 0);
+}
+
+// D_s := U_ss^{-1} for the eight diagonal 16 x 16 tiles of the band layout,
+// in place (128 threads: one per column of one tile, back substitution; the
+// rows below the diagonal come out 0).
 template <typename T>
-__device__ void syrk_tiles(int m, const T *__restrict__ P, int64_t ldp, T *__restrict__ C, int64_t ldc, int wave,
-                           int lane) {
+__device__ __forceinline__ void inv_diag_lds(T *L) {
+    int tid = threadIdx.x;
+    // opaque to the compiler: otherwise the unit vectors below and the tile
+    // positions are formed once per kernel and kept live (spilled) across the
+    // persistent loop
+    asm volatile("" : "+v"(tid));
+    const int sb = tid >> 4, t = tid & 15;
+    T *U = L + tile_base(sb, sb);
+    T d[16];
+    if (tid < 16 * (kBB / 16)) {
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+            T acc = (i == t) ? T(1) : T(0);
+#pragma unroll
+            for (int k = i + 1; k < 16; ++k) acc -= U[tile_pos<T>(i, k, 0)] * d[k];
+            d[i] = acc / U[tile_pos<T>(i, i, 0)];
+        }
+    }
+    __syncthreads();
+    if (tid < 16 * (kBB / 16)) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) U[tile_pos<T>(i, t, 0)] = d[i];
+    }
+    __syncthreads();
+}
+
+// X := U11^{-T} X for the 16 columns c0 .. c0 + 15 of the 128 x m panel X
+// (columns >= m skipped), one wavefront.  U11's off-diagonal tiles and the
+// inverses of its diagonal tiles are read from L (band layout).  Block by
+// block, right-looking: X_s = D_s^T R_s, then R_t -= U(s, t)^T X_s for t > s;
+// the strip stays in registers in the layout of mma_ma, so no product needs
+// its operand transposed.
+template <typename T>
+__device__ __forceinline__ void trsm_strip_lds(int m, const T *L, T *__restrict__ X, int64_t ldx, int c0, int lane) {
     typedef typename BAcc<T>::type acc_t;
+    constexpr int NB = kBB / 16;
     const int r = lane & 15, g = lane >> 4;
-    const int nt = (m + 31) >> 5;
-    const int ntasks = nt * (nt + 1) / 2;
-    for (int task = wave; task < ntasks; task += 4) {
-        int J = (int)((sqrtf(8.0f * (float)task + 1.0f) - 1.0f) * 0.5f);
-        while (J * (J + 1) / 2 > task) --J;
-        while ((J + 1) * (J + 2) / 2 <= task) ++J;
-        const int I = task - J * (J + 1) / 2;
-        const int rb = 32 * I, cb = 32 * J;
-        acc_t acc[2][2];
+    const bool cok = c0 + r < m;
+    T *__restrict__ xc = X + (int64_t)min(c0 + r, m - 1) * ldx;
+    acc_t acc[NB];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+    for (int s = 0; s < NB; ++s)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+        for (int v = 0; v < 4; ++v) acc[s][v] = xc[16 * s + k_slot<T>(g, v)];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = rb + 16 * a + acc_row<T>(r, g, v);
-                    const int j = cb + 16 * b + acc_col<T>(r, g, v);
-                    acc[a][b][v] = C[(int64_t)min(i, m - 1) + (int64_t)min(j, m - 1) * ldc];
-                }
-        // operand columns (clamped; products of clamped columns are never stored)
-        const T *xp[2], *yp[2];
+    for (int s = 0; s < NB; ++s) {
+        // this block's LDS operands first, all at once; the compiler barrier
+        // keeps later blocks' reads from being hoisted here (their registers
+        // would not fit)
+        T dm[4], um[NB][4];
+        const T *D = L + tile_base(s, s);
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            xp[a] = P + (int64_t)min(rb + 16 * a + r, m - 1) * ldp;
-            yp[a] = P + (int64_t)min(cb + 16 * a + r, m - 1) * ldp;
+        for (int t = 0; t < 4; ++t) dm[t] = D[tile_pos<T>(k_slot<T>(g, t), r, 0)];
+#pragma unroll
+        for (int q = s + 1; q < NB; ++q) {
+            const T *U = L + tile_base(s, q);
+            const int key = tile_key<T>(q - s);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) um[q][t] = U[tile_pos<T>(k_slot<T>(g, t), r, key)];
         }
+        asm volatile("" ::: "memory");
+        acc_t xs = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int kc = 0; kc < kBB; kc += 16) {
-            // lane (r, g) supplies k = kc + 4g + t in MFMA step t for both
-            // operands, so the k slots agree whatever the hardware's order
-            T x[2][4], y[2][4];
+        for (int t = 0; t < 4; ++t) xs = mma_ma(dm[t], acc[s][t], xs);
+        if (cok) {
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    x[a][t] = -xp[a][kc + 4 * g + t];
-                    y[a][t] = yp[a][kc + 4 * g + t];
-                }
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) acc[a][b] = mma(x[a][t], y[b][t], acc[a][b]);
+            for (int v = 0; v < 4; ++v) xc[16 * s + k_slot<T>(g, v)] = xs[v];
         }
+        T nx[4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int t = 0; t < 4; ++t) nx[t] = -xs[t];
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+        for (int q = s + 1; q < NB; ++q)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = rb + 16 * a + acc_row<T>(r, g, v);
-                    const int j = cb + 16 * b + acc_col<T>(r, g, v);
-                    if (i <= j && j < m) C[(int64_t)i + (int64_t)j * ldc] = acc[a][b][v];
+            for (int t = 0; t < 4; ++t) acc[q] = mma_ma(um[q][t], nx[t], acc[q]);
+    }
+}
+
+// C := C - P^T P on the upper triangle of the m x m matrix C, P is kBB x m,
+// by the whole workgroup.  For each 64-column block J of C the workgroup
+// stages P(:, J) in LDS (column stride ys_stride, so that the operand reads
+// below hit distinct banks); then for each 64-row block I <= J, wavefront w
+// takes rows I + 16 w .. I + 16 w + 15 against the 16-column blocks of J that
+// reach the diagonal and lie inside C, with its own 16 columns of P read from
+// global memory into registers.  k slot of lane (r, g) in step e: 4 e + g, for
+// both operands.
+template <typename T>
+constexpr int ys_stride() {
+    return sizeof(T) == 8 ? kBB + 2 : kBB + 4;  // 2 mod 32 doubles / 4 mod 64 floats
+}
+
+// One wavefront: rows R0 .. R0 + 15 of C against its column blocks
+// b0 .. b0 + NA - 1 of the staged block at column J0 (NA fixed, so that the
+// products carry no per-block predicate).
+template <typename T, int NA>
+__device__ __forceinline__ void syrk_rows(int m, const T *__restrict__ P, int64_t ldp, T *__restrict__ C, int64_t ldc,
+                                          const T *Y, int R0, int J0, int b0, int lane) {
+    typedef typename BAcc<T>::type acc_t;
+    constexpr int YS = ys_stride<T>();
+    const int r = lane & 15, g = lane >> 4;
+    const T *xp = P + (int64_t)min(R0 + r, m - 1) * ldp;
+    T x[kBB / 4];
+#pragma unroll
+    for (int e = 0; e < kBB / 4; ++e) x[e] = -xp[4 * e + g];
+    T cv[NA][4];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = R0 + acc_row<T>(r, g, v), j = J0 + 16 * (b0 + a) + acc_col<T>(r, g, v);
+            cv[a][v] = C[(int64_t)min(i, m - 1) + (int64_t)min(j, m - 1) * ldc];
+        }
+    acc_t acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = acc_t{T(0), T(0), T(0), T(0)};
+    const T *yb = Y + (16 * b0 + r) * YS + g;
+#pragma unroll
+    for (int e0 = 0; e0 < kBB / 4; e0 += 4) {
+        // 16 k at a time: the chunk's LDS reads, then its products
+        T y[4][NA];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) y[e][a] = yb[16 * a * YS + 4 * (e0 + e)];
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) acc[a] = mma(x[e0 + e], y[e][a], acc[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = R0 + acc_row<T>(r, g, v), j = J0 + 16 * (b0 + a) + acc_col<T>(r, g, v);
+            if (i <= j && j < m) C[(int64_t)i + (int64_t)j * ldc] = cv[a][v] + acc[a][v];
+        }
+}
+
+template <typename T>
+__device__ __forceinline__ void syrk_lds(int m, const T *__restrict__ P, int64_t ldp, T *__restrict__ C, int64_t ldc,
+                                         T *Y, int wave, int lane) {
+    constexpr int YS = ys_stride<T>();
+    const int tid = threadIdx.x;
+    for (int J0 = 0; J0 < m; J0 += 64) {
+        {
+            // thread (c, q) copies k = 32 q .. 32 q + 31 of column J0 + c
+            const int c = tid >> 2, q = tid & 3;
+            const T *src = P + (int64_t)min(J0 + c, m - 1) * ldp + 32 * q;
+            T v[32];
+#pragma unroll
+            for (int i = 0; i < 32; ++i) v[i] = src[i];
+            T *dst = Y + c * YS + 32 * q;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) dst[i] = v[i];
+        }
+        __syncthreads();
+        const int nb = min(4, (m - J0 + 15) >> 4);  // column blocks of J inside C
+        for (int I0 = 0; I0 <= J0; I0 += 64) {
+            const int R0 = I0 + 16 * wave;
+            const int b0 = (I0 == J0) ? wave : 0;  // blocks left of b0: below the diagonal
+            if (R0 < m) {
+                switch (nb - b0) {
+                    case 1: syrk_rows<T, 1>(m, P, ldp, C, ldc, Y, R0, J0, b0, lane); break;
+                    case 2: syrk_rows<T, 2>(m, P, ldp, C, ldc, Y, R0, J0, b0, lane); break;
+                    case 3: syrk_rows<T, 3>(m, P, ldp, C, ldc, Y, R0, J0, b0, lane); break;
+                    case 4: syrk_rows<T, 4>(m, P, ldp, C, ldc, Y, R0, J0, b0, lane); break;
+                    default: break;
                 }
+            }
+        }
+        __syncthreads();  // Y is restaged
     }
 }
 
 // Workgroup-shared scratch of factor_one: the diagonal block's tiles during
-// CHOL, the TRSM inverses and per-wavefront staging afterwards.
+// CHOL and TRSM (all of U11 after CHOL, the diagonal tiles then replaced by
+// their inverses), the staged SYRK operands afterwards.
 template <typename T>
 struct BatchLds {
     union {
-        T L[band_lds_size<kBB>()];  // diagonal block, upper 16 x 16 tiles
-        struct {
-            T Ds[kBB / 16][16][17];  // inverses of the 16 x 16 diagonal blocks of U11
-            T Rt[4][16][17];         // per wavefront TRSM scratch
-        } t;
+        T L[band_lds_size<kBB>()];      // diagonal block, upper 16 x 16 tiles
+        T Y[64 * ys_stride<T>()];       // SYRK: 64 staged columns of the panel
     };
     int s_bad;
 };
@@ -155,27 +282,21 @@ __device__ int factor_one(int n, T *__restrict__ A, int64_t lda, BatchLds<T> &sh
         const int bk = min(kBB, n - k0);
         const int m = n - k0 - bk;
         T *A11 = A + k0 + (int64_t)k0 * lda;
-        // CHOL: the block's tiles in LDS, U11 stored to A11 band by band
+        // CHOL: the block's tiles in LDS, U11 stored to A11 band by band and
+        // kept in L
         band_load<T, kBB>(bk, A11, lda, sh.L);
         __syncthreads();
-        const int bad = chol_lds_core2<T, kBB>(bk, sh.L, &sh.s_bad, A11, lda);
+        const int bad = chol_lds_core2<T, kBB, false, true>(bk, sh.L, &sh.s_bad, A11, lda);
         if (bad != 0) return k0 + bad;
-        __syncthreads();  // U11 in memory for every wavefront; L free again
+        __syncthreads();  // U11 in L and in memory
         if (m == 0) break;
         // TRSM: A12 := U11^{-T} A12 (bk == kBB here)
         T *A12 = A + k0 + (int64_t)(k0 + kBB) * lda;
-        trsm_inverses<T, kBB / 16, true>(kBB, A11, lda, sh.t.Ds);
-        __syncthreads();
-        for (int c0 = 16 * wave; c0 < m; c0 += 64) {
-            // keeps the U11 loads inside the loop (hoisted, they would not fit
-            // in registers)
-            asm volatile("" ::: "memory");
-            trsm_cols<T, kBB / 16, true>(kBB, m, A11, lda, A12, lda, c0, sh.t.Ds, sh.t.Rt[wave]);
-        }
-        __syncthreads();
+        inv_diag_lds<T>(sh.L);
+        for (int c0 = 16 * wave; c0 < m; c0 += 64) trsm_strip_lds<T>(m, sh.L, A12, lda, c0, lane);
+        __syncthreads();  // A12 in memory, L free
         // SYRK: A22 -= A12^T A12 (upper)
-        syrk_tiles<T>(m, A12, lda, A + (k0 + kBB) + (int64_t)(k0 + kBB) * lda, lda, wave, lane);
-        __syncthreads();
+        syrk_lds<T>(m, A12, lda, A + (k0 + kBB) + (int64_t)(k0 + kBB) * lda, lda, sh.Y, wave, lane);
     }
     return 0;
 }
