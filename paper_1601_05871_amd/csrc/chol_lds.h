@@ -215,13 +215,14 @@ __device__ __forceinline__ void band_load(int n, const T *__restrict__ A, int64_
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool wide = n == NMAX && ((lda & (PER - 1)) == 0) && (((uintptr_t)A & 15) == 0);
     if (wide && PER * 64 == NMAX) {
-        // FP64: 64 lanes x 2 rows = one column per load
+        // FP64: 64 lanes x 2 rows = one column per load; lanes below the
+        // diagonal read the diagonal's pair again (same bytes, no traffic)
         const int row = PER * lane;
         u4 v[NMAX / 4];
 #pragma unroll
         for (int e = 0; e < NMAX / 4; ++e) {
             const int col = 4 * e + wave;
-            v[e] = *reinterpret_cast<const u4 *>(A + (int64_t)col * lda + row);
+            v[e] = *reinterpret_cast<const u4 *>(A + (int64_t)col * lda + min(row, col & ~(PER - 1)));
         }
 #pragma unroll
         for (int e = 0; e < NMAX / 4; ++e) {
@@ -341,32 +342,7 @@ __device__ int chol_lds_core2(int n, T *L, int *s_bad, T *__restrict__ A, int64_
         T a[16];
         T *const acol = L + tile_base(r0 >> 4, col >> 4);  // this column's tile in the band
         const int akey = tile_key<T>((col >> 4) - (r0 >> 4));
-        // i > c on the diagonal: unused
-        if constexpr (sizeof(T) == 8) {
-            const T *cp = acol + ((col & 15) >> 2) * 64 + ((col & 15) & 3) * 16;  // row 0 before the XOR
-            const int hx = row_xor64(col & 15);
-#pragma unroll
-            for (int i = 0; i < 16; i += 2) {
-                const double2 pr = *reinterpret_cast<const double2 *>(cp + (i ^ hx));
-                a[i] = pr.x;
-                a[i + 1] = pr.y;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) a[i] = acol[tile_pos<T>(i, col & 15, akey)];
-        }
         int bad = 0;
-        T dme = T(1), rep, nt;
-        band_pivot_setup<0>(a, c, bad, dme, rep, nt);
-        band_pivots<0>(a, c, bad, dme, rep, nt);
-        const T sme = sqrt(dme);
-        const T ime = recip(sme);
-        band_scale<0>(a, diag_lane, c, sme, ime);
-        if constexpr (TS) {
-            if (lane == 0) ts[r0 / 2 + wave] = __builtin_amdgcn_s_memtime();
-        }
-        // U rows r0 .. r0 + 15 are final: straight to A; the panel also back
-        // into its band tiles, where the update reads it
         T *__restrict__ out = A + (int64_t)r0 + (int64_t)col * lda;
         auto to_tile = [&]() {
             if constexpr (sizeof(T) == 8) {
@@ -379,31 +355,61 @@ __device__ int chol_lds_core2(int n, T *L, int *s_bad, T *__restrict__ A, int64_
                 for (int i = 0; i < 16; ++i) acol[tile_pos<T>(i, col & 15, akey)] = a[i];
             }
         };
-        if (diag_lane) {
-            if (wave == 0) {
-                if (col < n) {
+        // a wavefront whose 48 panel columns all lie beyond the band has no
+        // work in this pass (wavefront 0 always has: the diagonal block)
+        const bool active = wave == 0 || 48 * wave < rest;
+        if (active) {
+            // i > c on the diagonal: unused
+            if constexpr (sizeof(T) == 8) {
+                const T *cp = acol + ((col & 15) >> 2) * 64 + ((col & 15) & 3) * 16;  // row 0 before the XOR
+                const int hx = row_xor64(col & 15);
 #pragma unroll
-                    for (int i = 0; i < 16; ++i)
-                        if (i <= c) out[i] = a[i];
+                for (int i = 0; i < 16; i += 2) {
+                    const double2 pr = *reinterpret_cast<const double2 *>(cp + (i ^ hx));
+                    a[i] = pr.x;
+                    a[i + 1] = pr.y;
                 }
-            }
-        } else if (pvalid) {
-            to_tile();
-            if (col < n) {
-                if (wide) {
-                    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+            } else {
 #pragma unroll
-                    for (int i = 0; i < 16; i += 16 / (int)sizeof(T)) {
-                        u4 w;
-                        __builtin_memcpy(&w, &a[i], 16);
-                        *reinterpret_cast<u4 *>(out + i) = w;
+                for (int i = 0; i < 16; ++i) a[i] = acol[tile_pos<T>(i, col & 15, akey)];
+            }
+            T dme = T(1), rep, nt;
+            band_pivot_setup<0>(a, c, bad, dme, rep, nt);
+            band_pivots<0>(a, c, bad, dme, rep, nt);
+            const T sme = sqrt(dme);
+            const T ime = recip(sme);
+            band_scale<0>(a, diag_lane, c, sme, ime);
+            if constexpr (TS) {
+                if (lane == 0) ts[r0 / 2 + wave] = __builtin_amdgcn_s_memtime();
+            }
+            // U rows r0 .. r0 + 15 are final: straight to A; the panel also back
+            // into its band tiles, where the update reads it
+            if (diag_lane) {
+                if (wave == 0) {
+                    if (col < n) {
+#pragma unroll
+                        for (int i = 0; i < 16; ++i)
+                            if (i <= c) out[i] = a[i];
                     }
-                } else {
+                }
+            } else if (pvalid) {
+                to_tile();
+                if (col < n) {
+                    if (wide) {
+                        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) out[i] = a[i];
+                        for (int i = 0; i < 16; i += 16 / (int)sizeof(T)) {
+                            u4 w;
+                            __builtin_memcpy(&w, &a[i], 16);
+                            *reinterpret_cast<u4 *>(out + i) = w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) out[i] = a[i];
+                    }
                 }
             }
-        }
+        }  // active
         if (tid == 0) *s_bad = bad;
         lds_barrier();
         // every wavefront has read the diagonal tile of this band: it can take U

@@ -177,19 +177,38 @@ constexpr int ys_stride() {
     return sizeof(T) == 8 ? kBB + 2 : kBB + 4;  // 2 mod 32 doubles / 4 mod 64 floats
 }
 
+// 16 (or 4) bytes per lane from global memory straight into LDS: lane l's
+// bytes land at lds + 16 l (4 l); lds wavefront-uniform.
+__device__ __forceinline__ void copy16_to_lds(const char *gsrc, char *lds) {
+    __builtin_amdgcn_global_load_lds(gsrc, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+__device__ __forceinline__ void copy4_to_lds(const char *gsrc, char *lds) {
+    __builtin_amdgcn_global_load_lds(gsrc, (__attribute__((address_space(3))) void *)lds, 4, 0, 0);
+}
+
 // One wavefront: rows R0 .. R0 + 15 of C against its column blocks
 // b0 .. b0 + NA - 1 of the staged block at column J0 (NA fixed, so that the
-// products carry no per-block predicate).
+// products carry no per-block predicate).  The wavefront's panel columns
+// R0 + r are negated into registers in two halves of k: xa (k < 64) arrives
+// loaded by the previous item; xb (k >= 64) is loaded at the start and used
+// in the second half, and xa is reloaded meanwhile with the next item's
+// columns Rn + r.  Element e of a half is k = 4 e + g (+ 64).
+template <typename T>
+__device__ __forceinline__ void syrk_load_half(int m, const T *__restrict__ P, int64_t ldp, int R0, int k0, int lane,
+                                               T (&x)[kBB / 8]) {
+    const T *xp = P + (int64_t)min(R0 + (lane & 15), m - 1) * ldp + k0 + (lane >> 4);
+#pragma unroll
+    for (int e = 0; e < kBB / 8; ++e) x[e] = -xp[4 * e];
+}
+
 template <typename T, int NA>
-__device__ __forceinline__ void syrk_rows(int m, const T *__restrict__ P, int64_t ldp, T *__restrict__ C, int64_t ldc,
-                                          const T *Y, int R0, int J0, int b0, int lane) {
+__device__ __forceinline__ void syrk_rows(int m, const T *__restrict__ P, int64_t ldp, T (&xa)[kBB / 8], int Rn,
+                                          T *__restrict__ C, int64_t ldc, const T *Y, int R0, int J0, int b0,
+                                          int lane) {
     typedef typename BAcc<T>::type acc_t;
     constexpr int YS = ys_stride<T>();
+    constexpr int H = kBB / 8;  // elements per half
     const int r = lane & 15, g = lane >> 4;
-    const T *xp = P + (int64_t)min(R0 + r, m - 1) * ldp;
-    T x[kBB / 4];
-#pragma unroll
-    for (int e = 0; e < kBB / 4; ++e) x[e] = -xp[4 * e + g];
     T cv[NA][4];
 #pragma unroll
     for (int a = 0; a < NA; ++a)
@@ -198,24 +217,31 @@ __device__ __forceinline__ void syrk_rows(int m, const T *__restrict__ P, int64_
             const int i = R0 + acc_row<T>(r, g, v), j = J0 + 16 * (b0 + a) + acc_col<T>(r, g, v);
             cv[a][v] = C[(int64_t)min(i, m - 1) + (int64_t)min(j, m - 1) * ldc];
         }
+    T xb[H];
+    syrk_load_half<T>(m, P, ldp, R0, kBB / 2, lane, xb);
     acc_t acc[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) acc[a] = acc_t{T(0), T(0), T(0), T(0)};
     const T *yb = Y + (16 * b0 + r) * YS + g;
+    auto half = [&](const T(&x)[H], int kh) {
 #pragma unroll
-    for (int e0 = 0; e0 < kBB / 4; e0 += 4) {
-        // 16 k at a time: the chunk's LDS reads, then its products
-        T y[4][NA];
+        for (int e0 = 0; e0 < H; e0 += 4) {
+            // 16 k at a time: the chunk's LDS reads, then its products
+            T y[4][NA];
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+            for (int e = 0; e < 4; ++e)
 #pragma unroll
-            for (int a = 0; a < NA; ++a) y[e][a] = yb[16 * a * YS + 4 * (e0 + e)];
-        asm volatile("" ::: "memory");
+                for (int a = 0; a < NA; ++a) y[e][a] = yb[16 * a * YS + kh + 4 * (e0 + e)];
+            asm volatile("" ::: "memory");
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+            for (int e = 0; e < 4; ++e)
 #pragma unroll
-            for (int a = 0; a < NA; ++a) acc[a] = mma(x[e0 + e], y[e][a], acc[a]);
-    }
+                for (int a = 0; a < NA; ++a) acc[a] = mma(x[e0 + e], y[e][a], acc[a]);
+        }
+    };
+    half(xa, 0);
+    syrk_load_half<T>(m, P, ldp, Rn, 0, lane, xa);
+    half(xb, kBB / 2);
 #pragma unroll
     for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -225,13 +251,38 @@ __device__ __forceinline__ void syrk_rows(int m, const T *__restrict__ P, int64_
         }
 }
 
+// A wavefront's items are (J, I) with I <= J in loop order; it is idle only
+// on a diagonal item whose rows start at or beyond m, which can happen only in
+// the last column block.  The panel columns of the next item are loaded while
+// the current one computes.
 template <typename T>
 __device__ __forceinline__ void syrk_lds(int m, const T *__restrict__ P, int64_t ldp, T *__restrict__ C, int64_t ldc,
                                          T *Y, int wave, int lane) {
     constexpr int YS = ys_stride<T>();
     const int tid = threadIdx.x;
+    const bool wide16 = ((reinterpret_cast<uintptr_t>(P) & 15) == 0) && ((ldp & 1) == 0);
+    T xa[kBB / 8];
+    syrk_load_half<T>(m, P, ldp, 16 * wave, 0, lane, xa);  // item (0, 0)
     for (int J0 = 0; J0 < m; J0 += 64) {
-        {
+        if constexpr (sizeof(T) == 8) {
+            // copies from global memory straight into LDS (no registers: the
+            // wavefront holds the next item's panel columns meanwhile); wavefront
+            // w copies columns 16 w .. 16 w + 15, 16 bytes per lane (one column
+            // per copy) when every column starts 16-byte aligned, else 4
+#pragma unroll 4
+            for (int cc = 0; cc < 16; ++cc) {
+                const int c = 16 * wave + cc;
+                const char *src = reinterpret_cast<const char *>(P + (int64_t)min(J0 + c, m - 1) * ldp);
+                char *dst = reinterpret_cast<char *>(Y + c * YS);
+                if (wide16) {
+                    copy16_to_lds(src + 16 * lane, dst);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) copy4_to_lds(src + 256 * q + 4 * lane, dst + 256 * q);
+                }
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        } else {
             // thread (c, q) copies k = 32 q .. 32 q + 31 of column J0 + c
             const int c = tid >> 2, q = tid & 3;
             const T *src = P + (int64_t)min(J0 + c, m - 1) * ldp + 32 * q;
@@ -247,13 +298,14 @@ __device__ __forceinline__ void syrk_lds(int m, const T *__restrict__ P, int64_t
         for (int I0 = 0; I0 <= J0; I0 += 64) {
             const int R0 = I0 + 16 * wave;
             const int b0 = (I0 == J0) ? wave : 0;  // blocks left of b0: below the diagonal
-            if (R0 < m) {
+            if (R0 < m && b0 < nb) {
+                // next item: (J, I + 64), or (J + 64, 0) after the diagonal
+                const int Rn = (I0 + 64 <= J0 ? I0 + 64 : 0) + 16 * wave;
                 switch (nb - b0) {
-                    case 1: syrk_rows<T, 1>(m, P, ldp, C, ldc, Y, R0, J0, b0, lane); break;
-                    case 2: syrk_rows<T, 2>(m, P, ldp, C, ldc, Y, R0, J0, b0, lane); break;
-                    case 3: syrk_rows<T, 3>(m, P, ldp, C, ldc, Y, R0, J0, b0, lane); break;
-                    case 4: syrk_rows<T, 4>(m, P, ldp, C, ldc, Y, R0, J0, b0, lane); break;
-                    default: break;
+                    case 1: syrk_rows<T, 1>(m, P, ldp, xa, Rn, C, ldc, Y, R0, J0, b0, lane); break;
+                    case 2: syrk_rows<T, 2>(m, P, ldp, xa, Rn, C, ldc, Y, R0, J0, b0, lane); break;
+                    case 3: syrk_rows<T, 3>(m, P, ldp, xa, Rn, C, ldc, Y, R0, J0, b0, lane); break;
+                    default: syrk_rows<T, 4>(m, P, ldp, xa, Rn, C, ldc, Y, R0, J0, b0, lane); break;
                 }
             }
         }
@@ -271,6 +323,7 @@ struct BatchLds {
         T Y[64 * ys_stride<T>()];       // SYRK: 64 staged columns of the panel
     };
     int s_bad;
+    int s_item;
 };
 
 // Factors one matrix with the whole workgroup; returns the info value.
@@ -305,23 +358,32 @@ template <typename T>
 __global__ __launch_bounds__(256, 2) void k_batched(int32_t batch, const int32_t *__restrict__ ns, T *const *As,
                                                     const int32_t *__restrict__ ldas, int32_t *__restrict__ info,
                                                     const int32_t *__restrict__ order, int32_t *counter) {
+    // one LDS object: with several, the compiler tags LDS accesses with alias
+    // scopes and makes LDS reads wait for every copy into LDS still in flight
     __shared__ BatchLds<T> sh;
-    __shared__ int s_item;
     const int tid = threadIdx.x;
     // Every value that steers the loop is made wave-uniform (readfirstlane):
     // the branches around the barriers are then scalar, and every lane of a
     // wavefront takes the same path through them.
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(counter, 1);
+        if (tid == 0) sh.s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int t = __builtin_amdgcn_readfirstlane(s_item);
+        const int t = __builtin_amdgcn_readfirstlane(sh.s_item);
         __syncthreads();
         if (t >= batch) break;  // every wave of the workgroup leaves together
         const int i = __builtin_amdgcn_readfirstlane(order[t]);
         const int n = __builtin_amdgcn_readfirstlane(ns[i]);
         const int lda = __builtin_amdgcn_readfirstlane(ldas[i]);
         int res = -1;  // order out of range or lda < n: not touched
-        if (n >= 0 && n <= kBatchMaxN && lda >= max(1, n)) res = factor_one<T>(n, As[i], (int64_t)lda, sh);
+        if (n >= 0 && n <= kBatchMaxN && lda >= max(1, n)) {
+            // the matrix pointer read as a global-memory pointer: a pointer of
+            // unknown address space would make every access a flat one, and
+            // flat accesses count on the LDS wait counter too (each LDS wait
+            // would also wait for the global loads and stores in flight)
+            typedef __attribute__((address_space(1))) T gT;
+            gT *gA = static_cast<gT *const *>(static_cast<const void *>(As))[i];
+            res = factor_one<T>(n, (T *)gA, (int64_t)lda, sh);
+        }
         if (tid == 0) info[i] = res;
         __syncthreads();
     }
