@@ -61,6 +61,31 @@ def spd_bbt(n: int, seed: int = 0) -> np.ndarray:
     return _symmetrize_upper(A)
 
 
+def hpd_bbh(n: int, seed: int = 0) -> np.ndarray:
+    """Complex Hermitian positive definite A = B B^H + 2n I, B with N(0,1)
+    real and imaginary parts (real parts first, then imaginary, from
+    PCG64(seed)); exactly Hermitian (the lower triangle mirrors the upper one
+    conjugated), real diagonal, kappa <~ 5.  Fortran-ordered complex128."""
+    g = _rng(seed)
+    B = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    A = B @ B.conj().T
+    A[np.diag_indices(n)] = A.diagonal().real + 2.0 * n
+    T = np.triu(A)
+    return np.asfortranarray(T + np.triu(T, 1).conj().T)
+
+
+def hpd_exact(n: int, seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """(A, U) with A = U^H U exactly in binary64: U upper triangular with a
+    diagonal of powers of two (1, 2, 4) and off-diagonal entries whose real and
+    imaginary parts are small integers, so every step of the unblocked complex
+    factorization is exact and recovers U bit for bit."""
+    g = _rng(seed)
+    U = np.triu(g.integers(-3, 4, (n, n)) + 1j * g.integers(-3, 4, (n, n))).astype(np.complex128)
+    U[np.diag_indices(n)] = 2.0 ** g.integers(0, 3, n)
+    A = U.conj().T @ U  # small integers: exact
+    return np.asfortranarray(A), np.asfortranarray(U)
+
+
 def spd_bbt_torch(n: int, seed: int, device):
     """Same recipe as spd_bbt, with the product B B^T formed by torch on
     ``device`` (fast at n = 16384).  The bytes can differ from spd_bbt in the

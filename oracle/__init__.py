@@ -47,6 +47,8 @@ def load(path: str) -> ctypes.CDLL:
         L.oracle_fill_pattern.restype = i64
         L.oracle_ichol_rows.argtypes = [i64, dp, dp, dp]
         L.oracle_ichol_rows.restype = i32
+        L.oracle_zpotrf_upper.argtypes = [i64, dp, i64]
+        L.oracle_zpotrf_upper.restype = i32
     return L
 
 
@@ -92,6 +94,27 @@ def potrf(A: np.ndarray, threads: int = 1, steps: int | None = None) -> tuple[np
     js = n if steps is None else int(steps)
     info = lib().oracle_potrf_upper_steps(n, _ptr(W), max(1, n), js, int(threads))
     return W, int(info)
+
+
+def zpotrf(A: np.ndarray) -> tuple[np.ndarray, int]:
+    """O8: unblocked complex Cholesky A = U^H U (Fig. "dense-chol" at b = 1
+    with the Hermitian update) on a copy of the complex128 matrix A.
+    Returns (A_out, info) as :func:`potrf`: the upper triangle holds U (real
+    positive diagonal), the strictly lower triangle is A's, untouched."""
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise TypeError("zpotrf expects a square matrix")
+    W = np.array(A, dtype=np.complex128, order="F", copy=True)
+    n = W.shape[0]
+    info = lib().oracle_zpotrf_upper(n, _ptr(W), max(1, n))
+    return W, int(info)
+
+
+def zfactor_backward_error(A: np.ndarray, U: np.ndarray) -> float:
+    """||A - U^H U||_F / ||A||_F for the upper triangle U of a complex factor
+    (A Hermitian, given by its upper triangle)."""
+    Ah = np.triu(A) + np.triu(A, 1).conj().T
+    Ut = np.triu(U)
+    return float(np.linalg.norm(Ah - Ut.conj().T @ Ut) / np.linalg.norm(Ah))
 
 
 def potrf_inplace(W: np.ndarray, lda: int, n: int, threads: int = 0, steps: int | None = None) -> int:

@@ -413,3 +413,51 @@ int oracle_ichol_rows(int64_t n, const int64_t *rp, const int32_t *ci, double *v
     }
     return 0;
 }
+
+/*
+ * O8 -- the loop of Fig. "dense-chol" at b = 1 for a complex Hermitian
+ * positive definite A = U^H U (the HERK the figure names is the Hermitian
+ * rank-k update; the conclusion lists complex data among the extensions).
+ * A holds interleaved (real, imaginary) doubles, element (i, j) at
+ * A[2 (i + j lda)] and A[2 (i + j lda) + 1] (lda counts complex elements);
+ * only the upper triangle is read and written.
+ *
+ * Step j, with alpha11 = A(j,j), a12 = A(j, j+1:n), A22 = A(j+1:n, j+1:n):
+ *   alpha11 := sqrt(re alpha11)                      CHOL (its imaginary part,
+ *                                                    zero for Hermitian A, is
+ *                                                    not read; U(j,j) is real)
+ *   a12     := a12 / alpha11                         TRSM (triu(alpha11)^{-H})
+ *   A22     := A22 - a12^H a12   (upper part)        HERK
+ * element-wise A(i,c) -= conj(U(j,i)) U(j,c) for j < i <= c, with
+ *   conj(x) y = (xr yr + xi yi) + i (xr yi - xi yr),
+ * each product rounded, the two summed, then subtracted.  Breakdown: the
+ * first pivot whose real part is not > 0 (NaN included) stops the loop and
+ * returns its 1-based column.  Returns 0 on success.
+ */
+#define ZR(A, lda, i, j) ((A)[2 * ((int64_t)(i) + (int64_t)(j) * (int64_t)(lda))])
+#define ZI(A, lda, i, j) ((A)[2 * ((int64_t)(i) + (int64_t)(j) * (int64_t)(lda)) + 1])
+
+int oracle_zpotrf_upper(int64_t n, double *A, int64_t lda) {
+    for (int64_t j = 0; j < n; ++j) {
+        double a = ZR(A, lda, j, j);
+        if (!(a > 0.0)) return (int)(j + 1);
+        double d = sqrt(a);
+        ZR(A, lda, j, j) = d;
+        ZI(A, lda, j, j) = 0.0;
+        for (int64_t c = j + 1; c < n; ++c) {
+            ZR(A, lda, j, c) = ZR(A, lda, j, c) / d;
+            ZI(A, lda, j, c) = ZI(A, lda, j, c) / d;
+        }
+        for (int64_t c = j + 1; c < n; ++c) {
+            double yr = ZR(A, lda, j, c), yi = ZI(A, lda, j, c);
+            for (int64_t i = j + 1; i <= c; ++i) {
+                double xr = ZR(A, lda, j, i), xi = ZI(A, lda, j, i);
+                double pr = xr * yr + xi * yi;
+                double pi = xr * yi - xi * yr;
+                ZR(A, lda, i, c) = ZR(A, lda, i, c) - pr;
+                ZI(A, lda, i, c) = ZI(A, lda, i, c) - pi;
+            }
+        }
+    }
+    return 0;
+}
