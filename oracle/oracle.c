@@ -439,18 +439,18 @@ int oracle_ichol_rows(int64_t n, const int64_t *rp, const int32_t *ci, double *v
 
 int oracle_zpotrf_upper(int64_t n, double *A, int64_t lda) {
     for (int64_t j = 0; j < n; ++j) {
-        double a = ZR(A, lda, j, j);
-        if (!(a > 0.0)) return (int)(j + 1);
-        double d = sqrt(a);
-        ZR(A, lda, j, j) = d;
+        double ar = ZR(A, lda, j, j);
+        if (!(ar > 0.0)) return (int)(j + 1);
+        double dr = sqrt(ar);
+        ZR(A, lda, j, j) = dr;
         ZI(A, lda, j, j) = 0.0;
         for (int64_t c = j + 1; c < n; ++c) {
-            ZR(A, lda, j, c) = ZR(A, lda, j, c) / d;
-            ZI(A, lda, j, c) = ZI(A, lda, j, c) / d;
+            ZR(A, lda, j, c) = ZR(A, lda, j, c) / dr;
+            ZI(A, lda, j, c) = ZI(A, lda, j, c) / dr;
         }
         for (int64_t c = j + 1; c < n; ++c) {
             double yr = ZR(A, lda, j, c), yi = ZI(A, lda, j, c);
-            for (int64_t i = j + 1; i <= c; ++i) {
+            for (int64_t i = j + 1; i <= c; i++) {
                 double xr = ZR(A, lda, j, i), xi = ZI(A, lda, j, i);
                 double pr = xr * yr + xi * yi;
                 double pi = xr * yi - xi * yr;

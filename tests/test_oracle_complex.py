@@ -68,9 +68,8 @@ MUTANTS = {
     "herk_no_conjugate": ("double pr = xr * yr + xi * yi;\n                double pi = xr * yi - xi * yr;",
                           "double pr = xr * yr - xi * yi;\n                double pi = xr * yi + xi * yr;"),
     "herk_imag_sign": ("double pi = xr * yi - xi * yr;", "double pi = xi * yr - xr * yi;"),
-    "trsm_real_part_only": ("ZI(A, lda, j, c) = ZI(A, lda, j, c) / d;", "ZI(A, lda, j, c) = ZI(A, lda, j, c);"),
-    "herk_skips_diagonal": ("for (int64_t i = j + 1; i <= c; ++i) {\n                double xr",
-                            "for (int64_t i = j + 1; i < c; ++i) {\n                double xr"),
+    "trsm_real_part_only": ("ZI(A, lda, j, c) = ZI(A, lda, j, c) / dr;", "ZI(A, lda, j, c) = ZI(A, lda, j, c);"),
+    "herk_skips_diagonal": ("for (int64_t i = j + 1; i <= c; i++) {", "for (int64_t i = j + 1; i < c; i++) {"),
 }
 
 
