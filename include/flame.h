@@ -45,7 +45,9 @@ extern "C" {
 #define FLAME_ERR_BREAKDOWN 5     /* flame_solve_mixed: no factorization attempt succeeded */
 
 /* ---- enumerations ------------------------------------------------------- */
-typedef enum { FLAME_F64 = 0, FLAME_F32 = 1 } flame_dtype_t;
+/* FLAME_Z64: complex double, each element two doubles (real part first, the
+ * C99 "double complex" / std::complex<double> layout); flame_factor only. */
+typedef enum { FLAME_F64 = 0, FLAME_F32 = 1, FLAME_Z64 = 2 } flame_dtype_t;
 
 /* The three loop invariants of A = U^T U after A_TL (k x k) is processed:
  *   BORDERED (1): A_TL = U_TL;                       A_TR, A_BR untouched
@@ -121,7 +123,21 @@ typedef struct {
  *   stream hipStream_t or NULL
  * Errors: -1 dtype, -2 n, -3 A (NULL with n > 0), -4 lda, -5 opts (bad field),
  * -6 info (NULL); FLAME_ERR_UNSUPPORTED for trail != NATIVE with dtype F32 or
- * with variant != RIGHT. */
+ * with variant != RIGHT.
+ *
+ * dtype FLAME_Z64: A complex Hermitian positive definite, A = U^H U with U
+ * upper triangular with a real positive diagonal (the loop of Fig.
+ * "dense-chol" with the Hermitian update A22 - A12^H A12 it names HERK, and
+ * A12 := triu(A11)^{-H} A12; the paper's data are real, complex data is one
+ * of the extensions its conclusion lists).  A is element-interleaved
+ * (lda counts complex elements); the imaginary parts of the diagonal are not
+ * read and are written 0.  Only the right-looking loop at native precision
+ * (variant AUTO or RIGHT, trail NATIVE; anything else FLAME_ERR_UNSUPPORTED);
+ * opts.nb is the outer block (default 256; rounded to a multiple of 64 in
+ * 64..512), opts.graph and opts.lookahead are ignored; FLAME_OPT_LOWER gives
+ * A = L L^H in the lower triangle.  Breakdown: info = first column whose
+ * pivot's real part is not > 0.  Device workspace of 16 n^2 bytes (two real
+ * planes) plus O(nb n) is allocated on the first call and kept. */
 int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opts_t *opts, int32_t *info,
                  void *stream);
 

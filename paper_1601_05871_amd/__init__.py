@@ -21,7 +21,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libflame.so")
 
-F64, F32 = 0, 1
+F64, F32, Z64 = 0, 1, 2
 OPT_FIXED_NB = 1
 OPT_LOWER = 2
 VAR_AUTO, VAR_BORDERED, VAR_LEFT, VAR_RIGHT, VAR_BY_BLOCKS = 0, 1, 2, 3, 4
@@ -202,7 +202,9 @@ def _dtype_code(t) -> int:
         return F64
     if t.dtype == torch.float32:
         return F32
-    raise TypeError(f"unsupported dtype {t.dtype} (float64 or float32)")
+    if t.dtype == torch.complex128:
+        return Z64  # flame_factor only
+    raise TypeError(f"unsupported dtype {t.dtype} (float64, float32, or complex128 for factor)")
 
 
 def _colmajor_ld(t, rows: int | None = None) -> int:
@@ -240,7 +242,9 @@ def factor(A, variant: int = VAR_RIGHT, nb: int = 128, trail="native", lookahead
     lower triangle, the upper one left as it is).  Returns the device int32
     ``info`` tensor (0, or the 1-based column of the first non-positive pivot).
     Asynchronous on the current stream.  ``fixed_nb``: the right-looking loop
-    runs every block at ``nb`` (no smaller blocks in the last columns)."""
+    runs every block at ``nb`` (no smaller blocks in the last columns).
+    complex128 A: the Hermitian factorization A = U^H U (A = L L^H with
+    ``lower``), right-looking at native precision only."""
     torch = _torch()
     if A.dim() != 2 or A.shape[0] != A.shape[1]:
         raise ValueError("A must be a square 2-D tensor")

@@ -36,17 +36,46 @@ int normalize_opts(const flame_opts_t *in, int32_t dtype, int64_t n, flame_opts_
     return 0;
 }
 
+// dtype FLAME_Z64: the complex Hermitian factorization (zfactor.cpp), the
+// right-looking loop only, native precision, run without graph capture.
+int factor_complex(int64_t n, void *A, int64_t lda, const flame_opts_t *opts, int32_t *info, void *stream) {
+    flame_opts_t o;
+    if (opts != nullptr)
+        o = *opts;
+    else
+        std::memset(&o, 0, sizeof(o));
+    if (o.variant < FLAME_VAR_AUTO || o.variant > FLAME_VAR_BY_BLOCKS) return -5;
+    if (o.nb < 0 || o.nb > kMaxNb) return -5;
+    if (o.trail < FLAME_TRAIL_NATIVE || o.trail > FLAME_TRAIL_BF16) return -5;
+    if (o.lookahead < -1 || o.lookahead > 2) return -5;
+    if (o.graph < 0 || o.graph > 1) return -5;
+    if ((o.flags & ~(FLAME_OPT_FIXED_NB | FLAME_OPT_LOWER)) != 0) return -5;
+    if (o.reserved[0] != 0 || o.reserved[1] != 0) return -5;
+    if ((o.variant != FLAME_VAR_AUTO && o.variant != FLAME_VAR_RIGHT) || o.trail != FLAME_TRAIL_NATIVE)
+        return FLAME_ERR_UNSUPPORTED;
+    const int nb = o.nb == 0 ? 256 : o.nb;
+    hipStream_t s = as_stream(stream);
+    if ((o.flags & FLAME_OPT_LOWER) == 0) return zfactor(n, A, lda, nb, info, s);
+    // lower storage (A = L L^H): the swapped triangles hold conj(A)'s upper
+    // triangle, whose factor U_c gives L = U_c^T once swapped back
+    int rc = launch_swap_triangles<zdouble>(n, static_cast<zdouble *>(A), lda, s);
+    if (!rc) rc = zfactor(n, A, lda, nb, info, s);
+    if (!rc) rc = launch_swap_triangles<zdouble>(n, static_cast<zdouble *>(A), lda, s);
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
 
 int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opts_t *opts, int32_t *info,
                  void *stream) {
-    if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
+    if (dtype != FLAME_F64 && dtype != FLAME_F32 && dtype != FLAME_Z64) return -1;
     if (n < 0 || n > ((int64_t)1 << 31) - 1) return -2;
     if (A == nullptr && n > 0) return -3;
     if (lda < (n > 1 ? n : 1)) return -4;
     if (info == nullptr) return -6;
+    if (dtype == FLAME_Z64) return factor_complex(n, A, lda, opts, info, stream);
     flame_opts_t o;
     int rc = normalize_opts(opts, dtype, n, &o);
     if (rc) return rc;

@@ -161,6 +161,30 @@ int launch_batched(int32_t batch, const int32_t *n, void *const *A, const int32_
                    hipStream_t s, bool traced = true);
 size_t batched_workspace_ints(int32_t batch);
 
+// ---- complex Hermitian factorization (k_complex.hip, zfactor.cpp) ---------
+// One complex double: two doubles, real part first (the interleaved layout).
+struct zdouble {
+    double re, im;
+    zdouble() = default;
+    __host__ __device__ constexpr zdouble(double v) : re(v), im(0.0) {}
+};
+// Real and imaginary planes (column-major, ld) := upper triangle of the
+// interleaved complex A, and back (the diagonal's imaginary part written 0).
+int launch_z_split(int64_t n, const void *A, int64_t lda, double *R, double *I, int64_t ld, hipStream_t s);
+int launch_z_merge(int64_t n, const double *R, const double *I, int64_t ld, void *A, int64_t lda, hipStream_t s);
+// dst := scale * src (skipped if info && *info) and dst := 0 (rows x cols,
+// real).
+int launch_scaled_copy(int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst, int64_t ldd,
+                       double scale, const int32_t *info, hipStream_t s);
+int launch_fill0(int64_t rows, int64_t cols, double *dst, int64_t ldd, hipStream_t s);
+// Complex diagonal block (n <= 64, planes): A := Chol(A); on breakdown
+// *info = info_base + column.  V := -U^{-1} (n <= 64).  Both skip if *info.
+int launch_zchol_lds(int n, double *R, double *I, int64_t ld, int32_t *info, int64_t info_base, hipStream_t s);
+int launch_ztrinv_lds(int n, const double *R, const double *I, int64_t ld, double *Vr, double *Vi, int64_t ldv,
+                      const int32_t *info, hipStream_t s);
+// The complex factorization of flame_factor (dtype FLAME_Z64), upper storage.
+int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t s);
+
 // ---- selector --------------------------------------------------------------
 int launch_selector(const float *w, const float *feat, int64_t count, float *logits, hipStream_t s);
 
@@ -178,7 +202,8 @@ enum {
     kWsSplit = 5,
     kWsMixed = 6,
     kWsDag = 7,
-    kWsSlots = 8
+    kWsComplex = 8,
+    kWsSlots = 9
 };
 int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out);
 // Generation of a slot's buffer: changes every time ctx_workspace replaces it

@@ -1,0 +1,208 @@
+// Complex Hermitian factorization A = U^H U (the loop of Fig. "dense-chol"
+// with its HERK update taken literally; complex data is one of the
+// extensions the conclusion lists): the kernels of the steps that are not a
+// plain real product.  The driver (zfactor.cpp) keeps the matrix as two real
+// planes, real and imaginary parts, so that the Hermitian update and the
+// off-diagonal products of the panel solve run as real matrix-core products
+// (launch_gemm_tn); the kernels here split and merge the planes, factor a
+// diagonal block of order <= 64 and form the inverse of a diagonal block of
+// U for the panel solve.
+#include "flame_internal.h"
+
+namespace flame {
+
+namespace {
+
+constexpr int kZ = 64;  // order of the diagonal blocks factored in LDS
+
+// planes := upper triangle of the interleaved complex A (one workgroup per
+// column); the strictly lower part of the planes is not written
+__global__ __launch_bounds__(256) void k_z_split(int64_t n, const double *__restrict__ A, int64_t lda,
+                                                 double *__restrict__ R, double *__restrict__ I, int64_t ld) {
+    const int64_t j = blockIdx.x;
+    for (int64_t i = threadIdx.x; i <= j; i += 256) {
+        const double *a = A + 2 * (i + j * lda);
+        R[i + j * ld] = a[0];
+        I[i + j * ld] = a[1];
+    }
+}
+
+// upper triangle of the interleaved A := planes; the diagonal's imaginary
+// part is written 0 (U has a real diagonal)
+__global__ __launch_bounds__(256) void k_z_merge(int64_t n, const double *__restrict__ R,
+                                                 const double *__restrict__ I, int64_t ld, double *__restrict__ A,
+                                                 int64_t lda) {
+    const int64_t j = blockIdx.x;
+    for (int64_t i = threadIdx.x; i <= j; i += 256) {
+        double *a = A + 2 * (i + j * lda);
+        a[0] = R[i + j * ld];
+        a[1] = (i == j) ? 0.0 : I[i + j * ld];
+    }
+}
+
+// dst := scale * src (rows x cols), one workgroup per column; skipped if
+// *info != 0 (after a breakdown the panel keeps what it held)
+__global__ __launch_bounds__(256) void k_scaled_copy(int64_t rows, const double *__restrict__ src, int64_t lds,
+                                                     double *__restrict__ dst, int64_t ldd, double scale,
+                                                     const int32_t *__restrict__ info) {
+    if (info != nullptr && *info != 0) return;
+    const int64_t j = blockIdx.x;
+    for (int64_t i = threadIdx.x; i < rows; i += 256) dst[i + j * ldd] = scale * src[i + j * lds];
+}
+
+__global__ __launch_bounds__(256) void k_fill0(int64_t rows, double *__restrict__ dst, int64_t ldd) {
+    const int64_t j = blockIdx.x;
+    for (int64_t i = threadIdx.x; i < rows; i += 256) dst[i + j * ldd] = 0.0;
+}
+
+// A := Chol(A) for the n x n (n <= 64) diagonal block held in the planes
+// (upper triangle), one workgroup, the block in LDS ([column][row], padded).
+// Step j: pivot re A(j,j) (its imaginary part is not read), row j divided by
+// its square root, then A(i,c) -= conj(U(j,i)) U(j,c) for j < i <= c, the
+// 256 threads on (column, row-group) pairs.  On a pivot that is not > 0 it
+// writes *info = info_base + j + 1 and stops (the planes then hold nothing
+// of this block's result).  Skips if *info != 0 on entry.
+__global__ __launch_bounds__(256) void k_zchol_lds(int n, double *__restrict__ R, double *__restrict__ I, int64_t ld,
+                                                   int32_t *__restrict__ info, int64_t info_base) {
+    __shared__ double sr[kZ][kZ + 1], si[kZ][kZ + 1];
+    if (*info != 0) return;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kZ * kZ; e += 256) {
+        const int i = e & (kZ - 1), j = e >> 6;
+        if (i <= j && j < n) {
+            sr[j][i] = R[i + (int64_t)j * ld];
+            si[j][i] = I[i + (int64_t)j * ld];
+        }
+    }
+    __syncthreads();
+    const int cl = tid & (kZ - 1), rg = tid >> 6;  // column lane, row group
+    for (int j = 0; j < n; ++j) {
+        const double d = sr[j][j];
+        if (!(d > 0.0)) {  // every thread reads the same pivot: a uniform exit
+            if (tid == 0) *info = (int32_t)(info_base + j + 1);
+            return;
+        }
+        const double s = sqrt(d);
+        for (int c = j + 1 + tid; c < n; c += 256) {
+            sr[c][j] = sr[c][j] / s;
+            si[c][j] = si[c][j] / s;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            sr[j][j] = s;
+            si[j][j] = 0.0;
+        }
+        const int c = j + 1 + cl;
+        if (c < n) {
+            const double yr = sr[c][j], yi = si[c][j];
+            for (int i = j + 1 + rg; i <= c; i += 4) {
+                const double xr = sr[i][j], xi = si[i][j];
+                sr[c][i] -= xr * yr + xi * yi;
+                si[c][i] -= xr * yi - xi * yr;
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < kZ * kZ; e += 256) {
+        const int i = e & (kZ - 1), j = e >> 6;
+        if (i <= j && j < n) {
+            R[i + (int64_t)j * ld] = sr[j][i];
+            I[i + (int64_t)j * ld] = si[j][i];
+        }
+    }
+}
+
+// V := -U^{-1} for the n x n (n <= 64) upper triangular U in the planes
+// (real diagonal), into the planes Vr, Vi (ldv), zero below the diagonal:
+// thread t solves U v = e_t by back substitution, v in LDS.  Skips if
+// *info != 0.
+__global__ __launch_bounds__(64) void k_ztrinv_lds(int n, const double *__restrict__ R, const double *__restrict__ I,
+                                                   int64_t ld, double *__restrict__ Vr, double *__restrict__ Vi,
+                                                   int64_t ldv, const int32_t *__restrict__ info) {
+    __shared__ double ur[kZ][kZ + 1], ui[kZ][kZ + 1];  // [column][row]
+    __shared__ double vr[kZ][kZ + 1], vi[kZ][kZ + 1];  // [column t][row]
+    if (*info != 0) return;
+    const int t = threadIdx.x;
+    for (int e = t; e < kZ * kZ; e += kZ) {
+        const int i = e & (kZ - 1), j = e >> 6;
+        if (i <= j && j < n) {
+            ur[j][i] = R[i + (int64_t)j * ld];
+            ui[j][i] = I[i + (int64_t)j * ld];
+        }
+    }
+    __syncthreads();
+    if (t < n) {
+        for (int i = n - 1; i >= 0; --i) {
+            double ar = (i == t) ? 1.0 : 0.0, ai = 0.0;
+            if (i <= t) {
+                for (int k = i + 1; k <= t; ++k) {
+                    const double pr = ur[k][i], pi = ui[k][i], qr = vr[t][k], qi = vi[t][k];
+                    ar -= pr * qr - pi * qi;
+                    ai -= pr * qi + pi * qr;
+                }
+                const double d = ur[i][i];  // real diagonal
+                ar /= d;
+                ai /= d;
+            }
+            vr[t][i] = ar;
+            vi[t][i] = ai;
+        }
+        for (int i = 0; i < n; ++i) {
+            Vr[i + (int64_t)t * ldv] = -vr[t][i];
+            Vi[i + (int64_t)t * ldv] = -vi[t][i];
+        }
+    }
+}
+
+unsigned cols_grid(int64_t cols) { return (unsigned)std::max<int64_t>(1, cols); }
+
+}  // namespace
+
+int launch_z_split(int64_t n, const void *A, int64_t lda, double *R, double *I, int64_t ld, hipStream_t s) {
+    if (n <= 0) return FLAME_OK;
+    hipLaunchKernelGGL(k_z_split, dim3(cols_grid(n)), dim3(256), 0, s, n, static_cast<const double *>(A), lda, R, I,
+                       ld);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int launch_z_merge(int64_t n, const double *R, const double *I, int64_t ld, void *A, int64_t lda, hipStream_t s) {
+    if (n <= 0) return FLAME_OK;
+    hipLaunchKernelGGL(k_z_merge, dim3(cols_grid(n)), dim3(256), 0, s, n, R, I, ld, static_cast<double *>(A), lda);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int launch_scaled_copy(int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst, int64_t ldd,
+                       double scale, const int32_t *info, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return FLAME_OK;
+    hipLaunchKernelGGL(k_scaled_copy, dim3(cols_grid(cols)), dim3(256), 0, s, rows, src, lds, dst, ldd, scale, info);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int launch_fill0(int64_t rows, int64_t cols, double *dst, int64_t ldd, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return FLAME_OK;
+    hipLaunchKernelGGL(k_fill0, dim3(cols_grid(cols)), dim3(256), 0, s, rows, dst, ldd);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int launch_zchol_lds(int n, double *R, double *I, int64_t ld, int32_t *info, int64_t info_base, hipStream_t s) {
+    if (n <= 0) return FLAME_OK;
+    if (n > kZ) return FLAME_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_zchol_lds, dim3(1), dim3(256), 0, s, n, R, I, ld, info, info_base);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int launch_ztrinv_lds(int n, const double *R, const double *I, int64_t ld, double *Vr, double *Vi, int64_t ldv,
+                      const int32_t *info, hipStream_t s) {
+    if (n <= 0) return FLAME_OK;
+    if (n > kZ) return FLAME_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_ztrinv_lds, dim3(1), dim3(kZ), 0, s, n, R, I, ld, Vr, Vi, ldv, info);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+}  // namespace flame

@@ -63,5 +63,6 @@ int launch_swap_triangles(int64_t n, T *A, int64_t lda, hipStream_t s) {
 
 template int launch_swap_triangles<double>(int64_t, double *, int64_t, hipStream_t);
 template int launch_swap_triangles<float>(int64_t, float *, int64_t, hipStream_t);
+template int launch_swap_triangles<zdouble>(int64_t, zdouble *, int64_t, hipStream_t);
 
 }  // namespace flame

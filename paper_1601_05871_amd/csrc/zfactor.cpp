@@ -1,0 +1,133 @@
+// Complex Hermitian factorization A = U^H U (dtype FLAME_Z64 of flame_factor):
+// the right-looking loop of Fig. "dense-chol" with its update read literally
+// as the Hermitian rank-k update,
+//   A11 := Chol(A11);  A12 := triu(A11)^{-H} A12;  A22 := A22 - A12^H A12,
+// on complex data (the conclusion lists complex data among the extensions).
+//
+// The matrix is kept in two real planes (real and imaginary parts, column-
+// major, ld = n) for the whole factorization, split from and merged back into
+// the caller's interleaved upper triangle.  Every complex product
+// C -= P^H Q is then four real matrix-core products of the trailing-update
+// kernel (launch_gemm_tn, C -= X^T Y), since
+//   P^H Q = (Pr^T Qr + Pi^T Qi) + i (Pr^T Qi - Pi^T Qr),
+// the last one with a negated copy of Pi.  The HERK of each iteration is one
+// such product (upper triangle only); the panel solve goes by diagonal blocks
+// of 64: the block's inverse V = U_ss^{-1} (k_ztrinv_lds), X_s := V^H X_s as a
+// product into a scratch panel, and X_t -= U_st^H X_s for the blocks below.
+// Diagonal blocks of the outer loop (nb) are factored by the same loop at
+// block 64, whose diagonal blocks go to the LDS kernel k_zchol_lds.
+#include <algorithm>
+
+#include "flame_internal.h"
+
+namespace flame {
+
+namespace {
+
+constexpr int kZB = 64;  // inner block (LDS kernels)
+
+struct ZWork {
+    double *R, *I;  // planes, ld = n
+    int64_t ld;
+    double *Tr, *Ti;  // scratch panel, kZB x n
+    double *Pn;       // negated imaginary operand, up to nb x n
+    double *Vr, *Vi;  // -U_ss^{-1}, kZB x kZB
+};
+
+// C -= P^H Q; P is K x M (ldp), Q is K x N (ldq), C is M x N (ldc), each given
+// by its planes.  upper: only i <= j of C is written (the HERK).
+int zgemm_h(bool upper, int64_t M, int64_t N, int64_t K, const double *Pr, const double *Pi, int64_t ldp,
+            const double *Qr, const double *Qi, int64_t ldq, double *Cr, double *Ci, int64_t ldc, double *Pn,
+            const int32_t *info, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return FLAME_OK;
+    int rc = launch_gemm_tn(Prec::F64, true, upper, M, N, K, Pr, ldp, Qr, ldq, Cr, ldc, info, s);
+    if (!rc) rc = launch_gemm_tn(Prec::F64, true, upper, M, N, K, Pi, ldp, Qi, ldq, Cr, ldc, info, s);
+    if (!rc) rc = launch_gemm_tn(Prec::F64, true, upper, M, N, K, Pr, ldp, Qi, ldq, Ci, ldc, info, s);
+    if (!rc) rc = launch_scaled_copy(K, M, Pi, ldp, Pn, K, -1.0, info, s);
+    if (!rc) rc = launch_gemm_tn(Prec::F64, true, upper, M, N, K, Pn, K, Qr, ldq, Ci, ldc, info, s);
+    return rc;
+}
+
+// X := triu(U)^{-H} X for the b x b block U at (k, k) and the b x m panel X
+// at (k, c0) of the planes.
+int ztrsm(const ZWork &w, int64_t k, int64_t b, int64_t c0, int64_t m, const int32_t *info, hipStream_t s) {
+    const int64_t ld = w.ld;
+    for (int64_t s0 = 0; s0 < b; s0 += kZB) {
+        const int64_t bs = std::min<int64_t>(kZB, b - s0);
+        const int64_t us = (k + s0) + (k + s0) * ld;  // U_ss
+        const int64_t xs = (k + s0) + c0 * ld;         // X_s
+        int rc = launch_ztrinv_lds((int)bs, w.R + us, w.I + us, ld, w.Vr, w.Vi, kZB, info, s);
+        // T := 0 - (-V)^H X_s = V^H X_s, then X_s := T
+        if (!rc) rc = launch_fill0(bs, m, w.Tr, kZB, s);
+        if (!rc) rc = launch_fill0(bs, m, w.Ti, kZB, s);
+        if (!rc)
+            rc = zgemm_h(false, bs, m, bs, w.Vr, w.Vi, kZB, w.R + xs, w.I + xs, ld, w.Tr, w.Ti, kZB, w.Pn, info, s);
+        if (!rc) rc = launch_scaled_copy(bs, m, w.Tr, kZB, w.R + xs, ld, 1.0, info, s);
+        if (!rc) rc = launch_scaled_copy(bs, m, w.Ti, kZB, w.I + xs, ld, 1.0, info, s);
+        if (rc) return rc;
+        const int64_t rest = b - s0 - bs;
+        if (rest > 0) {
+            // X_t -= U(s, t)^H X_s for the rows of the blocks below
+            const int64_t ust = (k + s0) + (k + s0 + bs) * ld;
+            const int64_t xt = (k + s0 + bs) + c0 * ld;
+            rc = zgemm_h(false, rest, m, bs, w.R + ust, w.I + ust, ld, w.R + xs, w.I + xs, ld, w.R + xt, w.I + xt,
+                         ld, w.Pn, info, s);
+            if (rc) return rc;
+        }
+    }
+    return FLAME_OK;
+}
+
+// Chol of the n x n diagonal block at (k, k) of the planes, by the loop at
+// block nb (<= kZB: the LDS kernel).
+int zpotrf_block(const ZWork &w, int64_t k, int64_t n, int64_t nb, int32_t *info, int64_t info_base,
+                 hipStream_t s) {
+    const int64_t ld = w.ld;
+    if (n <= kZB) return launch_zchol_lds((int)n, w.R + k + k * ld, w.I + k + k * ld, ld, info, info_base, s);
+    for (int64_t k0 = 0; k0 < n; k0 += nb) {
+        const int64_t bk = std::min<int64_t>(nb, n - k0);
+        const int64_t m = n - k0 - bk;
+        int rc = zpotrf_block(w, k + k0, bk, kZB, info, info_base + k0, s);
+        if (rc) return rc;
+        if (m == 0) break;
+        rc = ztrsm(w, k + k0, bk, k + k0 + bk, m, info, s);
+        if (rc) return rc;
+        // A22 -= A12^H A12 (upper)
+        const int64_t a12 = (k + k0) + (k + k0 + bk) * ld, a22 = (k + k0 + bk) + (k + k0 + bk) * ld;
+        rc = zgemm_h(true, m, m, bk, w.R + a12, w.I + a12, ld, w.R + a12, w.I + a12, ld, w.R + a22, w.I + a22, ld,
+                     w.Pn, info, s);
+        if (rc) return rc;
+    }
+    return FLAME_OK;
+}
+
+}  // namespace
+
+int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t s) {
+    int rc = launch_zero_i32(info, 1, s);
+    if (rc || n == 0) return rc;
+    nb = std::max(kZB, std::min(nb, 512)) / kZB * kZB;
+    DevCtx *ctx = ctx_for_current_device();
+    if (ctx == nullptr) return FLAME_ERR_HIP;
+    const size_t plane = (size_t)n * (size_t)n;
+    const size_t doubles = 2 * plane + 2 * (size_t)kZB * (size_t)n + (size_t)nb * (size_t)n + 2 * kZB * kZB;
+    void *ws = nullptr;
+    rc = ctx_workspace(ctx, kWsComplex, doubles * sizeof(double), &ws);
+    if (rc) return rc;
+    double *p = static_cast<double *>(ws);
+    ZWork w;
+    w.R = p;
+    w.I = p + plane;
+    w.ld = n;
+    w.Tr = p + 2 * plane;
+    w.Ti = w.Tr + (size_t)kZB * n;
+    w.Pn = w.Ti + (size_t)kZB * n;
+    w.Vr = w.Pn + (size_t)nb * n;
+    w.Vi = w.Vr + kZB * kZB;
+    rc = launch_z_split(n, A, lda, w.R, w.I, n, s);
+    if (!rc) rc = zpotrf_block(w, 0, n, nb, info, 0, s);
+    if (!rc) rc = launch_z_merge(n, w.R, w.I, n, A, lda, s);
+    return rc;
+}
+
+}  // namespace flame

@@ -77,6 +77,20 @@ def test_factor_unsupported_mixed_combinations():
     assert fl.lib().flame_factor(0, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == fl.FLAME_ERR_UNSUPPORTED
 
 
+def test_factor_complex_checks():
+    """dtype FLAME_Z64 (complex): the right-looking loop at native precision
+    only; option fields are checked as for the real dtypes, before any device
+    call."""
+    for kw in ({"variant": 1}, {"variant": 2}, {"variant": 4}, {"trail": 1}, {"trail": 2}):
+        o = _opts(**kw)
+        assert fl.lib().flame_factor(fl.Z64, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == fl.FLAME_ERR_UNSUPPORTED
+    for field, value in (("variant", 9), ("nb", 513), ("graph", 5), ("flags", 4)):
+        o = _opts(**{field: value})
+        assert fl.lib().flame_factor(fl.Z64, 4, FAKE, 4, ctypes.byref(o), FAKE, None) == -5
+    assert fl.lib().flame_factor(fl.Z64, 4, FAKE, 3, None, FAKE, None) == -4
+    assert fl.lib().flame_factor(3, 4, FAKE, 4, None, FAKE, None) == -1
+
+
 def test_solve_argument_errors():
     L = fl.lib()
     assert L.flame_solve(3, 4, 1, FAKE, 4, FAKE, 4, None, None, None) == -1
