@@ -86,6 +86,26 @@ def hpd_exact(n: int, seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
     return np.asfortranarray(A), np.asfortranarray(U)
 
 
+def diag_dominant(n: int, seed: int = 0) -> np.ndarray:
+    """Nonsymmetric A = G + 2 (n + 1) I, G ~ N(0,1) from PCG64(seed):
+    diagonally dominant by columns (the off-diagonal column sums of |G| stay
+    near 0.8 n), so partial pivoting keeps every diagonal pivot and the LU
+    without pivoting is the one LAPACK computes.  Fortran-ordered."""
+    G = gaussian(n, n, seed)
+    return np.asfortranarray(G + float(n + 1) * np.eye(n) * 2.0)
+
+
+def lu_exact(n: int, seed: int = 0) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """(A, L, U) with A = L U exactly in binary64: L unit lower triangular and U
+    upper triangular with small integer entries, U's diagonal powers of two,
+    so every step of the unblocked LU without pivoting is exact."""
+    g = _rng(seed)
+    L = np.tril(g.integers(-2, 3, (n, n)), -1).astype(np.float64) + np.eye(n)
+    U = np.triu(g.integers(-2, 3, (n, n))).astype(np.float64)
+    U[np.diag_indices(n)] = 2.0 ** g.integers(0, 3, n)
+    return np.asfortranarray(L @ U), L, U
+
+
 def spd_bbt_torch(n: int, seed: int, device):
     """Same recipe as spd_bbt, with the product B B^T formed by torch on
     ``device`` (fast at n = 16384).  The bytes can differ from spd_bbt in the

@@ -49,6 +49,8 @@ def load(path: str) -> ctypes.CDLL:
         L.oracle_ichol_rows.restype = i32
         L.oracle_zpotrf_upper.argtypes = [i64, dp, i64]
         L.oracle_zpotrf_upper.restype = i32
+        L.oracle_getrf_nopiv.argtypes = [i64, dp, i64]
+        L.oracle_getrf_nopiv.restype = i32
     return L
 
 
@@ -107,6 +109,24 @@ def zpotrf(A: np.ndarray) -> tuple[np.ndarray, int]:
     n = W.shape[0]
     info = lib().oracle_zpotrf_upper(n, _ptr(W), max(1, n))
     return W, int(info)
+
+
+def getrf_nopiv(A: np.ndarray) -> tuple[np.ndarray, int]:
+    """O9: LU without pivoting, A = L U, on a copy of A: the strictly lower
+    triangle receives L (unit diagonal implied), the upper triangle U.
+    Returns (A_out, info); info = first zero or non-finite pivot (1-based)."""
+    W = np.array(_fortran(A), dtype=np.float64, order="F", copy=True)
+    n = W.shape[0]
+    info = lib().oracle_getrf_nopiv(n, _ptr(W), max(1, n))
+    return W, int(info)
+
+
+def lu_backward_error(A: np.ndarray, W: np.ndarray) -> float:
+    """||A - L U||_F / ||A||_F for the packed factors W of :func:`getrf_nopiv`."""
+    n = W.shape[0]
+    L = np.tril(W, -1) + np.eye(n)
+    U = np.triu(W)
+    return float(np.linalg.norm(A - L @ U) / np.linalg.norm(A))
 
 
 def zfactor_backward_error(A: np.ndarray, U: np.ndarray) -> float:

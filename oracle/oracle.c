@@ -461,3 +461,31 @@ int oracle_zpotrf_upper(int64_t n, double *A, int64_t lda) {
     }
     return 0;
 }
+
+/*
+ * O9 -- LU factorization without pivoting, A = L U (L unit lower triangular,
+ * U upper triangular), in place: the same partitioned loop as the Cholesky
+ * loop of Fig. "dense-chol" (the conclusion names LU among the factorizations
+ * the by-blocks pattern carries over to), at b = 1.  Step j, with
+ * alpha11 = A(j,j), a21 = A(j+1:n, j), a12 = A(j, j+1:n):
+ *   a21 := a21 / alpha11          (the column of L below its unit diagonal)
+ *   A22 := A22 - a21 a12          (each product rounded, then subtracted)
+ * alpha11 and a12 are final as they stand (the row of U).  Breakdown (no
+ * pivoting: the paper does not treat it): the first pivot that is zero or not
+ * finite stops the loop and returns its 1-based column.  Returns 0 on success.
+ */
+int oracle_getrf_nopiv(int64_t n, double *A, int64_t lda) {
+    for (int64_t j = 0; j < n; ++j) {
+        double piv = AT(A, lda, j, j);
+        if (piv == 0.0 || !isfinite(piv)) return (int)(j + 1);
+        for (int64_t r = j + 1; r < n; ++r) AT(A, lda, r, j) = AT(A, lda, r, j) / piv;
+        for (int64_t c = j + 1; c < n; ++c) {
+            double ujc = AT(A, lda, j, c);
+            for (int64_t r = j + 1; r < n; ++r) {
+                double q = AT(A, lda, r, j) * ujc;
+                AT(A, lda, r, c) = AT(A, lda, r, c) - q;
+            }
+        }
+    }
+    return 0;
+}
