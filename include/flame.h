@@ -141,6 +141,23 @@ typedef struct {
 int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opts_t *opts, int32_t *info,
                  void *stream);
 
+/* LU factorization without pivoting, A = L U, in place (L unit lower
+ * triangular in the strictly lower triangle, U upper triangular in the upper
+ * triangle): the partitioned loop of Fig. "dense-chol" carried over to LU,
+ * which the paper's conclusion names among the factorizations its pattern
+ * extends to,
+ *   A11 := L\U(A11);  A12 := L11^{-1} A12;  A21 := A21 U11^{-1};
+ *   A22 := A22 - A21 A12,
+ * right-looking at block 64.  No row interchanges: meant for matrices whose
+ * LU exists without them (diagonally dominant ones, say).
+ *   dtype  FLAME_F64 (FLAME_ERR_UNSUPPORTED for FLAME_F32)
+ *   n, A, lda, stream as for flame_factor
+ *   info   device, one int32: 0, or the 1-based column of the first pivot
+ *          that is zero or not finite (A then holds a partial result)
+ * Device workspace of O(64 n) doubles, allocated on the first call and kept.
+ * Errors: -1 dtype, -2 n, -3 A, -4 lda, -5 info. */
+int flame_lu(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, void *stream);
+
 /* Cholesky-by-blocks (Fig. "sparse-chol" of the paper, the by-blocks form of
  * the loop of Fig. "dense-chol") over 128 x 128 blocks, run as a task DAG by
  * one persistent kernel.  For iteration k the block operations are

@@ -42,7 +42,7 @@ EXPORTS = (
     "flame_solve_mixed", "flame_shutdown", "flame_batched_factor_noalloc", "flame_trace_busy", "flame_probe",
     "flame_select_class", "flame_factor_by_blocks", "flame_by_blocks_tasks",
     "flame_ichol_analyze", "flame_ichol_stats", "flame_ichol_structure", "flame_ichol_factor", "flame_ichol_values",
-    "flame_ichol_destroy", "flame_ichol_apply", "flame_ichol_pcg",
+    "flame_ichol_destroy", "flame_ichol_apply", "flame_ichol_pcg", "flame_lu",
 )
 PROBE = {"mfma_f64": 0, "mfma_f32": 1, "mfma_bf16": 2, "copy": 3}
 NOALLOC_MAX_BATCH = 262144
@@ -121,6 +121,7 @@ def lib(path: str | None = None) -> ctypes.CDLL:
     L = ctypes.CDLL(path)
     i32, i64, vp, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
     L.flame_factor.argtypes = [i32, i64, vp, i64, ctypes.POINTER(Opts), vp, vp]
+    L.flame_lu.argtypes = [i32, i64, vp, i64, vp, vp]
     L.flame_solve.argtypes = [i32, i64, i64, vp, i64, vp, i64, ctypes.POINTER(Refine),
                               ctypes.POINTER(SolveReport), vp]
     L.flame_batched_factor.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.POINTER(Opts), vp]
@@ -259,6 +260,25 @@ def factor(A, variant: int = VAR_RIGHT, nb: int = 128, trail="native", lookahead
         o.flags |= OPT_LOWER
     rc = lib().flame_factor(_dtype_code(A), n, A.data_ptr(), lda, ctypes.byref(o), info.data_ptr(), _stream_ptr())
     _check("flame_factor", rc)
+    return info
+
+
+def lu(A, info=None):
+    """A := L\\U in place, LU without pivoting (flame_lu; FP64, column-major
+    device tensor).  Returns the device int32 ``info`` (0, or the 1-based
+    column of the first zero or non-finite pivot).  Asynchronous on the
+    current stream."""
+    torch = _torch()
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a square 2-D tensor")
+    if A.dtype != torch.float64:
+        raise TypeError("flame_lu takes float64")
+    n = A.shape[0]
+    lda = _colmajor_ld(A)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rc = lib().flame_lu(F64, n, A.data_ptr(), lda, info.data_ptr(), _stream_ptr())
+    _check("flame_lu", rc)
     return info
 
 

@@ -95,6 +95,16 @@ int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opt
                               : launch_swap_triangles<float>(n, static_cast<float *>(A), lda, s);
 }
 
+int flame_lu(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, void *stream) {
+    if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
+    if (n < 0 || n > ((int64_t)1 << 31) - 1) return -2;
+    if (A == nullptr && n > 0) return -3;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (info == nullptr) return -5;
+    if (dtype != FLAME_F64) return FLAME_ERR_UNSUPPORTED;
+    return lu_factor(n, static_cast<double *>(A), lda, info, as_stream(stream));
+}
+
 int flame_op_chol(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, int64_t info_base, void *stream) {
     if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
     if (n < 0 || n > kMaxBlockOp) return -2;

@@ -185,6 +185,17 @@ int launch_ztrinv_lds(int n, const double *R, const double *I, int64_t ld, doubl
 // The complex factorization of flame_factor (dtype FLAME_Z64), upper storage.
 int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t s);
 
+// ---- LU without pivoting (k_lu.hip, lu.cpp) ---------------------------------
+// Diagonal block (n <= 64) := L\U in place; on a zero or non-finite pivot
+// *info = info_base + column.  P1 := -(L^{-1})^T, P2 := -U^{-1} (n x n, ld 64)
+// of a factored block.  dst (cols x rows) := src^T.  All skip if *info
+// (the transpose only when info is given).
+int launch_lu_lds(int n, double *A, int64_t lda, int32_t *info, int64_t info_base, hipStream_t s);
+int launch_lu_inv(int n, const double *A, int64_t lda, double *P1, double *P2, const int32_t *info, hipStream_t s);
+int launch_transpose_copy(int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst, int64_t ldd,
+                          const int32_t *info, hipStream_t s);
+int lu_factor(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s);
+
 // ---- selector --------------------------------------------------------------
 int launch_selector(const float *w, const float *feat, int64_t count, float *logits, hipStream_t s);
 
@@ -203,7 +214,8 @@ enum {
     kWsMixed = 6,
     kWsDag = 7,
     kWsComplex = 8,
-    kWsSlots = 9
+    kWsLu = 9,
+    kWsSlots = 10
 };
 int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out);
 // Generation of a slot's buffer: changes every time ctx_workspace replaces it

@@ -91,6 +91,16 @@ def test_factor_complex_checks():
     assert fl.lib().flame_factor(3, 4, FAKE, 4, None, FAKE, None) == -1
 
 
+def test_lu_argument_errors():
+    L = fl.lib()
+    assert L.flame_lu(7, 4, FAKE, 4, FAKE, None) == -1
+    assert L.flame_lu(0, -1, FAKE, 4, FAKE, None) == -2
+    assert L.flame_lu(0, 4, None, 4, FAKE, None) == -3
+    assert L.flame_lu(0, 4, FAKE, 3, FAKE, None) == -4
+    assert L.flame_lu(0, 4, FAKE, 4, None, None) == -5
+    assert L.flame_lu(1, 4, FAKE, 4, FAKE, None) == fl.FLAME_ERR_UNSUPPORTED
+
+
 def test_solve_argument_errors():
     L = fl.lib()
     assert L.flame_solve(3, 4, 1, FAKE, 4, FAKE, 4, None, None, None) == -1
