@@ -70,6 +70,12 @@ def main() -> int:
     ap.add_argument("--ichol", action="store_true",
                     help="instead of the default run: level(k) incomplete Cholesky-by-blocks (flame_ichol_*) on "
                          "grid Laplacians, with the oracle's sequential incomplete factor timed beside it")
+    ap.add_argument("--extensions", action="store_true",
+                    help="instead of the default run: the complex Hermitian factorization (flame_factor, "
+                         "complex128) and the LU without pivoting (flame_lu) at the orders of --ext-ns, with the "
+                         "oracle's unblocked loops timed beside them at --ext-oracle-n")
+    ap.add_argument("--ext-ns", default="2048,4096,8192")
+    ap.add_argument("--ext-oracle-n", type=int, default=1024)
     ap.add_argument("--table-ns", default="4096,8192,16384")
     ap.add_argument("--table-nbs", default="64,128,256")
     ap.add_argument("--table-seeds", default="0,1,2")
@@ -101,6 +107,8 @@ def main() -> int:
         return dag_mode(args, dev, fl, inputs, torch)
     if args.ichol:
         return ichol_mode(args, dev, fl, inputs, torch)
+    if args.extensions:
+        return extensions_mode(args, dev, fl, inputs, torch)
     if args.copy_probe_gib > 0:
         words = int(args.copy_probe_gib * (1 << 30)) // 8
         src = torch.ones(words, dtype=torch.float64, device=dev)
@@ -528,6 +536,82 @@ def dag_mode(args, dev, fl, inputs, torch) -> int:
         print(json.dumps(rec), flush=True)
         del P, W, U
         torch.cuda.empty_cache()
+    return 0
+
+
+def extensions_mode(args, dev, fl, inputs, torch) -> int:
+    """The loop's extensions the paper's conclusion lists: the complex
+    Hermitian factorization A = U^H U (flame_factor on complex128, 4 n^3 / 3
+    real flops) and the LU without pivoting (flame_lu, 2 n^3 / 3 flops), each
+    the median of --steps runs after --warmup on a resident seeded matrix
+    (B B^H + n I, complex Gaussian B; G + 2 (n + 1) I, Gaussian G) restored
+    outside the timed region, with the backward error of the last run; beside
+    them the oracle's unblocked loops (O8, O9; one host thread) at
+    --ext-oracle-n, one run each.  One JSON line per case."""
+    import time
+
+    import oracle
+
+    stream = torch.cuda.current_stream()
+
+    def timed(P, fn, check):
+        W = torch.empty_like(P)
+        ts = []
+        for r in range(args.warmup + args.steps):
+            W.copy_(P)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            info = fn(W)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if int(info.item()) != 0:
+                raise RuntimeError("breakdown")
+            if r >= args.warmup:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)), check(P, W)
+
+    def herm_err(P, W):
+        U = torch.triu(W)
+        return float(torch.linalg.norm(P - U.conj().T @ U) / torch.linalg.norm(P))
+
+    def lu_err(P, W):
+        n = W.shape[0]
+        L = torch.tril(W, -1) + torch.eye(n, dtype=W.dtype, device=W.device)
+        return float(torch.linalg.norm(P - L @ torch.triu(W)) / torch.linalg.norm(P))
+
+    for n in [int(v) for v in args.ext_ns.split(",") if v]:
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed)
+        B = torch.randn(n, n, dtype=torch.complex128, device=dev, generator=g)
+        P = B @ B.conj().T
+        P.diagonal().copy_(P.diagonal().real + n)
+        P = (torch.triu(P) + torch.triu(P, 1).conj().T).mT.contiguous().mT
+        ms, err = timed(P, lambda W: fl.factor(W, variant=fl.VAR_RIGHT, nb=128), herm_err)
+        print(json.dumps({"case": "complex_hermitian", "n": n, "ms": round(ms, 3),
+                          "tflops": round(4 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "backward_error": err}),
+              flush=True)
+        del B, P
+        G = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
+        P = (G + 2.0 * (n + 1) * torch.eye(n, dtype=torch.float64, device=dev)).mT.contiguous().mT
+        ms, err = timed(P, lambda W: fl.lu(W), lu_err)
+        print(json.dumps({"case": "lu_nopiv", "n": n, "ms": round(ms, 3),
+                          "tflops": round(2 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "backward_error": err}),
+              flush=True)
+        del G, P
+        torch.cuda.empty_cache()
+    if not args.no_cpu:
+        n = args.ext_oracle_n
+        A = inputs.hpd_bbh(n, args.seed)
+        t0 = time.perf_counter()
+        oracle.zpotrf(A)
+        t_z = time.perf_counter() - t0
+        A = inputs.diag_dominant(n, args.seed)
+        t0 = time.perf_counter()
+        oracle.getrf_nopiv(A)
+        t_l = time.perf_counter() - t0
+        print(json.dumps({"case": "oracle", "n": n, "cores": 1, "complex_hermitian_s": round(t_z, 3),
+                          "lu_nopiv_s": round(t_l, 3)}), flush=True)
     return 0
 
 

@@ -114,16 +114,19 @@ __global__ __launch_bounds__(256) void k_zchol_lds(int n, double *__restrict__ R
 
 // V := -U^{-1} for the n x n (n <= 64) upper triangular U in the planes
 // (real diagonal), into the planes Vr, Vi (ldv), zero below the diagonal:
-// thread t solves U v = e_t by back substitution, v in LDS.  Skips if
-// *info != 0.
-__global__ __launch_bounds__(64) void k_ztrinv_lds(int n, const double *__restrict__ R, const double *__restrict__ I,
-                                                   int64_t ld, double *__restrict__ Vr, double *__restrict__ Vi,
-                                                   int64_t ldv, const int32_t *__restrict__ info) {
+// column t of U^{-1} by back substitution, U v = e_t, row by row from the
+// last; the sum over k of each row is split over four threads (k mod 4) and
+// combined after a barrier.  256 threads; U, the columns and the partial
+// sums in LDS.  Skips if *info != 0.
+__global__ __launch_bounds__(256) void k_ztrinv_lds(int n, const double *__restrict__ R, const double *__restrict__ I,
+                                                    int64_t ld, double *__restrict__ Vr, double *__restrict__ Vi,
+                                                    int64_t ldv, const int32_t *__restrict__ info) {
     __shared__ double ur[kZ][kZ + 1], ui[kZ][kZ + 1];  // [column][row]
     __shared__ double vr[kZ][kZ + 1], vi[kZ][kZ + 1];  // [column t][row]
+    __shared__ double pr[4][kZ], pi[4][kZ];             // partial sums [k mod 4][column]
     if (*info != 0) return;
-    const int t = threadIdx.x;
-    for (int e = t; e < kZ * kZ; e += kZ) {
+    const int tid = threadIdx.x, t = tid & (kZ - 1), q = tid >> 6;
+    for (int e = tid; e < kZ * kZ; e += 256) {
         const int i = e & (kZ - 1), j = e >> 6;
         if (i <= j && j < n) {
             ur[j][i] = R[i + (int64_t)j * ld];
@@ -131,26 +134,33 @@ __global__ __launch_bounds__(64) void k_ztrinv_lds(int n, const double *__restri
         }
     }
     __syncthreads();
-    if (t < n) {
-        for (int i = n - 1; i >= 0; --i) {
-            double ar = (i == t) ? 1.0 : 0.0, ai = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+        double sr = 0.0, si = 0.0;
+        if (t < n && i <= t) {
+            for (int k = i + 1 + q; k <= t; k += 4) {
+                sr += ur[k][i] * vr[t][k] - ui[k][i] * vi[t][k];
+                si += ur[k][i] * vi[t][k] + ui[k][i] * vr[t][k];
+            }
+        }
+        pr[q][t] = sr;
+        pi[q][t] = si;
+        __syncthreads();
+        if (q == 0 && t < n) {
+            double ar = 0.0, ai = 0.0;
             if (i <= t) {
-                for (int k = i + 1; k <= t; ++k) {
-                    const double pr = ur[k][i], pi = ui[k][i], qr = vr[t][k], qi = vi[t][k];
-                    ar -= pr * qr - pi * qi;
-                    ai -= pr * qi + pi * qr;
-                }
                 const double d = ur[i][i];  // real diagonal
-                ar /= d;
-                ai /= d;
+                ar = (((i == t) ? 1.0 : 0.0) - ((pr[0][t] + pr[1][t]) + (pr[2][t] + pr[3][t]))) / d;
+                ai = (0.0 - ((pi[0][t] + pi[1][t]) + (pi[2][t] + pi[3][t]))) / d;
             }
             vr[t][i] = ar;
             vi[t][i] = ai;
         }
-        for (int i = 0; i < n; ++i) {
-            Vr[i + (int64_t)t * ldv] = -vr[t][i];
-            Vi[i + (int64_t)t * ldv] = -vi[t][i];
-        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += 256) {
+        const int i = e % n, c = e / n;
+        Vr[i + (int64_t)c * ldv] = -vr[c][i];
+        Vi[i + (int64_t)c * ldv] = -vi[c][i];
     }
 }
 
@@ -200,7 +210,7 @@ int launch_ztrinv_lds(int n, const double *R, const double *I, int64_t ld, doubl
                       const int32_t *info, hipStream_t s) {
     if (n <= 0) return FLAME_OK;
     if (n > kZ) return FLAME_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(k_ztrinv_lds, dim3(1), dim3(kZ), 0, s, n, R, I, ld, Vr, Vi, ldv, info);
+    hipLaunchKernelGGL(k_ztrinv_lds, dim3(1), dim3(256), 0, s, n, R, I, ld, Vr, Vi, ldv, info);
     FLAME_CHECK_LAUNCH();
     return FLAME_OK;
 }

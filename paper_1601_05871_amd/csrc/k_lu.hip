@@ -55,40 +55,56 @@ __global__ __launch_bounds__(256) void k_lu_lds(int n, double *__restrict__ A, i
 // For the factored n x n block (L\U): P1 := -(L^{-1})^T and P2 := -U^{-1}
 // (n x n each, ld kL, zero outside the triangles), so that the
 // trailing-update kernel's C -= X^T Y gives C + L^{-1} Y with X = P1 and
-// C + U^{-T} Y with X = P2.  Thread t forms column t of L^{-1} (forward
-// substitution, unit diagonal) and of U^{-1} (back substitution) in LDS.
-__global__ __launch_bounds__(64) void k_lu_inv(int n, const double *__restrict__ A, int64_t lda,
-                                               double *__restrict__ P1, double *__restrict__ P2,
-                                               const int32_t *__restrict__ info) {
+// C + U^{-T} Y with X = P2.  512 threads: the first 256 form the columns of
+// L^{-1} (forward substitution, L w = e_t, unit diagonal), the others those
+// of U^{-1} (back substitution, U v = e_t), both row by row in lockstep, the
+// sum over k of each row split over four threads (k mod 4) and combined after
+// a barrier.  The block, the columns and the partial sums in LDS.
+__global__ __launch_bounds__(512) void k_lu_inv(int n, const double *__restrict__ A, int64_t lda,
+                                                double *__restrict__ P1, double *__restrict__ P2,
+                                                const int32_t *__restrict__ info) {
     __shared__ double a[kL][kL + 1];   // [column][row]
     __shared__ double w[kL][kL + 1];   // [column t][row] of L^{-1}
     __shared__ double v[kL][kL + 1];   // [column t][row] of U^{-1}
+    __shared__ double part[2][4][kL];  // partial sums [triangle][k mod 4][column]
     if (*info != 0) return;
-    const int t = threadIdx.x;
-    for (int e = t; e < kL * kL; e += kL) {
+    const int tid = threadIdx.x, t = tid & (kL - 1), q = (tid >> 6) & 3, up = tid >> 8;
+    for (int e = tid; e < kL * kL; e += 512) {
         const int i = e & (kL - 1), j = e >> 6;
         if (i < n && j < n) a[j][i] = A[i + (int64_t)j * lda];
     }
     __syncthreads();
-    if (t < n) {
-        for (int i = 0; i < n; ++i) {  // L w = e_t
-            double s = (i == t) ? 1.0 : 0.0;
-            if (i > t)
-                for (int k = t; k < i; ++k) s -= a[k][i] * w[t][k];
-            w[t][i] = (i >= t) ? s : 0.0;
-        }
-        for (int i = n - 1; i >= 0; --i) {  // U v = e_t
-            double s = (i == t) ? 1.0 : 0.0;
-            if (i <= t) {
-                for (int k = i + 1; k <= t; ++k) s -= a[k][i] * v[t][k];
-                s /= a[i][i];
+    for (int step = 0; step < n; ++step) {
+        double s = 0.0;
+        if (t < n) {
+            if (!up) {  // row i of L w = e_t: w_i = delta - sum_{t <= k < i} L(i, k) w_k
+                const int i = step;
+                if (i > t)
+                    for (int k = t + q; k < i; k += 4) s += a[k][i] * w[t][k];
+            } else {  // row i of U v = e_t: v_i = (delta - sum_{i < k <= t} U(i, k) v_k) / U(i, i)
+                const int i = n - 1 - step;
+                if (i <= t)
+                    for (int k = i + 1 + q; k <= t; k += 4) s += a[k][i] * v[t][k];
             }
-            v[t][i] = s;
         }
-        for (int i = 0; i < n; ++i) {
-            P1[t + (int64_t)i * kL] = -w[t][i];  // P1(t, i) = -W(i, t)
-            P2[i + (int64_t)t * kL] = -v[t][i];  // P2(i, t) = -V(i, t)
+        part[up][q][t] = s;
+        __syncthreads();
+        if (q == 0 && t < n) {
+            const double sum = (part[up][0][t] + part[up][1][t]) + (part[up][2][t] + part[up][3][t]);
+            if (!up) {
+                const int i = step;
+                w[t][i] = (i < t) ? 0.0 : (((i == t) ? 1.0 : 0.0) - sum);
+            } else {
+                const int i = n - 1 - step;
+                v[t][i] = (i > t) ? 0.0 : (((i == t) ? 1.0 : 0.0) - sum) / a[i][i];
+            }
         }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += 512) {
+        const int i = e % n, c = e / n;
+        P1[c + (int64_t)i * kL] = -w[c][i];  // P1(c, i) = -W(i, c)
+        P2[i + (int64_t)c * kL] = -v[c][i];  // P2(i, c) = -V(i, c)
     }
 }
 
@@ -125,7 +141,7 @@ int launch_lu_lds(int n, double *A, int64_t lda, int32_t *info, int64_t info_bas
 int launch_lu_inv(int n, const double *A, int64_t lda, double *P1, double *P2, const int32_t *info, hipStream_t s) {
     if (n <= 0) return FLAME_OK;
     if (n > kL) return FLAME_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(k_lu_inv, dim3(1), dim3(kL), 0, s, n, A, lda, P1, P2, info);
+    hipLaunchKernelGGL(k_lu_inv, dim3(1), dim3(512), 0, s, n, A, lda, P1, P2, info);
     FLAME_CHECK_LAUNCH();
     return FLAME_OK;
 }
