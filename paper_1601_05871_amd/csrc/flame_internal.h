@@ -182,6 +182,11 @@ int launch_fill0(int64_t rows, int64_t cols, double *dst, int64_t ldd, hipStream
 int launch_zchol_lds(int n, double *R, double *I, int64_t ld, int32_t *info, int64_t info_base, hipStream_t s);
 int launch_ztrinv_lds(int n, const double *R, const double *I, int64_t ld, double *Vr, double *Vi, int64_t ldv,
                       const int32_t *info, hipStream_t s);
+// C -= P^H Q on planes in one matrix-core pass (P K x M, Q K x N, C M x N;
+// upper: i <= j only).  Skips if *info.
+int launch_zgemm_h(bool upper, int64_t M, int64_t N, int64_t K, const double *Pr, const double *Pi, int64_t ldp,
+                   const double *Qr, const double *Qi, int64_t ldq, double *Cr, double *Ci, int64_t ldc,
+                   const int32_t *info, hipStream_t s);
 // The complex factorization of flame_factor (dtype FLAME_Z64), upper storage.
 int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t s);
 

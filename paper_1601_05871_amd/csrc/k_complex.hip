@@ -164,6 +164,91 @@ __global__ __launch_bounds__(256) void k_ztrinv_lds(int n, const double *__restr
     }
 }
 
+typedef double zd4 __attribute__((ext_vector_type(4)));
+
+// acc += x^T y over one k slot: lane (r, g) of the result holds element
+// (r, g + 4 v) of the 16 x 16 block in item v, r from x's columns (C's rows),
+// g + 4 v from y's columns.
+__device__ __forceinline__ zd4 zmma(double x, double y, zd4 acc) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(y, x, acc, 0, 0, 0);
+}
+
+// C -= P^H Q on planes, in one pass: per k slot the four real products
+//   C_re -= Pr^T Qr + Pi^T Qi,   C_im -= Pr^T Qi - Pi^T Qr
+// share the operands each lane loads.  P is K x M (ldp), Q is K x N (ldq),
+// C is M x N (ldc).  A workgroup takes a 64 x 64 tile of C, each wavefront
+// 32 x 32 of it (2 x 2 blocks of 16 x 16, real and imaginary accumulators);
+// operands straight from global memory, k = kc + 4 g + t in step t of a
+// 16-k chunk, rows, columns and k beyond the matrices clamped or zeroed.
+// upper: only i <= j of C is written (tiles entirely below skipped).
+// Skips if *info != 0.
+__global__ __launch_bounds__(256) void k_zgemm_h(int64_t M, int64_t N, int64_t K, const double *__restrict__ Pr,
+                                                 const double *__restrict__ Pi, int64_t ldp,
+                                                 const double *__restrict__ Qr, const double *__restrict__ Qi,
+                                                 int64_t ldq, double *__restrict__ Cr, double *__restrict__ Ci,
+                                                 int64_t ldc, int upper, const int32_t *__restrict__ info) {
+    if (*info != 0) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * 64 + (wave >> 1) * 32;
+    const int64_t col0 = (int64_t)blockIdx.y * 64 + (wave & 1) * 32;
+    if (row0 >= M || col0 >= N) return;
+    if (upper && row0 > col0 + 31) return;
+    zd4 are[2][2], aim[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) are[a][b] = aim[a][b] = zd4{0.0, 0.0, 0.0, 0.0};
+    const double *pr[2], *pi[2], *qr[2], *qi[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int64_t pc = min(row0 + 16 * a + r, M - 1), qc = min(col0 + 16 * a + r, N - 1);
+        pr[a] = Pr + pc * ldp;
+        pi[a] = Pi + pc * ldp;
+        qr[a] = Qr + qc * ldq;
+        qi[a] = Qi + qc * ldq;
+    }
+    for (int64_t kc = 0; kc < K; kc += 16) {
+        double xr[2][4], xi[2][4], yr[2][4], yi[2][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t k = kc + 4 * g + t;
+            const bool ok = k < K;
+            const int64_t kk = ok ? k : K - 1;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                xr[a][t] = ok ? -pr[a][kk] : 0.0;
+                xi[a][t] = ok ? pi[a][kk] : 0.0;
+                yr[a][t] = qr[a][kk];
+                yi[a][t] = qi[a][kk];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    are[a][b] = zmma(xr[a][t], yr[b][t], are[a][b]);   // - Pr^T Qr
+                    are[a][b] = zmma(-xi[a][t], yi[b][t], are[a][b]);  // - Pi^T Qi
+                    aim[a][b] = zmma(xr[a][t], yi[b][t], aim[a][b]);   // - Pr^T Qi
+                    aim[a][b] = zmma(xi[a][t], yr[b][t], aim[a][b]);   // + Pi^T Qr
+                }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = row0 + 16 * a + r, j = col0 + 16 * b + g + 4 * v;
+                if (i < M && j < N && (!upper || i <= j)) {
+                    Cr[i + j * ldc] += are[a][b][v];
+                    Ci[i + j * ldc] += aim[a][b][v];
+                }
+            }
+}
+
 unsigned cols_grid(int64_t cols) { return (unsigned)std::max<int64_t>(1, cols); }
 
 }  // namespace
@@ -194,6 +279,17 @@ int launch_scaled_copy(int64_t rows, int64_t cols, const double *src, int64_t ld
 int launch_fill0(int64_t rows, int64_t cols, double *dst, int64_t ldd, hipStream_t s) {
     if (rows <= 0 || cols <= 0) return FLAME_OK;
     hipLaunchKernelGGL(k_fill0, dim3(cols_grid(cols)), dim3(256), 0, s, rows, dst, ldd);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int launch_zgemm_h(bool upper, int64_t M, int64_t N, int64_t K, const double *Pr, const double *Pi, int64_t ldp,
+                   const double *Qr, const double *Qi, int64_t ldq, double *Cr, double *Ci, int64_t ldc,
+                   const int32_t *info, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return FLAME_OK;
+    const dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64));
+    hipLaunchKernelGGL(k_zgemm_h, grid, dim3(256), 0, s, M, N, K, Pr, Pi, ldp, Qr, Qi, ldq, Cr, Ci, ldc,
+                       upper ? 1 : 0, info);
     FLAME_CHECK_LAUNCH();
     return FLAME_OK;
 }

@@ -35,11 +35,16 @@ struct ZWork {
 };
 
 // C -= P^H Q; P is K x M (ldp), Q is K x N (ldq), C is M x N (ldc), each given
-// by its planes.  upper: only i <= j of C is written (the HERK).
+// by its planes.  upper: only i <= j of C is written (the HERK: four real
+// products on the LDS-staged trailing-update kernel); otherwise the fused
+// complex product k_zgemm_h.
 int zgemm_h(bool upper, int64_t M, int64_t N, int64_t K, const double *Pr, const double *Pi, int64_t ldp,
             const double *Qr, const double *Qi, int64_t ldq, double *Cr, double *Ci, int64_t ldc, double *Pn,
             const int32_t *info, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return FLAME_OK;
+    // the panel solve's products (at most nb rows of C): one fused pass,
+    // the four real products sharing their operand loads
+    if (!upper) return launch_zgemm_h(false, M, N, K, Pr, Pi, ldp, Qr, Qi, ldq, Cr, Ci, ldc, info, s);
     int rc = launch_gemm_tn(Prec::F64, true, upper, M, N, K, Pr, ldp, Qr, ldq, Cr, ldc, info, s);
     if (!rc) rc = launch_gemm_tn(Prec::F64, true, upper, M, N, K, Pi, ldp, Qi, ldq, Cr, ldc, info, s);
     if (!rc) rc = launch_gemm_tn(Prec::F64, true, upper, M, N, K, Pr, ldp, Qi, ldq, Ci, ldc, info, s);
