@@ -56,58 +56,78 @@ __global__ __launch_bounds__(256) void k_fill0(int64_t rows, double *__restrict_
 }
 
 // A := Chol(A) for the n x n (n <= 64) diagonal block held in the planes
-// (upper triangle), one workgroup, the block in LDS ([column][row], padded).
-// Step j: pivot re A(j,j) (its imaginary part is not read), row j divided by
-// its square root, then A(i,c) -= conj(U(j,i)) U(j,c) for j < i <= c, the
-// 256 threads on (column, row-group) pairs.  On a pivot that is not > 0 it
-// writes *info = info_base + j + 1 and stops (the planes then hold nothing
-// of this block's result).  Skips if *info != 0 on entry.
+// (upper triangle), one workgroup.  Thread (c, g) (c = tid % 64,
+// g = tid / 64) keeps elements (g + 4 k, c), k < 16, real and imaginary
+// parts, in registers for the whole factorization; step j goes through LDS
+// only for the pivot and row j of U (double-buffered by step parity, two
+// barriers per step): the pivot's owner publishes re A(j,j) (its imaginary
+// part is not read); every thread reads it, row j's owners divide their
+// element by its square root and publish U(j, :); every thread updates its
+// elements (i, c), j < i <= c, with conj(U(j,i)) U(j,c) (selects, no
+// per-element branch).  A pivot that is not > 0: *info = info_base + j + 1
+// and every thread leaves (the planes then hold nothing of this block's
+// result).  Skips if *info != 0 on entry.
 __global__ __launch_bounds__(256) void k_zchol_lds(int n, double *__restrict__ R, double *__restrict__ I, int64_t ld,
                                                    int32_t *__restrict__ info, int64_t info_base) {
-    __shared__ double sr[kZ][kZ + 1], si[kZ][kZ + 1];
+    __shared__ double rowr[2][kZ], rowi[2][kZ], pivb[2];
     if (*info != 0) return;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < kZ * kZ; e += 256) {
-        const int i = e & (kZ - 1), j = e >> 6;
-        if (i <= j && j < n) {
-            sr[j][i] = R[i + (int64_t)j * ld];
-            si[j][i] = I[i + (int64_t)j * ld];
-        }
+    const int tid = threadIdx.x, c = tid & (kZ - 1), g = tid >> 6;
+    double ar[16], ai[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int i = g + 4 * k;
+        const bool in = i <= c && c < n;
+        ar[k] = in ? R[i + (int64_t)c * ld] : 0.0;
+        ai[k] = in ? I[i + (int64_t)c * ld] : 0.0;
     }
-    __syncthreads();
-    const int cl = tid & (kZ - 1), rg = tid >> 6;  // column lane, row group
-    for (int j = 0; j < n; ++j) {
-        const double d = sr[j][j];
-        if (!(d > 0.0)) {  // every thread reads the same pivot: a uniform exit
+    // j = 4 kj + r with kj unrolled: the registers holding row j are
+    // ar[kj], ai[kj], compile-time indices (run-time ones would put the
+    // arrays in scratch)
+#pragma unroll
+    for (int kj = 0; kj < 16; ++kj)
+    for (int r = 0; r < 4; ++r) {
+        const int j = 4 * kj + r;
+        if (j >= n) break;
+        const int b = j & 1;
+        const bool rowown = g == r;
+        if (rowown && c == j) pivb[b] = ar[kj];
+        __syncthreads();
+        const double d = pivb[b];
+        if (!(d > 0.0)) {
             if (tid == 0) *info = (int32_t)(info_base + j + 1);
             return;
         }
-        const double s = sqrt(d);
-        for (int c = j + 1 + tid; c < n; c += 256) {
-            sr[c][j] = sr[c][j] / s;
-            si[c][j] = si[c][j] / s;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            sr[j][j] = s;
-            si[j][j] = 0.0;
-        }
-        const int c = j + 1 + cl;
-        if (c < n) {
-            const double yr = sr[c][j], yi = si[c][j];
-            for (int i = j + 1 + rg; i <= c; i += 4) {
-                const double xr = sr[i][j], xi = si[i][j];
-                sr[c][i] -= xr * yr + xi * yi;
-                si[c][i] -= xr * yi - xi * yr;
+        const double sq = sqrt(d);
+        if (rowown) {  // row j of U: A(j, c) / sqrt(d) for c > j, sqrt(d) on the diagonal
+            const double rs = 1.0 / sq;
+            double ur = ar[kj] * rs, ui = ai[kj] * rs;
+            if (c == j) {
+                ur = sq;
+                ui = 0.0;
             }
+            ar[kj] = (c >= j) ? ur : ar[kj];
+            ai[kj] = (c >= j) ? ui : ai[kj];
+            rowr[b][c] = ur;
+            rowi[b][c] = ui;
         }
         __syncthreads();
+        const double yr = rowr[b][c], yi = rowi[b][c];
+        const bool cu = c > j && c < n;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int i = g + 4 * k;
+            const double xr = rowr[b][i], xi = rowi[b][i];
+            const bool up = cu && i > j && i <= c;
+            ar[k] = up ? ar[k] - (xr * yr + xi * yi) : ar[k];
+            ai[k] = up ? ai[k] - (xr * yi - xi * yr) : ai[k];
+        }
     }
-    for (int e = tid; e < kZ * kZ; e += 256) {
-        const int i = e & (kZ - 1), j = e >> 6;
-        if (i <= j && j < n) {
-            R[i + (int64_t)j * ld] = sr[j][i];
-            I[i + (int64_t)j * ld] = si[j][i];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int i = g + 4 * k;
+        if (i <= c && c < n) {
+            R[i + (int64_t)c * ld] = ar[k];
+            I[i + (int64_t)c * ld] = ai[k];
         }
     }
 }
