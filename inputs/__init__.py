@@ -25,6 +25,8 @@ Cholesky benchmarks):
                 (Marchenko-Pastur, square case), so kappa(A) ~ (4 + sigma) /
                 sigma = kappa at the cost of one product (the selector's sweep
                 shapes; spd_kappa fixes the spectrum exactly but needs a QR)
+  qr_matrix     m x n, N(0,1) from PCG64(seed + 3000) in C order, column j
+                scaled by kappa^(-j/(n-1)) (the QR workloads)
   selector_shapes
                 (n, batch, dtype, kappa): n and batch log-uniform on [64, 32768]
                 and [1, 10000], FP64 with probability 3/4, kappa log-uniform on
@@ -51,6 +53,16 @@ def _symmetrize_upper(A: np.ndarray) -> np.ndarray:
 def gaussian(n: int, m: int, seed: int) -> np.ndarray:
     """n x m N(0,1) matrix, drawn in C order from PCG64(seed)."""
     return _rng(seed).standard_normal((n, m), dtype=np.float64)
+
+
+def qr_matrix(m: int, n: int, seed: int = 0, kappa: float = 1.0) -> np.ndarray:
+    """m x n Fortran-ordered QR input: G ~ N(0,1) from PCG64(seed + 3000) in C
+    order, column j scaled by kappa^(-j/(n-1)) (kappa = 1: plain Gaussian;
+    otherwise a condition number of roughly kappa times that of G)."""
+    G = _rng(seed + 3000).standard_normal((m, n), dtype=np.float64)
+    if kappa != 1.0 and n > 1:
+        G = G * (float(kappa) ** (-np.arange(n, dtype=np.float64) / (n - 1)))[None, :]
+    return np.asfortranarray(G)
 
 
 def spd_bbt(n: int, seed: int = 0) -> np.ndarray:

@@ -51,6 +51,8 @@ def load(path: str) -> ctypes.CDLL:
         L.oracle_zpotrf_upper.restype = i32
         L.oracle_getrf_nopiv.argtypes = [i64, dp, i64]
         L.oracle_getrf_nopiv.restype = i32
+        L.oracle_geqrf.argtypes = [i64, i64, dp, i64, dp]
+        L.oracle_geqrf.restype = None
     return L
 
 
@@ -127,6 +129,44 @@ def lu_backward_error(A: np.ndarray, W: np.ndarray) -> float:
     L = np.tril(W, -1) + np.eye(n)
     U = np.triu(W)
     return float(np.linalg.norm(A - L @ U) / np.linalg.norm(A))
+
+
+def geqrf(A: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """O10: Householder QR of the m x n (m >= n) matrix A on a copy: R in the
+    upper triangle, the reflectors' vectors below the diagonal (unit entry
+    implied), and their scalars tau (n).  Q = H_0 ... H_{n-1},
+    H_j = I - tau_j v_j v_j^T."""
+    W = np.array(_fortran(A), dtype=np.float64, order="F", copy=True)
+    m, n = W.shape
+    tau = np.zeros(n, dtype=np.float64)
+    lib().oracle_geqrf(m, n, _ptr(W), max(1, m), _ptr(tau))
+    return W, tau
+
+
+def qr_form_q(W: np.ndarray, tau: np.ndarray) -> np.ndarray:
+    """The m x n matrix Q[:, :n] of the packed reflectors (W, tau) of
+    :func:`geqrf`: H_0 ... H_{n-1} applied to the first n columns of I, the
+    last reflector first."""
+    m, n = W.shape
+    Q = np.eye(m, n)
+    for j in range(n - 1, -1, -1):
+        v = np.zeros(m)
+        v[j] = 1.0
+        v[j + 1:] = W[j + 1:, j]
+        Q -= tau[j] * np.outer(v, v @ Q)
+    return Q
+
+
+def qr_backward_error(A: np.ndarray, W: np.ndarray, tau: np.ndarray) -> float:
+    """||A - Q R||_F / ||A||_F for the packed QR factors (W, tau)."""
+    Q = qr_form_q(W, tau)
+    return float(np.linalg.norm(A - Q @ np.triu(W[: W.shape[1], :])) / np.linalg.norm(A))
+
+
+def qr_orthogonality(W: np.ndarray, tau: np.ndarray) -> float:
+    """||Q^T Q - I||_F for the first n columns of Q."""
+    Q = qr_form_q(W, tau)
+    return float(np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1])))
 
 
 def zfactor_backward_error(A: np.ndarray, U: np.ndarray) -> float:

@@ -489,3 +489,45 @@ int oracle_getrf_nopiv(int64_t n, double *A, int64_t lda) {
     }
     return 0;
 }
+
+/*
+ * O10 -- Householder QR, A = Q R (m >= n), in place: the partitioned loop of
+ * Fig. "dense-chol" carried over to QR (the conclusion names QR among the
+ * factorizations the by-blocks pattern carries over to), at b = 1.  Step j,
+ * with alpha = A(j,j) and x = A(j+1:m, j):
+ *   sigma = x^T x.  sigma == 0: tau_j = 0 (H_j = I), column j stays.
+ *   Otherwise beta = -sign(alpha) sqrt(alpha^2 + sigma) (sign(0) = +),
+ *     tau_j = (beta - alpha) / beta, x := x / (alpha - beta) (so that
+ *     v_j = [1; x]), A(j,j) := beta, and every later column c is reflected:
+ *     w = A(j,c) + x^T A(j+1:m, c);  A(j,c) -= tau_j w;
+ *     A(j+1:m, c) -= tau_j w x.
+ * On exit R is the upper triangle, v_j below the diagonal of column j (unit
+ * entry implied), Q = H_0 H_1 ... H_{n-1} with H_j = I - tau_j v_j v_j^T (the
+ * reflector convention of LAPACK's geqrf).  No rescaling of columns whose
+ * squared norm under- or overflows.
+ */
+void oracle_geqrf(int64_t m, int64_t n, double *A, int64_t lda, double *tau) {
+    for (int64_t j = 0; j < n && j < m; ++j) {
+        double alpha = AT(A, lda, j, j);
+        double sigma = 0.0;
+        for (int64_t r = j + 1; r < m; ++r) sigma += AT(A, lda, r, j) * AT(A, lda, r, j);
+        if (sigma == 0.0) {
+            tau[j] = 0.0;
+            continue;
+        }
+        double mag = sqrt(alpha * alpha + sigma);
+        double beta = alpha >= 0.0 ? -mag : mag;
+        double tj = (beta - alpha) / beta;
+        double den = alpha - beta;
+        for (int64_t r = j + 1; r < m; ++r) AT(A, lda, r, j) = AT(A, lda, r, j) / den;
+        AT(A, lda, j, j) = beta;
+        tau[j] = tj;
+        for (int64_t c = j + 1; c < n; ++c) {
+            double w = AT(A, lda, j, c);
+            for (int64_t r = j + 1; r < m; ++r) w += AT(A, lda, r, j) * AT(A, lda, r, c);
+            AT(A, lda, j, c) = AT(A, lda, j, c) - tj * w;
+            double tw = tj * w;
+            for (int64_t i = j + 1; i < m; ++i) AT(A, lda, i, c) = AT(A, lda, i, c) - tw * AT(A, lda, i, j);
+        }
+    }
+}
