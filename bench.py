@@ -546,8 +546,10 @@ def extensions_mode(args, dev, fl, inputs, torch) -> int:
     the median of --steps runs after --warmup on a resident seeded matrix
     (B B^H + n I, complex Gaussian B; G + 2 (n + 1) I, Gaussian G) restored
     outside the timed region, with the backward error of the last run; beside
-    them the oracle's unblocked loops (O8, O9; one host thread) at
-    --ext-oracle-n, one run each.  One JSON line per case."""
+    them the oracle's unblocked loops (O8, O9, O10; one host thread) at
+    --ext-oracle-n, one run each.  Householder QR (flame_qr, 4 n^3 / 3 flops
+    for a square matrix) on a Gaussian matrix, checked by R^T R = A^T A, with
+    the vendor geqrf through torch timed beside it.  One JSON line per case."""
     import time
 
     import oracle
@@ -580,6 +582,10 @@ def extensions_mode(args, dev, fl, inputs, torch) -> int:
         L = torch.tril(W, -1) + torch.eye(n, dtype=W.dtype, device=W.device)
         return float(torch.linalg.norm(P - L @ torch.triu(W)) / torch.linalg.norm(P))
 
+    def qr_err(P, W):  # R^T R = P^T P
+        R = torch.triu(W)
+        return float(torch.linalg.norm(P.T @ P - R.T @ R) / torch.linalg.norm(P) ** 2)
+
     for n in [int(v) for v in args.ext_ns.split(",") if v]:
         g = torch.Generator(device=dev)
         g.manual_seed(args.seed)
@@ -599,6 +605,26 @@ def extensions_mode(args, dev, fl, inputs, torch) -> int:
                           "tflops": round(2 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "backward_error": err}),
               flush=True)
         del G, P
+        G = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
+        P = G.mT.contiguous().mT
+        ms, err = timed(P, lambda W: fl.qr(W)[1], qr_err)
+        rec = {"case": "qr_householder", "n": n, "ms": round(ms, 3),
+               "tflops": round(4 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "gram_error": err}
+        try:  # the same factorization by the vendor library through torch (context)
+            W = P.clone()
+            torch.geqrf(W)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            torch.geqrf(W)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rec["torch_geqrf_ms"] = round(e0.elapsed_time(e1), 3)
+        except RuntimeError as e:
+            rec["torch_geqrf_ms"] = None
+            rec["torch_geqrf_error"] = str(e)[:120]
+        print(json.dumps(rec), flush=True)
+        del G, P
         torch.cuda.empty_cache()
     if not args.no_cpu:
         n = args.ext_oracle_n
@@ -610,8 +636,12 @@ def extensions_mode(args, dev, fl, inputs, torch) -> int:
         t0 = time.perf_counter()
         oracle.getrf_nopiv(A)
         t_l = time.perf_counter() - t0
+        A = inputs.qr_matrix(n, n, args.seed)
+        t0 = time.perf_counter()
+        oracle.geqrf(A)
+        t_q = time.perf_counter() - t0
         print(json.dumps({"case": "oracle", "n": n, "cores": 1, "complex_hermitian_s": round(t_z, 3),
-                          "lu_nopiv_s": round(t_l, 3)}), flush=True)
+                          "lu_nopiv_s": round(t_l, 3), "qr_householder_s": round(t_q, 3)}), flush=True)
     return 0
 
 

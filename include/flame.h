@@ -158,6 +158,32 @@ int flame_factor(int32_t dtype, int64_t n, void *A, int64_t lda, const flame_opt
  * Errors: -1 dtype, -2 n, -3 A, -4 lda, -5 info. */
 int flame_lu(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, void *stream);
 
+/* Householder QR factorization, A = Q R, in place, for an m x n matrix with
+ * m >= n: the partitioned loop of Fig. "dense-chol" carried over to QR, which
+ * the paper's conclusion names among the factorizations its pattern extends
+ * to (a panel of columns is reduced by reflectors, their block form
+ * I - V T V^T is applied to the columns on its right).  On exit R is in the
+ * upper triangle and the reflectors' vectors below the diagonal, with the
+ * reflector convention of LAPACK's geqrf: Q = H_0 H_1 ... H_{n-1},
+ * H_j = I - tau_j v_j v_j^T, v_j(j) = 1 implied, v_j(0:j) = 0, and
+ * R(j,j) = -sign(alpha) ||[alpha; x]|| for the column [alpha; x] it reduces
+ * (tau_j = 0 and H_j = I when x = 0).  No rescaling of columns whose squared
+ * norm under- or overflows.  Panels of 32 columns, outer blocks of 128.
+ *   dtype  FLAME_F64 (FLAME_ERR_UNSUPPORTED for FLAME_F32)
+ *   m, n   rows and columns, 0 <= n <= m; m <= 131072 (else
+ *          FLAME_ERR_UNSUPPORTED: the panel's rows are spread over
+ *          ceil(m / 512) workgroups that must all be resident)
+ *   A, lda device, column-major, lda >= max(1, m)
+ *   tau    device, n doubles (output)
+ *   info   device, one int32: 0, or 1 if a wait between the panel kernel's
+ *          workgroups gave up (not expected; A and tau are then invalid)
+ *   stream as for flame_factor
+ * Device workspace of about 2 KB per row and column (V in two layouts, the
+ * block products) plus the split-K buffer of the trailing product, allocated
+ * on the first call and kept.  Calls that overlap on one device race on it.
+ * Errors: -1 dtype, -2 m, -3 n, -4 A, -5 lda, -6 tau, -7 info. */
+int flame_qr(int32_t dtype, int64_t m, int64_t n, void *A, int64_t lda, void *tau, int32_t *info, void *stream);
+
 /* Cholesky-by-blocks (Fig. "sparse-chol" of the paper, the by-blocks form of
  * the loop of Fig. "dense-chol") over 128 x 128 blocks, run as a task DAG by
  * one persistent kernel.  For iteration k the block operations are

@@ -42,7 +42,7 @@ EXPORTS = (
     "flame_solve_mixed", "flame_shutdown", "flame_batched_factor_noalloc", "flame_trace_busy", "flame_probe",
     "flame_select_class", "flame_factor_by_blocks", "flame_by_blocks_tasks",
     "flame_ichol_analyze", "flame_ichol_stats", "flame_ichol_structure", "flame_ichol_factor", "flame_ichol_values",
-    "flame_ichol_destroy", "flame_ichol_apply", "flame_ichol_pcg", "flame_lu",
+    "flame_ichol_destroy", "flame_ichol_apply", "flame_ichol_pcg", "flame_lu", "flame_qr",
 )
 PROBE = {"mfma_f64": 0, "mfma_f32": 1, "mfma_bf16": 2, "copy": 3}
 NOALLOC_MAX_BATCH = 262144
@@ -122,6 +122,7 @@ def lib(path: str | None = None) -> ctypes.CDLL:
     i32, i64, vp, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
     L.flame_factor.argtypes = [i32, i64, vp, i64, ctypes.POINTER(Opts), vp, vp]
     L.flame_lu.argtypes = [i32, i64, vp, i64, vp, vp]
+    L.flame_qr.argtypes = [i32, i64, i64, vp, i64, vp, vp, vp]
     L.flame_solve.argtypes = [i32, i64, i64, vp, i64, vp, i64, ctypes.POINTER(Refine),
                               ctypes.POINTER(SolveReport), vp]
     L.flame_batched_factor.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.POINTER(Opts), vp]
@@ -280,6 +281,31 @@ def lu(A, info=None):
     rc = lib().flame_lu(F64, n, A.data_ptr(), lda, info.data_ptr(), _stream_ptr())
     _check("flame_lu", rc)
     return info
+
+
+def qr(A, tau=None, info=None):
+    """A := the packed Householder QR of the m x n (m >= n) column-major FP64
+    device tensor A in place (flame_qr): R in the upper triangle, the
+    reflectors' vectors below the diagonal (LAPACK geqrf convention).
+    Returns (tau, info): tau the n reflector scalars, info the device int32
+    (0, or 1 if a wait between the panel kernel's workgroups gave up).
+    Asynchronous on the current stream."""
+    torch = _torch()
+    if A.dim() != 2:
+        raise ValueError("A must be a 2-D tensor")
+    if A.dtype != torch.float64:
+        raise TypeError("flame_qr takes float64")
+    m, n = A.shape
+    lda = _colmajor_ld(A)
+    if tau is None:
+        tau = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
+    elif tau.dtype != torch.float64 or tau.numel() < n or not tau.is_cuda:
+        raise ValueError("tau must be a device float64 tensor with at least n elements")
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rc = lib().flame_qr(F64, m, n, A.data_ptr(), lda, tau.data_ptr(), info.data_ptr(), _stream_ptr())
+    _check("flame_qr", rc)
+    return tau[:n], info
 
 
 def _report(rep: SolveReport, rc: int) -> dict:

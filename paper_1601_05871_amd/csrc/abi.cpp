@@ -105,6 +105,18 @@ int flame_lu(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, void
     return lu_factor(n, static_cast<double *>(A), lda, info, as_stream(stream));
 }
 
+int flame_qr(int32_t dtype, int64_t m, int64_t n, void *A, int64_t lda, void *tau, int32_t *info, void *stream) {
+    if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
+    if (m < 0 || m > ((int64_t)1 << 31) - 1) return -2;
+    if (n < 0 || n > m) return -3;
+    if (A == nullptr && n > 0) return -4;
+    if (lda < (m > 1 ? m : 1)) return -5;
+    if (tau == nullptr && n > 0) return -6;
+    if (info == nullptr) return -7;
+    if (dtype != FLAME_F64 || m > 131072) return FLAME_ERR_UNSUPPORTED;
+    return qr_factor(m, n, static_cast<double *>(A), lda, static_cast<double *>(tau), info, as_stream(stream));
+}
+
 int flame_op_chol(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, int64_t info_base, void *stream) {
     if (dtype != FLAME_F64 && dtype != FLAME_F32) return -1;
     if (n < 0 || n > kMaxBlockOp) return -2;

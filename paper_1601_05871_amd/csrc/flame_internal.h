@@ -201,6 +201,12 @@ int launch_transpose_copy(int64_t rows, int64_t cols, const double *src, int64_t
                           const int32_t *info, hipStream_t s);
 int lu_factor(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s);
 
+// ---- Householder QR (k_qr.hip, qr.cpp) -----------------------------------
+// A = Q R in place (m >= n): R in the upper triangle, the reflectors below
+// the diagonal, tau (n, device); *info := 0, or 1 if a device-side wait of
+// the panel kernel gave up.
+int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *tau, int32_t *info, hipStream_t s);
+
 // ---- selector --------------------------------------------------------------
 int launch_selector(const float *w, const float *feat, int64_t count, float *logits, hipStream_t s);
 
@@ -220,7 +226,8 @@ enum {
     kWsDag = 7,
     kWsComplex = 8,
     kWsLu = 9,
-    kWsSlots = 10
+    kWsQr = 10,
+    kWsSlots = 11
 };
 int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out);
 // Generation of a slot's buffer: changes every time ctx_workspace replaces it

@@ -101,6 +101,20 @@ def test_lu_argument_errors():
     assert L.flame_lu(1, 4, FAKE, 4, FAKE, None) == fl.FLAME_ERR_UNSUPPORTED
 
 
+def test_qr_argument_errors():
+    L = fl.lib()
+    assert L.flame_qr(7, 4, 4, FAKE, 4, FAKE, FAKE, None) == -1
+    assert L.flame_qr(0, -1, 0, FAKE, 4, FAKE, FAKE, None) == -2
+    assert L.flame_qr(0, 4, -1, FAKE, 4, FAKE, FAKE, None) == -3
+    assert L.flame_qr(0, 4, 5, FAKE, 4, FAKE, FAKE, None) == -3  # n > m
+    assert L.flame_qr(0, 4, 4, None, 4, FAKE, FAKE, None) == -4
+    assert L.flame_qr(0, 4, 4, FAKE, 3, FAKE, FAKE, None) == -5
+    assert L.flame_qr(0, 4, 4, FAKE, 4, None, FAKE, None) == -6
+    assert L.flame_qr(0, 4, 4, FAKE, 4, FAKE, None, None) == -7
+    assert L.flame_qr(1, 4, 4, FAKE, 4, FAKE, FAKE, None) == fl.FLAME_ERR_UNSUPPORTED
+    assert L.flame_qr(0, 131073, 4, FAKE, 131073, FAKE, FAKE, None) == fl.FLAME_ERR_UNSUPPORTED
+
+
 def test_solve_argument_errors():
     L = fl.lib()
     assert L.flame_solve(3, 4, 1, FAKE, 4, FAKE, 4, None, None, None) == -1
