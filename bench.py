@@ -75,6 +75,8 @@ def main() -> int:
                          "complex128) and the LU without pivoting (flame_lu) at the orders of --ext-ns, with the "
                          "oracle's unblocked loops timed beside them at --ext-oracle-n")
     ap.add_argument("--ext-ns", default="2048,4096,8192")
+    ap.add_argument("--ext-cases", default="complex,lu,qr",
+                    help="with --extensions: qr alone runs only the QR case (for profiles)")
     ap.add_argument("--ext-oracle-n", type=int, default=1024)
     ap.add_argument("--table-ns", default="4096,8192,16384")
     ap.add_argument("--table-nbs", default="64,128,256")
@@ -586,9 +588,17 @@ def extensions_mode(args, dev, fl, inputs, torch) -> int:
         R = torch.triu(W)
         return float(torch.linalg.norm(P.T @ P - R.T @ R) / torch.linalg.norm(P) ** 2)
 
+    cases = set(args.ext_cases.split(","))
     for n in [int(v) for v in args.ext_ns.split(",") if v]:
         g = torch.Generator(device=dev)
         g.manual_seed(args.seed)
+        if "qr" in cases and not cases & {"complex", "lu"}:
+            G = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
+            ms, err = timed(G.mT.contiguous().mT, lambda W: fl.qr(W)[1], qr_err)
+            print(json.dumps({"case": "qr_householder", "n": n, "ms": round(ms, 3),
+                              "tflops": round(4 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "gram_error": err}),
+                  flush=True)
+            continue
         B = torch.randn(n, n, dtype=torch.complex128, device=dev, generator=g)
         P = B @ B.conj().T
         P.diagonal().copy_(P.diagonal().real + n)

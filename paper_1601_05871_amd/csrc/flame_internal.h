@@ -227,7 +227,8 @@ enum {
     kWsComplex = 8,
     kWsLu = 9,
     kWsQr = 10,
-    kWsSlots = 11
+    kWsQrSplit = 11,
+    kWsSlots = 12
 };
 int ctx_workspace(DevCtx *c, int slot, size_t bytes, void **out);
 // Generation of a slot's buffer: changes every time ctx_workspace replaces it

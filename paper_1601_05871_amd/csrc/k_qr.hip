@@ -19,9 +19,11 @@
 // of them and adds them in workgroup order, so that every workgroup derives
 // the same scalars bit for bit.  One workgroup (m <= 512) skips the exchange.
 //
-// k_qr_t forms the upper triangular T of the block reflector
+// k_qr_gt forms the upper triangular T of the block reflector
 // H_0 ... H_{k-1} = I - V T V^T column by column (T(j, j) = tau_j,
 // T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^T v_j) from the Gram matrix of V.
+#include <algorithm>
+
 #include "dev_sync.h"
 #include "flame_internal.h"
 
@@ -71,12 +73,37 @@ __device__ bool poll_slot(const double *p, int32_t *stop, double *out) {
             *out = v;
             return true;
         }
-        if (load_dev(stop) != 0) return false;
-        if (++spins > kQrSpin) {
-            store_dev(stop, 1);
-            return false;
+        if ((++spins & 63) == 0) {  // the stop flag every 64 rounds: one load per round otherwise
+            if (load_dev(stop) != 0) return false;
+            if (spins > kQrSpin) {
+                store_dev(stop, 1);
+                return false;
+            }
         }
         __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// v of the lane whose index differs in bit log2(D) (D < 32: inside each half
+// of the wavefront), through the swizzle's bit mode on the two halves.
+template <int D>
+__device__ __forceinline__ double xor_lane(double v) {
+    constexpr int pat = 0x1F | (D << 10);
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), pat);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), pat);
+    return __hiloint2double(hi, lo);
+}
+
+// One step of the halving sum over lanes: the lane keeps H of its 2 H
+// values (the upper ones when its bit D is set), added to its partner's.
+template <int H, int D>
+__device__ __forceinline__ void halve(double *d, int lane) {
+    const bool hi = (lane & D) != 0;
+#pragma unroll
+    for (int c = 0; c < H; ++c) {
+        const double give = hi ? d[c] : d[c + H];
+        const double keep = hi ? d[c + H] : d[c];
+        d[c] = keep + xor_lane<D>(give);
     }
 }
 
@@ -86,14 +113,16 @@ __global__ __launch_bounds__(256) void k_qr_fill_empty(int64_t count, double *__
 }
 
 __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
-    __shared__ double red[4][kQB];      // per-wave column sums
+    __shared__ double red[8][kQB];      // per half-wavefront column sums
     __shared__ double grp[8][kQB + 1];  // workgroup partials added by groups of the grid
     __shared__ double prow[2][kQB];     // pivot row: [0] as held by its owner, [1] as used
     __shared__ double tws[kQB];         // tau w_c (0 for c <= j)
-    __shared__ double sc[4];            // beta, tau, alpha - beta, sigma
+    __shared__ double mulv[kQB];        // 1, and 1 / (alpha - beta) at column j
+    __shared__ double keep[kQB];        // 1, and 0 at column j
+    __shared__ double sc[4];            // beta, tau, 1 / (alpha - beta), sigma
     __shared__ int s_bad;
     if (*p.info != 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wg = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wg = blockIdx.x;
     const int64_t r0 = (int64_t)wg * kWgRows + tid;
     double a[kRpt][kQB];
 #pragma unroll
@@ -105,45 +134,37 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
     if (tid == 0) s_bad = 0;
     double *const xrow = p.xch + (int64_t)p.b * p.P * kQB;
     for (int j = 0; j < p.b; ++j) {
-        // column j of this thread's rows (selected without a dynamic index)
-        double x[kRpt];
+        // column j of this thread's rows below the pivot (0 for the others),
+        // picked by a product with the j-th unit vector (uniform, scalar):
+        // exact for finite values, and no per-element select
+        double xm[kRpt];
         bool below[kRpt];
 #pragma unroll
         for (int i = 0; i < kRpt; ++i) {
             const int64_t r = r0 + 256 * i;
             below[i] = r > j && r < p.m;
-            x[i] = 0.0;
+            double x = 0.0;
 #pragma unroll
-            for (int c = 0; c < kQB; ++c)
-                if (c == j) x[i] = a[i][c];
+            for (int c = 0; c < kQB; ++c) x = fma(a[i][c], c == j ? 1.0 : 0.0, x);
+            xm[i] = below[i] ? x : 0.0;
         }
         {
-            double d[kQB];
+            double d[kQB];  // (the columns left of j are formed too, and not used)
 #pragma unroll
             for (int c = 0; c < kQB; ++c) {
                 double s = 0.0;
 #pragma unroll
-                for (int i = 0; i < kRpt; ++i)
-                    if (below[i]) s += x[i] * a[i][c];
+                for (int i = 0; i < kRpt; ++i) s = fma(xm[i], a[i][c], s);
                 d[c] = s;
             }
-            // wave sum by recursive halving: at distance 32 >> st the lane
-            // keeps half of its columns (the upper half when that bit of its
-            // index is set), added to its partner's; in the end it holds
-            // column (lane >> 1) & 31
-#pragma unroll
-            for (int st = 0; st < 5; ++st) {
-                const int h = 16 >> st, dist = 32 >> st;
-                const bool hi = (lane & dist) != 0;
-#pragma unroll
-                for (int c = 0; c < h; ++c) {
-                    const double give = hi ? d[c] : d[c + h];
-                    const double keep = hi ? d[c + h] : d[c];
-                    d[c] = keep + __shfl_xor(give, dist);
-                }
-            }
-            d[0] += __shfl_xor(d[0], 1);
-            if ((lane & 1) == 0) red[wave][(lane >> 1) & (kQB - 1)] = d[0];
+            // sum over each half-wavefront by recursive halving: afterwards
+            // lane l holds column l & 31 of its half's 32 lanes
+            halve<16, 16>(d, lane);
+            halve<8, 8>(d, lane);
+            halve<4, 4>(d, lane);
+            halve<2, 2>(d, lane);
+            halve<1, 1>(d, lane);
+            red[tid >> 5][lane & (kQB - 1)] = d[0];
         }
         if (wg == 0 && tid == j) {
 #pragma unroll
@@ -153,13 +174,16 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
         double s_c = 0.0, s_j = 0.0;  // d_c and sigma, for threads tid < kQB
         if (p.P == 1) {
             if (tid < kQB) {
-                s_c = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-                s_j = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+                s_c = ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) +
+                      ((red[4][tid] + red[5][tid]) + (red[6][tid] + red[7][tid]));
+                s_j = ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) +
+                      ((red[4][j] + red[5][j]) + (red[6][j] + red[7][j]));
                 prow[1][tid] = prow[0][tid];
             }
         } else {
             if (tid < kQB) {
-                const double part = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+                const double part = ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) +
+                                    ((red[4][tid] + red[5][tid]) + (red[6][tid] + red[7][tid]));
                 store_dev(p.xch + ((int64_t)j * p.P + wg) * kQB + tid, publishable(part));
                 if (wg == 0) store_dev(xrow + (int64_t)j * kQB + tid, publishable(prow[0][tid]));
             }
@@ -195,10 +219,12 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
                 const double mag = sqrt(alpha * alpha + s_j);
                 beta = alpha >= 0.0 ? -mag : mag;
                 tj = (beta - alpha) / beta;
-                den = alpha - beta;
-                if (tid > j) tw = tj * (prow[1][tid] + s_c / den);
+                den = 1.0 / (alpha - beta);  // the reflector's scale, as a reciprocal
+                if (tid > j) tw = tj * (prow[1][tid] + s_c * den);
             }
             tws[tid] = tw;
+            mulv[tid] = tid == j ? den : 1.0;
+            keep[tid] = tid == j ? 0.0 : 1.0;
             if (tid == 0) {
                 sc[0] = beta;
                 sc[1] = tj;
@@ -210,16 +236,20 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
         __syncthreads();
         if (sc[3] == 0.0) continue;  // H_j = I (uniform: every thread reads the same value)
         const double beta = sc[0], den = sc[2];
+        // below the pivot: A(r, c) -= tau w_c v_r (tau w_c = 0 for c <= j) and
+        // A(r, j) := v_r, as A(r, c) mul_c - tau w_c v_r (mul_c = 1 except
+        // mul_j = 1 / (alpha - beta)); the pivot row: A(j, c) -= tau w_c and
+        // A(j, j) := beta, as A(j, c) keep_c - tau w_c + beta (1 - keep_c)
 #pragma unroll
         for (int i = 0; i < kRpt; ++i) {
             const int64_t r = r0 + 256 * i;
             if (below[i]) {
-                const double v = x[i] / den;
+                const double v = xm[i] * den;
 #pragma unroll
-                for (int c = 0; c < kQB; ++c) a[i][c] = c == j ? v : a[i][c] - tws[c] * v;
+                for (int c = 0; c < kQB; ++c) a[i][c] = fma(a[i][c], mulv[c], -(tws[c] * v));
             } else if (r == j) {
 #pragma unroll
-                for (int c = 0; c < kQB; ++c) a[i][c] = c == j ? beta : a[i][c] - tws[c];
+                for (int c = 0; c < kQB; ++c) a[i][c] = fma(a[i][c], keep[c], fma(beta, 1.0 - keep[c], -tws[c]));
             }
         }
     }
@@ -237,33 +267,199 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
             }
         }
     }
-    if (wg == 0)
+    if (wg == 0) {
         for (int64_t e = tid; e < p.ro * p.b; e += 256) {
             const int64_t rr = e % p.ro, c = e / p.ro;
             p.Vs[rr + c * p.ldvs] = 0.0;
             p.Vt[c + rr * p.ldvt] = 0.0;
         }
+    }
 }
 
-// Columns j0..j1-1 of T (ld ldt, j1 <= kOB) from G = -V^T V (ld ldg) and tau,
-// given columns 0..j0-1; one workgroup, T(0:j1, 0:j1) in LDS, thread i forms
-// row i.
-__global__ __launch_bounds__(kOB) void k_qr_t(int j0, int j1, const double *__restrict__ G, int64_t ldg,
-                                              const double *__restrict__ tau, double *__restrict__ T, int64_t ldt,
-                                              const int32_t *__restrict__ info) {
-    __shared__ double t[kOB][kOB + 1];
+// Zeroes two rows x cols blocks of the same shape (ld ldd).
+__global__ __launch_bounds__(256) void k_qr_zero2(int64_t rows, double *__restrict__ d0, double *__restrict__ d1,
+                                                  int64_t ldd) {
+    const int64_t j = blockIdx.x;
+    for (int64_t i = threadIdx.x; i < rows; i += 256) {
+        d0[i + j * ldd] = 0.0;
+        d1[i + j * ldd] = 0.0;
+    }
+}
+
+// Partial products of the skinny C -= X^T Y (M, N <= 128, K long): workgroup
+// s forms X(K_s, :)^T Y(K_s, :) over its slice K_s of kc rows and stores it
+// at part + s M N (column-major, ld M); the caller adds the slices in order.
+// Rows staged through LDS 32 at a time; thread (ti, tj) forms the outputs
+// (ti + 16 a, tj + 16 b), a < TM, b < TN (16 TM >= M, 16 TN >= N).
+template <int TM, int TN>
+__global__ __launch_bounds__(256) void k_qr_skinny(int M, int N, int64_t K, int64_t kc, const double *__restrict__ X,
+                                                   int64_t ldx, const double *__restrict__ Y, int64_t ldy,
+                                                   double *__restrict__ part, const int32_t *__restrict__ info) {
+    __shared__ double xs[32][16 * TM + 1];
+    __shared__ double ys[32][16 * TN + 1];
     if (*info != 0) return;
-    const int i = threadIdx.x;
-    for (int l = 0; l < j0; ++l) t[i][l] = (i <= l) ? T[i + (int64_t)l * ldt] : 0.0;
-    __syncthreads();
-    for (int j = j0; j < j1; ++j) {
-        const double tj = tau[j];
-        double s = 0.0;
-        for (int l = i; l < j; ++l) s += t[i][l] * G[l + (int64_t)j * ldg];  // V^T v_j = -G(:, j)
-        t[i][j] = i < j ? tj * s : (i == j ? tj : 0.0);
+    const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
+    const int kr = tid & 31, cg = tid >> 5;  // staging: row kr of the 32, columns cg + 8 u
+    const int64_t k0 = (int64_t)blockIdx.x * kc, k1 = min(K, k0 + kc);
+    double acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = 0.0;
+    // the next 32 rows are loaded into registers while the current ones are used
+    double xr[2 * TM], yr[2 * TN];
+    auto fetch = [&](int64_t kb) {
+        const int64_t k = kb + kr;
+        const bool in = k < k1;
+#pragma unroll
+        for (int u = 0; u < 2 * TM; ++u) {
+            const int i = cg + 8 * u;
+            xr[u] = (in && i < M) ? X[k + i * ldx] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 2 * TN; ++u) {
+            const int j = cg + 8 * u;
+            yr[u] = (in && j < N) ? Y[k + j * ldy] : 0.0;
+        }
+    };
+    fetch(k0);
+    for (int64_t kb = k0; kb < k1; kb += 32) {
+#pragma unroll
+        for (int u = 0; u < 2 * TM; ++u) xs[kr][cg + 8 * u] = xr[u];
+#pragma unroll
+        for (int u = 0; u < 2 * TN; ++u) ys[kr][cg + 8 * u] = yr[u];
+        __syncthreads();
+        if (kb + 32 < k1) fetch(kb + 32);
+#pragma unroll 4
+        for (int q = 0; q < 32; ++q) {
+            double xv[TM], yv[TN];
+#pragma unroll
+            for (int a = 0; a < TM; ++a) xv[a] = xs[q][ti + 16 * a];
+#pragma unroll
+            for (int b = 0; b < TN; ++b) yv[b] = ys[q][tj + 16 * b];
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) acc[a][b] += xv[a] * yv[b];
+        }
         __syncthreads();
     }
-    for (int j = j0; j < j1; ++j) T[i + (int64_t)j * ldt] = t[i][j];  // zero below the diagonal
+    double *dst = part + (int64_t)blockIdx.x * M * N;
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            const int i = ti + 16 * a, j = tj + 16 * b;
+            if (i < M && j < N) dst[i + (int64_t)j * M] = acc[a][b];
+        }
+}
+
+// From the S partial products of V^T V_p (j1 x b, b = j1 - j0 <= kQB,
+// j1 <= kOB: the Gram columns of the panel's reflectors j0..j1-1, added in
+// slice order), columns j0..j1-1 of T (ld ldt), given columns 0..j0-1.  In
+// block form, with T11 the first j0 columns and V = [V1 V2]:
+//   T22 = the recurrence on the new columns alone,
+//   T12 = -T11 (V1^T V2) T22.
+// One workgroup.  T22: row i of T22 depends only on row i and on V2^T V2, so
+// each row is formed by one thread from its own registers, no barriers; then
+// the two products through LDS.
+__global__ __launch_bounds__(256) void k_qr_gt(int S, int j0, int j1, const double *__restrict__ part,
+                                               const double *__restrict__ tau, double *__restrict__ T, int64_t ldt,
+                                               const int32_t *__restrict__ info) {
+    constexpr int kH = kOB - kQB;          // rows of T12 at most
+    __shared__ double g[kOB][kQB + 1];     // V^T V_p (rows 0..j1-1)
+    __shared__ double t22[kQB][kQB + 1];
+    __shared__ double x[kH][kQB + 1];      // (V1^T V2) T22
+    __shared__ double t11[kH][kH + 1];
+    __shared__ double tv[kQB];
+    if (*info != 0) return;
+    const int tid = threadIdx.x, b = j1 - j0;
+    for (int e = tid; e < j1 * b; e += 256) {
+        const int r = e % j1, c = e / j1;
+        double sum = 0.0;
+#pragma unroll 8
+        for (int q = 0; q < S; ++q) sum += part[(int64_t)q * j1 * b + e];
+        g[r][c] = sum;
+    }
+    for (int e = tid; e < j0 * j0; e += 256) {
+        const int r = e % j0, c = e / j0;
+        t11[r][c] = r <= c ? T[r + (int64_t)c * ldt] : 0.0;
+    }
+    if (tid < kQB) tv[tid] = tid < b ? tau[j0 + tid] : 0.0;
+    __syncthreads();
+    if (tid < kQB) {  // row i = tid of T22: T(i, c) = -tau_c sum_{l < c} T(i, l) (V2^T V2)(l, c)
+        const int i = tid;
+        double t[kQB];
+#pragma unroll
+        for (int c = 0; c < kQB; ++c) {
+            double sum = 0.0;
+#pragma unroll
+            for (int l = 0; l < c; ++l) sum += t[l] * g[j0 + l][c];
+            t[c] = c < b ? (c > i ? -tv[c] * sum : (c == i ? tv[c] : 0.0)) : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < kQB; ++c) t22[i][c] = t[c];
+    }
+    __syncthreads();
+    if (j0 > 0) {
+        // thread (r, h): row r, columns 8 h .. 8 h + 7, eight independent sums
+        for (int e = tid; e < j0 * 4; e += 256) {  // X = (V1^T V2) T22
+            const int r = e % j0, h = e / j0;
+            double acc[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+            for (int l = 0; l < b; ++l) {
+                const double gl = g[r][l];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] += gl * t22[l][8 * h + c];
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) x[r][8 * h + c] = acc[c];
+        }
+        __syncthreads();
+        for (int e = tid; e < j0 * 4; e += 256) {  // T12 = -T11 X
+            const int r = e % j0, h = e / j0;
+            double acc[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+            for (int l = r; l < j0; ++l) {
+                const double tl = t11[r][l];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] += tl * x[l][8 * h + c];
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (8 * h + c < b) T[r + (int64_t)(j0 + 8 * h + c) * ldt] = -acc[c];
+        }
+    }
+    // T22 and zeros below it (the rows up to kOB: the products read the whole block)
+    for (int e = tid; e < (kOB - j0) * b; e += 256) {
+        const int r = e % (kOB - j0), c = e / (kOB - j0);
+        T[(j0 + r) + (int64_t)(j0 + c) * ldt] = r < kQB ? t22[r][c] : 0.0;
+    }
+}
+
+// Y := T^T V^T C for the product slices of V^T C (kb x nc, added in slice
+// order): one workgroup per column j of Y (ld kOB); T (kb x kb, ld ldt,
+// upper triangular).
+__global__ __launch_bounds__(kOB) void k_qr_wy(int S, int kb, int nc, const double *__restrict__ part,
+                                               const double *__restrict__ T, int64_t ldt, double *__restrict__ Y,
+                                               const int32_t *__restrict__ info) {
+    __shared__ double w[kOB];
+    if (*info != 0) return;
+    const int i = threadIdx.x, j = blockIdx.x;
+    if (i < kb) {
+        double sum = 0.0;
+#pragma unroll 8
+        for (int q = 0; q < S; ++q) sum += part[(int64_t)q * kb * nc + i + (int64_t)j * kb];
+        w[i] = sum;
+    }
+    __syncthreads();
+    if (i < kb) {
+        double sum = 0.0;
+        for (int l = 0; l <= i; ++l) sum += T[l + (int64_t)i * ldt] * w[l];
+        Y[i + (int64_t)j * kOB] = sum;
+    }
 }
 
 }  // namespace
@@ -300,11 +496,63 @@ int launch_qr_panel(int64_t m, int b, double *A, int64_t lda, double *tau, doubl
     return FLAME_OK;
 }
 
-int launch_qr_t(int j0, int j1, const double *G, int64_t ldg, const double *tau, double *T, int64_t ldt,
-                const int32_t *info, hipStream_t s) {
+int launch_qr_zero2(int64_t rows, int64_t cols, double *d0, double *d1, int64_t ldd, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return FLAME_OK;
+    hipLaunchKernelGGL(k_qr_zero2, dim3((unsigned)cols), dim3(256), 0, s, rows, d0, d1, ldd);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int qr_slices(int64_t K, int smax, int64_t *kc) {
+    int S = (int)std::min<int64_t>(smax, std::max<int64_t>(1, (K + 127) / 128));
+    int64_t c = ((K + S - 1) / S + 31) / 32 * 32;
+    S = (int)((K + c - 1) / c);
+    *kc = c;
+    return S;
+}
+
+namespace {
+template <int TM, int TN>
+void skinny_launch(int S, int M, int N, int64_t K, int64_t kc, const double *X, int64_t ldx, const double *Y,
+                   int64_t ldy, double *part, const int32_t *info, hipStream_t s) {
+    hipLaunchKernelGGL((k_qr_skinny<TM, TN>), dim3((unsigned)S), dim3(256), 0, s, M, N, K, kc, X, ldx, Y, ldy, part,
+                       info);
+}
+template <int TM>
+void skinny_n(int tn, int S, int M, int N, int64_t K, int64_t kc, const double *X, int64_t ldx, const double *Y,
+              int64_t ldy, double *part, const int32_t *info, hipStream_t s) {
+    if (tn <= 2) skinny_launch<TM, 2>(S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
+    else if (tn <= 4) skinny_launch<TM, 4>(S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
+    else skinny_launch<TM, 8>(S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
+}
+}  // namespace
+
+int launch_qr_skinny(int S, int M, int N, int64_t K, int64_t kc, const double *X, int64_t ldx, const double *Y,
+                     int64_t ldy, double *part, const int32_t *info, hipStream_t s) {
+    if (M <= 0 || N <= 0) return FLAME_OK;
+    if (M > kOB || N > kOB || K <= 0) return FLAME_ERR_UNSUPPORTED;
+    const int tm = (M + 15) / 16, tn = (N + 15) / 16;
+    if (tm <= 2) skinny_n<2>(tn, S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
+    else if (tm <= 4) skinny_n<4>(tn, S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
+    else skinny_n<8>(tn, S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int launch_qr_gt(int S, int j0, int j1, const double *part, const double *tau, double *T, int64_t ldt,
+                 const int32_t *info, hipStream_t s) {
     if (j1 <= j0) return FLAME_OK;
-    if (j0 < 0 || j1 > kOB) return FLAME_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(k_qr_t, dim3(1), dim3(kOB), 0, s, j0, j1, G, ldg, tau, T, ldt, info);
+    if (j0 < 0 || j1 > kOB || j1 - j0 > kQB) return FLAME_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_qr_gt, dim3(1), dim3(256), 0, s, S, j0, j1, part, tau, T, ldt, info);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int launch_qr_wy(int S, int kb, int nc, const double *part, const double *T, int64_t ldt, double *Y,
+                 const int32_t *info, hipStream_t s) {
+    if (kb <= 0 || nc <= 0) return FLAME_OK;
+    if (kb > kOB) return FLAME_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_qr_wy, dim3((unsigned)nc), dim3(kOB), 0, s, S, kb, nc, part, T, ldt, Y, info);
     FLAME_CHECK_LAUNCH();
     return FLAME_OK;
 }

@@ -26,22 +26,37 @@ namespace flame {
 int qr_panel_rows();
 int launch_qr_panel(int64_t m, int b, double *A, int64_t lda, double *tau, double *Vs, int64_t ldvs, double *Vt,
                     int64_t ldvt, int64_t ro, double *xch, int32_t *info, hipStream_t s);
-int launch_qr_t(int j0, int j1, const double *G, int64_t ldg, const double *tau, double *T, int64_t ldt,
-                const int32_t *info, hipStream_t s);
+int launch_qr_zero2(int64_t rows, int64_t cols, double *d0, double *d1, int64_t ldd, hipStream_t s);
+int qr_slices(int64_t K, int smax, int64_t *kc);
+int launch_qr_skinny(int S, int M, int N, int64_t K, int64_t kc, const double *X, int64_t ldx, const double *Y,
+                     int64_t ldy, double *part, const int32_t *info, hipStream_t s);
+int launch_qr_gt(int S, int j0, int j1, const double *part, const double *tau, double *T, int64_t ldt,
+                 const int32_t *info, hipStream_t s);
+int launch_qr_wy(int S, int kb, int nc, const double *part, const double *T, int64_t ldt, double *Y,
+                 const int32_t *info, hipStream_t s);
 
 namespace {
 
-constexpr int kIB = 32;   // panel
-constexpr int kOB = 128;  // outer block
+constexpr int kIB = 32;        // panel
+constexpr int kOB = 128;       // outer block
+constexpr int kSideCus = 16;   // compute units the side stream's large product leaves to the panels
+constexpr int kSlices = 128;   // K slices of a skinny product at most
+constexpr int kGramSlices = 32;
+
+struct QrBuf {  // one outer block's reflectors (two of them: the side stream reads one while the next is built)
+    double *Vs;  // m x kOB, ld ldvs
+    double *Vt;  // kOB x m, ld kOB
+    double *T;   // kOB x kOB
+};
 
 struct QrWork {
-    double *Vs;  // m x kOB, ld ldvs
+    QrBuf buf[2];
     int64_t ldvs;
-    double *Vt;  // kOB x m, ld kOB
-    double *W, *Y;  // kOB x n, ld kOB
-    double *G, *T;  // kOB x kOB
+    double *W[2], *Y[2];  // kOB x n, ld kOB: [0] main stream, [1] side stream
+    double *split;        // split-K partial products of the side stream
+    double *part;         // skinny-product slices (main stream)
+    double *gpart;        // Gram slices of a panel (main stream)
     double *xch;
-    double *split;  // split-K partial products
 };
 
 // C -= X^T Y with a long K: the largest multiple of 32 of K split over
@@ -58,20 +73,44 @@ int gemm_long(int64_t M, int64_t N, int64_t K, const double *X, int64_t ldx, con
 }
 
 // C := (I - V T^T V^T) C for the mr x nc block C, kb reflectors: V (mr x kb)
-// at V (ld ldv), its rows at Vt (ld kOB), T (kb x kb) at Tb (ld kOB).
-int apply_qt(const QrWork &w, int64_t mr, int64_t nc, int kb, const double *V, const double *Vt, const double *Tb,
-             double *C, int64_t ldc, const int32_t *info, hipStream_t s) {
+// at V (ld ldvs), its rows at Vt (ld kOB), T (kb x kb) at Tb (ld kOB).
+// nc <= kOB (main stream): Y := T^T V^T C from the slices of the skinny
+// product V^T C, then C -= (V^T)^T Y.
+int apply_qt_narrow(const QrWork &w, int64_t mr, int64_t nc, int kb, const double *V, const double *Vt,
+                    const double *Tb, double *C, int64_t ldc, const int32_t *info, hipStream_t s) {
     if (nc <= 0) return FLAME_OK;
-    int rc = launch_fill0(kb, nc, w.W, kOB, s);
-    if (!rc) rc = gemm_long(kb, nc, mr, V, w.ldvs, C, ldc, w.W, kOB, w.split, info, s);
-    if (!rc) rc = launch_fill0(kb, nc, w.Y, kOB, s);
-    if (!rc) rc = launch_gemm_tn(Prec::F64, true, false, kb, nc, kb, Tb, kOB, w.W, kOB, w.Y, kOB, info, s);
-    if (!rc) rc = launch_gemm_tn(Prec::F64, true, false, mr, nc, kb, Vt, kOB, w.Y, kOB, C, ldc, info, s);
+    int64_t kc = 0;
+    const int S = qr_slices(mr, kSlices, &kc);
+    int rc = launch_qr_skinny(S, kb, (int)nc, mr, kc, V, w.ldvs, C, ldc, w.part, info, s);
+    if (!rc) rc = launch_qr_wy(S, kb, (int)nc, w.part, Tb, kOB, w.Y[0], info, s);
+    if (!rc) rc = launch_gemm_tn(Prec::F64, true, false, mr, nc, kb, Vt, kOB, w.Y[0], kOB, C, ldc, info, s);
+    return rc;
+}
+
+// The same for any nc (side stream): W := 0 - V^T C (split over K),
+// Y := 0 - T^T W, C -= (V^T)^T Y.
+int apply_qt_wide(const QrWork &w, int64_t mr, int64_t nc, int kb, const double *V, const double *Vt,
+                  const double *Tb, double *C, int64_t ldc, const int32_t *info, hipStream_t s, int reserve_cus) {
+    if (nc <= 0) return FLAME_OK;
+    int rc = launch_qr_zero2(kb, nc, w.W[1], w.Y[1], kOB, s);
+    if (!rc) rc = gemm_long(kb, nc, mr, V, w.ldvs, C, ldc, w.W[1], kOB, w.split, info, s);
+    if (!rc) rc = launch_gemm_tn(Prec::F64, true, false, kb, nc, kb, Tb, kOB, w.W[1], kOB, w.Y[1], kOB, info, s);
+    if (!rc)
+        rc = launch_gemm_tn(Prec::F64, true, false, mr, nc, kb, Vt, kOB, w.Y[1], kOB, C, ldc, info, s, reserve_cus);
     return rc;
 }
 
 }  // namespace
 
+static int qr_blocks(const QrWork &w, int64_t m, int64_t n, double *A, int64_t lda, double *tau, int32_t *info,
+                     hipStream_t s, hipStream_t side, hipEvent_t ev_next, hipEvent_t ev_rest, bool *side_pending);
+
+// Lookahead of one block: block k's update of the columns beyond block k + 1
+// runs on the side stream while the main stream updates block k + 1's
+// columns and factors its panels; before block k + 1's own updates the main
+// stream waits for it.  The reflectors of consecutive blocks live in
+// alternate buffers, so block k + 1's panels never overwrite what the side
+// stream still reads.
 int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *tau, int32_t *info, hipStream_t s) {
     int rc = launch_zero_i32(info, 1, s);
     if (rc || n == 0) return rc;
@@ -80,48 +119,88 @@ int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *tau, int32_t
     const int64_t pmax = (m + qr_panel_rows() - 1) / qr_panel_rows();
     const int64_t ldvs = (m + 1) / 2 * 2;  // even: 16-byte aligned columns
     const size_t xch = (size_t)kIB * pmax * kIB + (size_t)kIB * kIB;
-    const size_t doubles = (size_t)ldvs * kOB + (size_t)kOB * (size_t)m + 2 * (size_t)kOB * (size_t)n +
-                           2 * (size_t)kOB * kOB + xch;
+    const size_t per_buf = (size_t)ldvs * kOB + (size_t)kOB * (size_t)m + (size_t)kOB * kOB;
+    const size_t part = (size_t)kSlices * kOB * kOB, gpart = (size_t)kGramSlices * kOB * kIB;
+    const size_t doubles = 2 * per_buf + 4 * (size_t)kOB * (size_t)n + part + gpart + xch;
     void *ws = nullptr;
     rc = ctx_workspace(ctx, kWsQr, doubles * sizeof(double), &ws);
     if (rc) return rc;
     void *split = nullptr;
-    rc = ctx_workspace(ctx, kWsSplit, splitk_workspace_bytes(), &split);
+    rc = ctx_workspace(ctx, kWsQrSplit, splitk_workspace_bytes(), &split);
     if (rc) return rc;
     QrWork w;
-    w.Vs = static_cast<double *>(ws);
+    double *p = static_cast<double *>(ws);
+    for (int b = 0; b < 2; ++b) {
+        w.buf[b].Vs = p;
+        w.buf[b].Vt = p + (size_t)ldvs * kOB;
+        w.buf[b].T = w.buf[b].Vt + (size_t)kOB * m;
+        p += per_buf;
+    }
     w.ldvs = ldvs;
-    w.Vt = w.Vs + (size_t)ldvs * kOB;
-    w.W = w.Vt + (size_t)kOB * m;
-    w.Y = w.W + (size_t)kOB * n;
-    w.G = w.Y + (size_t)kOB * n;
-    w.T = w.G + (size_t)kOB * kOB;
-    w.xch = w.T + (size_t)kOB * kOB;
+    for (int q = 0; q < 2; ++q) {
+        w.W[q] = p;
+        w.Y[q] = p + (size_t)kOB * n;
+        p += 2 * (size_t)kOB * n;
+    }
+    w.part = p;
+    w.gpart = p + part;
+    w.xch = w.gpart + gpart;
     w.split = static_cast<double *>(split);
-    for (int64_t k = 0; k < n; k += kOB) {
+    hipStream_t side = ctx_side_stream(ctx);
+    hipEvent_t ev_next = ctx_event(ctx, 2);  // main: the next block's columns updated, V and T final
+    hipEvent_t ev_rest = ctx_event(ctx, 3);  // side: the columns beyond the next block updated
+    bool side_pending = false;
+    rc = qr_blocks(w, m, n, A, lda, tau, info, s, side, ev_next, ev_rest, &side_pending);
+    // the side stream's last update joins the caller's stream (also after an error)
+    if (side_pending) FLAME_HIP(hipStreamWaitEvent(s, ev_rest, 0));
+    return rc;
+}
+
+static int qr_blocks(const QrWork &w, int64_t m, int64_t n, double *A, int64_t lda, double *tau, int32_t *info,
+                     hipStream_t s, hipStream_t side, hipEvent_t ev_next, hipEvent_t ev_rest, bool *side_pending) {
+    const int64_t ldvs = w.ldvs;
+    int rc = FLAME_OK;
+    for (int64_t k = 0, blk = 0; k < n; k += kOB, ++blk) {
+        const QrBuf &B = w.buf[blk & 1];
         const int nbk = (int)std::min<int64_t>(kOB, n - k);
         const int64_t mk = m - k;
         for (int i0 = 0; i0 < nbk; i0 += kIB) {
             const int bi = std::min(kIB, nbk - i0);
             const int64_t mi = mk - i0;
             double *Ap = A + (k + i0) + (k + i0) * lda;
-            rc = launch_qr_panel(mi, bi, Ap, lda, tau + k + i0, w.Vs + (int64_t)i0 * ldvs, ldvs, w.Vt + i0, kOB, i0,
+            rc = launch_qr_panel(mi, bi, Ap, lda, tau + k + i0, B.Vs + (int64_t)i0 * ldvs, ldvs, B.Vt + i0, kOB, i0,
                                  w.xch, info, s);
-            // G(0:i0+bi, i0:i0+bi) := -V^T V_p over the rows where V_p is not zero
-            if (!rc) rc = launch_fill0(i0 + bi, bi, w.G + (int64_t)i0 * kOB, kOB, s);
+            // V^T V_p (rows i0.. : V_p is zero above), then T's new columns
+            int64_t kc = 0;
+            const int S = qr_slices(mi, kGramSlices, &kc);
             if (!rc)
-                rc = gemm_long(i0 + bi, bi, mi, w.Vs + i0, ldvs, w.Vs + i0 + (int64_t)i0 * ldvs, ldvs,
-                               w.G + (int64_t)i0 * kOB, kOB, w.split, info, s);
-            if (!rc) rc = launch_qr_t(i0, i0 + bi, w.G, kOB, tau + k, w.T, kOB, info, s);
+                rc = launch_qr_skinny(S, i0 + bi, bi, mi, kc, B.Vs + i0, ldvs, B.Vs + i0 + (int64_t)i0 * ldvs, ldvs,
+                                      w.gpart, info, s);
+            if (!rc) rc = launch_qr_gt(S, i0, i0 + bi, w.gpart, tau + k, B.T, kOB, info, s);
             // the block's columns right of the panel
             if (!rc)
-                rc = apply_qt(w, mi, nbk - i0 - bi, bi, w.Vs + i0 + (int64_t)i0 * ldvs, w.Vt + i0 + (int64_t)i0 * kOB,
-                              w.T + i0 + (int64_t)i0 * kOB, Ap + (int64_t)bi * lda, lda, info, s);
+                rc = apply_qt_narrow(w, mi, nbk - i0 - bi, bi, B.Vs + i0 + (int64_t)i0 * ldvs,
+                                     B.Vt + i0 + (int64_t)i0 * kOB, B.T + i0 + (int64_t)i0 * kOB,
+                                     Ap + (int64_t)bi * lda, lda, info, s);
             if (rc) return rc;
         }
-        // the columns right of the block
-        rc = apply_qt(w, mk, n - k - nbk, nbk, w.Vs, w.Vt, w.T, A + k + (k + nbk) * lda, lda, info, s);
+        const int64_t rest = n - k - nbk;
+        if (rest == 0) break;
+        // the previous block's side update covered these columns too
+        if (*side_pending) FLAME_HIP(hipStreamWaitEvent(s, ev_rest, 0));
+        *side_pending = false;
+        const int64_t nn = std::min<int64_t>(kOB, rest), far = rest - nn;
+        double *C = A + k + (k + nbk) * lda;
+        rc = apply_qt_narrow(w, mk, nn, nbk, B.Vs, B.Vt, B.T, C, lda, info, s);
         if (rc) return rc;
+        if (far > 0) {
+            FLAME_HIP(hipEventRecord(ev_next, s));
+            FLAME_HIP(hipStreamWaitEvent(side, ev_next, 0));
+            rc = apply_qt_wide(w, mk, far, nbk, B.Vs, B.Vt, B.T, C + nn * lda, lda, info, side, kSideCus);
+            if (rc) return rc;
+            FLAME_HIP(hipEventRecord(ev_rest, side));
+            *side_pending = true;
+        }
     }
     return FLAME_OK;
 }
