@@ -7,7 +7,7 @@
 // k_qr_panel factors an m x b (b <= 32) panel with the reflector convention
 // of LAPACK's geqrf (beta = -sign(alpha) ||[alpha; x]||, tau = (beta - alpha)
 // / beta, v = [1; x / (alpha - beta)]).  The panel's rows are spread over
-// several workgroups (512 rows each, two per thread, all b columns in
+// several workgroups (512 rows each, one per thread, all b columns in
 // registers), so a tall panel is read from HBM once.  Step j needs, from all
 // rows r > j, the sums
 //     d_c = sum_r A(r, j) A(r, c),   c >= j     (d_j = sigma = ||x||^2),
@@ -32,8 +32,10 @@ namespace flame {
 namespace {
 
 constexpr int kQB = 32;                  // panel width
-constexpr int kRpt = 2;                  // panel rows per thread
-constexpr int kWgRows = 256 * kRpt;      // panel rows per workgroup
+constexpr int kPT = 512;                 // panel kernel threads (two wavefronts per SIMD)
+constexpr int kRpt = 1;                  // panel rows per thread
+constexpr int kWgRows = kPT * kRpt;      // panel rows per workgroup
+constexpr int kGroups = kPT / 32;        // half-wavefronts
 constexpr int kOB = 128;                 // outer block (order of T)
 constexpr long long kQrSpin = 1LL << 22; // sleep rounds before a wait gives up
 // The empty-slot marker: a signalling NaN.  Arithmetic never produces one and
@@ -107,14 +109,28 @@ __device__ __forceinline__ void halve(double *d, int lane) {
     }
 }
 
+// Column c of the kGroups rows of an LDS table, added pairwise in a fixed
+// order (every workgroup adds the same values the same way).
+template <int LD>
+__device__ __forceinline__ double sum_groups(const double (*t)[LD], int c) {
+    double v[kGroups];
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) v[g] = t[g][c];
+#pragma unroll
+    for (int w = 1; w < kGroups; w *= 2)
+#pragma unroll
+        for (int g = 0; g < kGroups; g += 2 * w) v[g] += v[g + w];
+    return v[0];
+}
+
 __global__ __launch_bounds__(256) void k_qr_fill_empty(int64_t count, double *__restrict__ p) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < count) p[i] = __longlong_as_double((long long)kEmpty);
 }
 
-__global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
-    __shared__ double red[8][kQB];      // per half-wavefront column sums
-    __shared__ double grp[8][kQB + 1];  // workgroup partials added by groups of the grid
+__global__ __launch_bounds__(kPT) void k_qr_panel(QrPanelP p) {
+    __shared__ double red[kGroups][kQB];      // per half-wavefront column sums
+    __shared__ double grp[kGroups][kQB + 1];  // workgroup partials added by groups of the grid
     __shared__ double prow[2][kQB];     // pivot row: [0] as held by its owner, [1] as used
     __shared__ double tws[kQB];         // tau w_c (0 for c <= j)
     __shared__ double mulv[kQB];        // 1, and 1 / (alpha - beta) at column j
@@ -127,7 +143,7 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
     double a[kRpt][kQB];
 #pragma unroll
     for (int i = 0; i < kRpt; ++i) {
-        const int64_t r = r0 + 256 * i;
+        const int64_t r = r0 + kPT * i;
 #pragma unroll
         for (int c = 0; c < kQB; ++c) a[i][c] = (r < p.m && c < p.b) ? p.A[r + c * p.lda] : 0.0;
     }
@@ -141,7 +157,7 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
         bool below[kRpt];
 #pragma unroll
         for (int i = 0; i < kRpt; ++i) {
-            const int64_t r = r0 + 256 * i;
+            const int64_t r = r0 + kPT * i;
             below[i] = r > j && r < p.m;
             double x = 0.0;
 #pragma unroll
@@ -174,24 +190,21 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
         double s_c = 0.0, s_j = 0.0;  // d_c and sigma, for threads tid < kQB
         if (p.P == 1) {
             if (tid < kQB) {
-                s_c = ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) +
-                      ((red[4][tid] + red[5][tid]) + (red[6][tid] + red[7][tid]));
-                s_j = ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) +
-                      ((red[4][j] + red[5][j]) + (red[6][j] + red[7][j]));
+                s_c = sum_groups(red, tid);
+                s_j = sum_groups(red, j);
                 prow[1][tid] = prow[0][tid];
             }
         } else {
             if (tid < kQB) {
-                const double part = ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) +
-                                    ((red[4][tid] + red[5][tid]) + (red[6][tid] + red[7][tid]));
+                const double part = sum_groups(red, tid);
                 store_dev(p.xch + ((int64_t)j * p.P + wg) * kQB + tid, publishable(part));
                 if (wg == 0) store_dev(xrow + (int64_t)j * kQB + tid, publishable(prow[0][tid]));
             }
-            // gather: thread (g, c) adds the partials of workgroups g, g + 8, ...
+            // gather: thread (g, c) adds the partials of workgroups g, g + kGroups, ...
             const int c = tid & (kQB - 1), g = tid >> 5;
             double s = 0.0;
             bool ok = true;
-            for (int q = g; q < p.P && ok; q += 8) {
+            for (int q = g; q < p.P && ok; q += kGroups) {
                 double v = 0.0;
                 ok = poll_slot(p.xch + ((int64_t)j * p.P + q) * kQB + c, p.info, &v);
                 s += v;
@@ -206,10 +219,8 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
             __syncthreads();
             if (s_bad) return;
             if (tid < kQB) {
-                s_c = ((grp[0][tid] + grp[1][tid]) + (grp[2][tid] + grp[3][tid])) +
-                      ((grp[4][tid] + grp[5][tid]) + (grp[6][tid] + grp[7][tid]));
-                s_j = ((grp[0][j] + grp[1][j]) + (grp[2][j] + grp[3][j])) +
-                      ((grp[4][j] + grp[5][j]) + (grp[6][j] + grp[7][j]));
+                s_c = sum_groups(grp, tid);
+                s_j = sum_groups(grp, j);
             }
         }
         if (tid < kQB) {  // the scalars of step j, the same in every thread and workgroup
@@ -242,7 +253,7 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
         // A(j, j) := beta, as A(j, c) keep_c - tau w_c + beta (1 - keep_c)
 #pragma unroll
         for (int i = 0; i < kRpt; ++i) {
-            const int64_t r = r0 + 256 * i;
+            const int64_t r = r0 + kPT * i;
             if (below[i]) {
                 const double v = xm[i] * den;
 #pragma unroll
@@ -255,7 +266,7 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
     }
 #pragma unroll
     for (int i = 0; i < kRpt; ++i) {
-        const int64_t r = r0 + 256 * i;
+        const int64_t r = r0 + kPT * i;
         if (r >= p.m) continue;
 #pragma unroll
         for (int c = 0; c < kQB; ++c) {
@@ -268,7 +279,7 @@ __global__ __launch_bounds__(256) void k_qr_panel(QrPanelP p) {
         }
     }
     if (wg == 0) {
-        for (int64_t e = tid; e < p.ro * p.b; e += 256) {
+        for (int64_t e = tid; e < p.ro * p.b; e += kPT) {
             const int64_t rr = e % p.ro, c = e / p.ro;
             p.Vs[rr + c * p.ldvs] = 0.0;
             p.Vt[c + rr * p.ldvt] = 0.0;
@@ -490,7 +501,7 @@ int launch_qr_panel(int64_t m, int b, double *A, int64_t lda, double *tau, doubl
         FLAME_CHECK_LAUNCH();
     }
     const int tr = trace_begin(FLAME_KC_CHOL, s);
-    hipLaunchKernelGGL(k_qr_panel, dim3((unsigned)p.P), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_qr_panel, dim3((unsigned)p.P), dim3(kPT), 0, s, p);
     FLAME_CHECK_LAUNCH();
     trace_end(tr, s, 4.0 * (double)m * b * b, 8.0 * (double)m * b * 4);
     return FLAME_OK;
