@@ -58,6 +58,10 @@ struct QrPanelP {
     int64_t ldvt;
     int64_t ro;
     double *xch;  // b * P * kQB partial sums, then b * kQB pivot-row values
+    // the other exchange buffer, reset here for the next panel (whose
+    // workgroups are no more than these), nreset doubles; none when P = 1
+    double *xnext;
+    int64_t nreset;
     int32_t *info;
 };
 
@@ -139,6 +143,8 @@ __global__ __launch_bounds__(kPT) void k_qr_panel(QrPanelP p) {
     __shared__ int s_bad;
     if (*p.info != 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wg = blockIdx.x;
+    for (int64_t e = (int64_t)wg * kPT + tid; e < p.nreset; e += (int64_t)p.P * kPT)
+        p.xnext[e] = __longlong_as_double((long long)kEmpty);
     const int64_t r0 = (int64_t)wg * kWgRows + tid;
     double a[kRpt][kQB];
 #pragma unroll
@@ -302,22 +308,38 @@ __global__ __launch_bounds__(256) void k_qr_zero2(int64_t rows, double *__restri
 // at part + s M N (column-major, ld M); the caller adds the slices in order.
 // Rows staged through LDS 32 at a time; thread (ti, tj) forms the outputs
 // (ti + 16 a, tj + 16 b), a < TM, b < TN (16 TM >= M, 16 TN >= N).
+struct SkinnyJob {
+    int M, N;  // <= kOB
+    int64_t K, kc;
+    const double *X;
+    int64_t ldx;
+    const double *Y;
+    int64_t ldy;
+    double *part;
+};
+
+// LDS of a skinny product: 32 staged rows of X and of Y (TM, TN <= 8).
+struct SkinnyLds {
+    double xs[32][kOB + 1];
+    double ys[32][kOB + 1];
+};
+
+// Slice s of the skinny C = X^T Y (M, N <= 128, K long): X(K_s, :)^T Y(K_s, :)
+// over the slice K_s of kc rows, stored at part + s M N (column-major, ld M);
+// the caller adds the slices in order.  Rows staged through LDS 32 at a time,
+// the next 32 loaded into registers while the current ones are used; thread
+// (ti, tj) forms the outputs (ti + 16 a, tj + 16 b), a < TM, b < TN
+// (16 TM >= M, 16 TN >= N).
 template <int TM, int TN>
-__global__ __launch_bounds__(256) void k_qr_skinny(int M, int N, int64_t K, int64_t kc, const double *__restrict__ X,
-                                                   int64_t ldx, const double *__restrict__ Y, int64_t ldy,
-                                                   double *__restrict__ part, const int32_t *__restrict__ info) {
-    __shared__ double xs[32][16 * TM + 1];
-    __shared__ double ys[32][16 * TN + 1];
-    if (*info != 0) return;
+__device__ __forceinline__ void skinny_slice(const SkinnyJob &q, int64_t s, SkinnyLds &L) {
     const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
     const int kr = tid & 31, cg = tid >> 5;  // staging: row kr of the 32, columns cg + 8 u
-    const int64_t k0 = (int64_t)blockIdx.x * kc, k1 = min(K, k0 + kc);
+    const int64_t k0 = s * q.kc, k1 = min(q.K, k0 + q.kc);
     double acc[TM][TN];
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = 0.0;
-    // the next 32 rows are loaded into registers while the current ones are used
     double xr[2 * TM], yr[2 * TN];
     auto fetch = [&](int64_t kb) {
         const int64_t k = kb + kr;
@@ -325,29 +347,29 @@ __global__ __launch_bounds__(256) void k_qr_skinny(int M, int N, int64_t K, int6
 #pragma unroll
         for (int u = 0; u < 2 * TM; ++u) {
             const int i = cg + 8 * u;
-            xr[u] = (in && i < M) ? X[k + i * ldx] : 0.0;
+            xr[u] = (in && i < q.M) ? q.X[k + i * q.ldx] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 2 * TN; ++u) {
             const int j = cg + 8 * u;
-            yr[u] = (in && j < N) ? Y[k + j * ldy] : 0.0;
+            yr[u] = (in && j < q.N) ? q.Y[k + j * q.ldy] : 0.0;
         }
     };
     fetch(k0);
     for (int64_t kb = k0; kb < k1; kb += 32) {
 #pragma unroll
-        for (int u = 0; u < 2 * TM; ++u) xs[kr][cg + 8 * u] = xr[u];
+        for (int u = 0; u < 2 * TM; ++u) L.xs[kr][cg + 8 * u] = xr[u];
 #pragma unroll
-        for (int u = 0; u < 2 * TN; ++u) ys[kr][cg + 8 * u] = yr[u];
+        for (int u = 0; u < 2 * TN; ++u) L.ys[kr][cg + 8 * u] = yr[u];
         __syncthreads();
         if (kb + 32 < k1) fetch(kb + 32);
 #pragma unroll 4
-        for (int q = 0; q < 32; ++q) {
+        for (int r = 0; r < 32; ++r) {
             double xv[TM], yv[TN];
 #pragma unroll
-            for (int a = 0; a < TM; ++a) xv[a] = xs[q][ti + 16 * a];
+            for (int a = 0; a < TM; ++a) xv[a] = L.xs[r][ti + 16 * a];
 #pragma unroll
-            for (int b = 0; b < TN; ++b) yv[b] = ys[q][tj + 16 * b];
+            for (int b = 0; b < TN; ++b) yv[b] = L.ys[r][tj + 16 * b];
 #pragma unroll
             for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -355,14 +377,25 @@ __global__ __launch_bounds__(256) void k_qr_skinny(int M, int N, int64_t K, int6
         }
         __syncthreads();
     }
-    double *dst = part + (int64_t)blockIdx.x * M * N;
+    double *dst = q.part + s * q.M * q.N;
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
             const int i = ti + 16 * a, j = tj + 16 * b;
-            if (i < M && j < N) dst[i + (int64_t)j * M] = acc[a][b];
+            if (i < q.M && j < q.N) dst[i + (int64_t)j * q.M] = acc[a][b];
         }
+}
+
+// One or two skinny products in one launch: workgroups [0, S1) take the
+// slices of the first, the others those of the second.
+template <int TM1, int TN1, int TM2, int TN2>
+__global__ __launch_bounds__(256) void k_qr_skinny(SkinnyJob q1, int S1, SkinnyJob q2,
+                                                   const int32_t *__restrict__ info) {
+    __shared__ SkinnyLds L;
+    if (*info != 0) return;
+    if ((int)blockIdx.x < S1) skinny_slice<TM1, TN1>(q1, blockIdx.x, L);
+    else skinny_slice<TM2, TN2>(q2, blockIdx.x - S1, L);
 }
 
 // From the S partial products of V^T V_p (j1 x b, b = j1 - j0 <= kQB,
@@ -477,8 +510,17 @@ __global__ __launch_bounds__(kOB) void k_qr_wy(int S, int kb, int nc, const doub
 
 int qr_panel_rows() { return kWgRows; }
 
+int launch_qr_fill_empty(int64_t count, double *p, hipStream_t s) {
+    if (count <= 0) return FLAME_OK;
+    hipLaunchKernelGGL(k_qr_fill_empty, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, p);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+// xch must hold empty slots on entry (launch_qr_fill_empty once, then each
+// panel resets xnext for the one after it).
 int launch_qr_panel(int64_t m, int b, double *A, int64_t lda, double *tau, double *Vs, int64_t ldvs, double *Vt,
-                    int64_t ldvt, int64_t ro, double *xch, int32_t *info, hipStream_t s) {
+                    int64_t ldvt, int64_t ro, double *xch, double *xnext, int32_t *info, hipStream_t s) {
     if (m <= 0 || b <= 0) return FLAME_OK;
     if (b > kQB || m < b) return FLAME_ERR_UNSUPPORTED;
     QrPanelP p;
@@ -494,12 +536,9 @@ int launch_qr_panel(int64_t m, int b, double *A, int64_t lda, double *tau, doubl
     p.ldvt = ldvt;
     p.ro = ro;
     p.xch = xch;
+    p.xnext = xnext;
+    p.nreset = p.P > 1 ? (int64_t)kQB * p.P * kQB + (int64_t)kQB * kQB : 0;
     p.info = info;
-    if (p.P > 1) {
-        const int64_t count = (int64_t)b * p.P * kQB + (int64_t)b * kQB;
-        hipLaunchKernelGGL(k_qr_fill_empty, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, xch);
-        FLAME_CHECK_LAUNCH();
-    }
     const int tr = trace_begin(FLAME_KC_CHOL, s);
     hipLaunchKernelGGL(k_qr_panel, dim3((unsigned)p.P), dim3(kPT), 0, s, p);
     FLAME_CHECK_LAUNCH();
@@ -523,29 +562,49 @@ int qr_slices(int64_t K, int smax, int64_t *kc) {
 }
 
 namespace {
-template <int TM, int TN>
-void skinny_launch(int S, int M, int N, int64_t K, int64_t kc, const double *X, int64_t ldx, const double *Y,
-                   int64_t ldy, double *part, const int32_t *info, hipStream_t s) {
-    hipLaunchKernelGGL((k_qr_skinny<TM, TN>), dim3((unsigned)S), dim3(256), 0, s, M, N, K, kc, X, ldx, Y, ldy, part,
+int tiles16(int v) { return v <= 32 ? 2 : (v <= 64 ? 4 : 8); }
+
+template <int TM1, int TN1, int TM2, int TN2>
+void skinny_go(const SkinnyJob &q1, int S1, const SkinnyJob &q2, int S2, const int32_t *info, hipStream_t s) {
+    hipLaunchKernelGGL((k_qr_skinny<TM1, TN1, TM2, TN2>), dim3((unsigned)(S1 + S2)), dim3(256), 0, s, q1, S1, q2,
                        info);
 }
-template <int TM>
-void skinny_n(int tn, int S, int M, int N, int64_t K, int64_t kc, const double *X, int64_t ldx, const double *Y,
-              int64_t ldy, double *part, const int32_t *info, hipStream_t s) {
-    if (tn <= 2) skinny_launch<TM, 2>(S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
-    else if (tn <= 4) skinny_launch<TM, 4>(S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
-    else skinny_launch<TM, 8>(S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
+template <int TM1, int TN1, int TM2>
+void skinny_tn2(int tn2, const SkinnyJob &q1, int S1, const SkinnyJob &q2, int S2, const int32_t *info,
+                hipStream_t s) {
+    if (tn2 == 2) skinny_go<TM1, TN1, TM2, 2>(q1, S1, q2, S2, info, s);
+    else if (tn2 == 4) skinny_go<TM1, TN1, TM2, 4>(q1, S1, q2, S2, info, s);
+    else skinny_go<TM1, TN1, TM2, 8>(q1, S1, q2, S2, info, s);
 }
 }  // namespace
 
-int launch_qr_skinny(int S, int M, int N, int64_t K, int64_t kc, const double *X, int64_t ldx, const double *Y,
-                     int64_t ldy, double *part, const int32_t *info, hipStream_t s) {
-    if (M <= 0 || N <= 0) return FLAME_OK;
-    if (M > kOB || N > kOB || K <= 0) return FLAME_ERR_UNSUPPORTED;
-    const int tm = (M + 15) / 16, tn = (N + 15) / 16;
-    if (tm <= 2) skinny_n<2>(tn, S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
-    else if (tm <= 4) skinny_n<4>(tn, S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
-    else skinny_n<8>(tn, S, M, N, K, kc, X, ldx, Y, ldy, part, info, s);
+// The Gram columns of a panel (M1 x N1, N1 <= 32) and, when S2 > 0, the
+// product V_p^T C of its update (M2 = 32 x N2), in one launch; or one product
+// alone (S2 = 0).  Shapes the driver uses: (M1 <= 128, N1 <= 32) with
+// (32, <= 128), and (<= 128, <= 128) alone.
+int launch_qr_skinny(int S1, int M1, int N1, int64_t K1, int64_t kc1, const double *X1, int64_t ldx1,
+                     const double *Y1, int64_t ldy1, double *part1, int S2, int M2, int N2, int64_t K2, int64_t kc2,
+                     const double *X2, int64_t ldx2, const double *Y2, int64_t ldy2, double *part2,
+                     const int32_t *info, hipStream_t s) {
+    if (M1 <= 0 || N1 <= 0 || S1 <= 0) return FLAME_OK;
+    if (M1 > kOB || N1 > kOB || K1 <= 0) return FLAME_ERR_UNSUPPORTED;
+    SkinnyJob q1{M1, N1, K1, kc1, X1, ldx1, Y1, ldy1, part1};
+    SkinnyJob q2{M2, N2, K2, kc2, X2, ldx2, Y2, ldy2, part2};
+    if (S2 > 0 && (M2 <= 0 || N2 <= 0)) S2 = 0;
+    if (S2 > 0 && (N1 > kQB || M2 > kQB || N2 > kOB || K2 <= 0)) return FLAME_ERR_UNSUPPORTED;
+    const int tm1 = tiles16(M1), tn1 = tiles16(N1);
+    if (S2 > 0) {  // the panel's pair: TN1 = 2, TM2 = 2
+        const int tn2 = tiles16(N2);
+        if (tm1 == 2) skinny_tn2<2, 2, 2>(tn2, q1, S1, q2, S2, info, s);
+        else if (tm1 == 4) skinny_tn2<4, 2, 2>(tn2, q1, S1, q2, S2, info, s);
+        else skinny_tn2<8, 2, 2>(tn2, q1, S1, q2, S2, info, s);
+    } else if (tn1 == 2) {  // one product (the second shape is not used)
+        if (tm1 == 2) skinny_go<2, 2, 2, 2>(q1, S1, q2, 0, info, s);
+        else if (tm1 == 4) skinny_go<4, 2, 2, 2>(q1, S1, q2, 0, info, s);
+        else skinny_go<8, 2, 2, 2>(q1, S1, q2, 0, info, s);
+    } else {
+        skinny_go<8, 8, 2, 2>(q1, S1, q2, 0, info, s);
+    }
     FLAME_CHECK_LAUNCH();
     return FLAME_OK;
 }

@@ -24,12 +24,15 @@
 namespace flame {
 
 int qr_panel_rows();
+int launch_qr_fill_empty(int64_t count, double *p, hipStream_t s);
 int launch_qr_panel(int64_t m, int b, double *A, int64_t lda, double *tau, double *Vs, int64_t ldvs, double *Vt,
-                    int64_t ldvt, int64_t ro, double *xch, int32_t *info, hipStream_t s);
+                    int64_t ldvt, int64_t ro, double *xch, double *xnext, int32_t *info, hipStream_t s);
 int launch_qr_zero2(int64_t rows, int64_t cols, double *d0, double *d1, int64_t ldd, hipStream_t s);
 int qr_slices(int64_t K, int smax, int64_t *kc);
-int launch_qr_skinny(int S, int M, int N, int64_t K, int64_t kc, const double *X, int64_t ldx, const double *Y,
-                     int64_t ldy, double *part, const int32_t *info, hipStream_t s);
+int launch_qr_skinny(int S1, int M1, int N1, int64_t K1, int64_t kc1, const double *X1, int64_t ldx1,
+                     const double *Y1, int64_t ldy1, double *part1, int S2, int M2, int N2, int64_t K2, int64_t kc2,
+                     const double *X2, int64_t ldx2, const double *Y2, int64_t ldy2, double *part2,
+                     const int32_t *info, hipStream_t s);
 int launch_qr_gt(int S, int j0, int j1, const double *part, const double *tau, double *T, int64_t ldt,
                  const int32_t *info, hipStream_t s);
 int launch_qr_wy(int S, int kb, int nc, const double *part, const double *T, int64_t ldt, double *Y,
@@ -56,7 +59,8 @@ struct QrWork {
     double *split;        // split-K partial products of the side stream
     double *part;         // skinny-product slices (main stream)
     double *gpart;        // Gram slices of a panel (main stream)
-    double *xch;
+    double *xch[2];  // panel exchange slots, alternate panels
+    int64_t nxch;
 };
 
 // C -= X^T Y with a long K: the largest multiple of 32 of K split over
@@ -81,7 +85,8 @@ int apply_qt_narrow(const QrWork &w, int64_t mr, int64_t nc, int kb, const doubl
     if (nc <= 0) return FLAME_OK;
     int64_t kc = 0;
     const int S = qr_slices(mr, kSlices, &kc);
-    int rc = launch_qr_skinny(S, kb, (int)nc, mr, kc, V, w.ldvs, C, ldc, w.part, info, s);
+    int rc = launch_qr_skinny(S, kb, (int)nc, mr, kc, V, w.ldvs, C, ldc, w.part, 0, 0, 0, 0, 0, nullptr, 0, nullptr,
+                              0, nullptr, info, s);
     if (!rc) rc = launch_qr_wy(S, kb, (int)nc, w.part, Tb, kOB, w.Y[0], info, s);
     if (!rc) rc = launch_gemm_tn(Prec::F64, true, false, mr, nc, kb, Vt, kOB, w.Y[0], kOB, C, ldc, info, s);
     return rc;
@@ -121,7 +126,7 @@ int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *tau, int32_t
     const size_t xch = (size_t)kIB * pmax * kIB + (size_t)kIB * kIB;
     const size_t per_buf = (size_t)ldvs * kOB + (size_t)kOB * (size_t)m + (size_t)kOB * kOB;
     const size_t part = (size_t)kSlices * kOB * kOB, gpart = (size_t)kGramSlices * kOB * kIB;
-    const size_t doubles = 2 * per_buf + 4 * (size_t)kOB * (size_t)n + part + gpart + xch;
+    const size_t doubles = 2 * per_buf + 4 * (size_t)kOB * (size_t)n + part + gpart + 2 * xch;
     void *ws = nullptr;
     rc = ctx_workspace(ctx, kWsQr, doubles * sizeof(double), &ws);
     if (rc) return rc;
@@ -144,7 +149,11 @@ int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *tau, int32_t
     }
     w.part = p;
     w.gpart = p + part;
-    w.xch = w.gpart + gpart;
+    w.xch[0] = w.gpart + gpart;
+    w.xch[1] = w.xch[0] + xch;
+    w.nxch = (int64_t)xch;
+    rc = launch_qr_fill_empty(2 * w.nxch, w.xch[0], s);
+    if (rc) return rc;
     w.split = static_cast<double *>(split);
     hipStream_t side = ctx_side_stream(ctx);
     hipEvent_t ev_next = ctx_event(ctx, 2);  // main: the next block's columns updated, V and T final
@@ -160,6 +169,7 @@ static int qr_blocks(const QrWork &w, int64_t m, int64_t n, double *A, int64_t l
                      hipStream_t s, hipStream_t side, hipEvent_t ev_next, hipEvent_t ev_rest, bool *side_pending) {
     const int64_t ldvs = w.ldvs;
     int rc = FLAME_OK;
+    int64_t np = 0;  // panels so far (which exchange buffer)
     for (int64_t k = 0, blk = 0; k < n; k += kOB, ++blk) {
         const QrBuf &B = w.buf[blk & 1];
         const int nbk = (int)std::min<int64_t>(kOB, n - k);
@@ -169,19 +179,26 @@ static int qr_blocks(const QrWork &w, int64_t m, int64_t n, double *A, int64_t l
             const int64_t mi = mk - i0;
             double *Ap = A + (k + i0) + (k + i0) * lda;
             rc = launch_qr_panel(mi, bi, Ap, lda, tau + k + i0, B.Vs + (int64_t)i0 * ldvs, ldvs, B.Vt + i0, kOB, i0,
-                                 w.xch, info, s);
-            // V^T V_p (rows i0.. : V_p is zero above), then T's new columns
-            int64_t kc = 0;
+                                 w.xch[np & 1], w.xch[(np + 1) & 1], info, s);
+            ++np;
+            // in one launch: V^T V_p (rows i0..: V_p is zero above) and, for
+            // the block's columns right of the panel, V_p^T C
+            const int64_t nc = nbk - i0 - bi;
+            const double *Vp = B.Vs + i0 + (int64_t)i0 * ldvs;
+            double *Cp = Ap + (int64_t)bi * lda;
+            int64_t kc = 0, kcw = 0;
             const int S = qr_slices(mi, kGramSlices, &kc);
+            const int Sw = nc > 0 ? qr_slices(mi, kSlices, &kcw) : 0;
             if (!rc)
-                rc = launch_qr_skinny(S, i0 + bi, bi, mi, kc, B.Vs + i0, ldvs, B.Vs + i0 + (int64_t)i0 * ldvs, ldvs,
-                                      w.gpart, info, s);
+                rc = launch_qr_skinny(S, i0 + bi, bi, mi, kc, B.Vs + i0, ldvs, Vp, ldvs, w.gpart, Sw, bi, (int)nc, mi,
+                                      kcw, Vp, ldvs, Cp, lda, w.part, info, s);
+            // T's new columns, then C := (I - V_p T_pp^T V_p^T) C
             if (!rc) rc = launch_qr_gt(S, i0, i0 + bi, w.gpart, tau + k, B.T, kOB, info, s);
-            // the block's columns right of the panel
-            if (!rc)
-                rc = apply_qt_narrow(w, mi, nbk - i0 - bi, bi, B.Vs + i0 + (int64_t)i0 * ldvs,
-                                     B.Vt + i0 + (int64_t)i0 * kOB, B.T + i0 + (int64_t)i0 * kOB,
-                                     Ap + (int64_t)bi * lda, lda, info, s);
+            if (!rc && nc > 0)
+                rc = launch_qr_wy(Sw, bi, (int)nc, w.part, B.T + i0 + (int64_t)i0 * kOB, kOB, w.Y[0], info, s);
+            if (!rc && nc > 0)
+                rc = launch_gemm_tn(Prec::F64, true, false, mi, nc, bi, B.Vt + i0 + (int64_t)i0 * kOB, kOB, w.Y[0],
+                                    kOB, Cp, lda, info, s);
             if (rc) return rc;
         }
         const int64_t rest = n - k - nbk;
