@@ -37,6 +37,7 @@ constexpr int kRpt = 1;                  // panel rows per thread
 constexpr int kWgRows = kPT * kRpt;      // panel rows per workgroup
 constexpr int kGroups = kPT / 32;        // half-wavefronts
 constexpr int kOB = 128;                 // outer block (order of T)
+constexpr int kGramMax = 16;             // K slices of the Gram product at most
 constexpr long long kQrSpin = 1LL << 22; // sleep rounds before a wait gives up
 // The empty-slot marker: a signalling NaN.  Arithmetic never produces one and
 // published values are canonicalized (any NaN becomes the quiet NaN), so a
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(256) void k_qr_skinny(SkinnyJob q1, int S1, SkinnyJ
 // One workgroup.  T22: row i of T22 depends only on row i and on V2^T V2, so
 // each row is formed by one thread from its own registers, no barriers; then
 // the two products through LDS.
-__global__ __launch_bounds__(256) void k_qr_gt(int S, int j0, int j1, const double *__restrict__ part,
+__global__ __launch_bounds__(1024) void k_qr_gt(int S, int j0, int j1, const double *__restrict__ part,
                                                const double *__restrict__ tau, double *__restrict__ T, int64_t ldt,
                                                const int32_t *__restrict__ info) {
     constexpr int kH = kOB - kQB;          // rows of T12 at most
@@ -418,14 +419,19 @@ __global__ __launch_bounds__(256) void k_qr_gt(int S, int j0, int j1, const doub
     __shared__ double tv[kQB];
     if (*info != 0) return;
     const int tid = threadIdx.x, b = j1 - j0;
-    for (int e = tid; e < j1 * b; e += 256) {
+    // the slices (S <= kGramMax) of each element are all loaded before they
+    // are added, in slice order
+    for (int e = tid; e < j1 * b; e += 1024) {
         const int r = e % j1, c = e / j1;
+        double v[kGramMax];
+#pragma unroll
+        for (int q = 0; q < kGramMax; ++q) v[q] = q < S ? part[(int64_t)q * j1 * b + e] : 0.0;
         double sum = 0.0;
-#pragma unroll 8
-        for (int q = 0; q < S; ++q) sum += part[(int64_t)q * j1 * b + e];
+#pragma unroll
+        for (int q = 0; q < kGramMax; ++q) sum += v[q];
         g[r][c] = sum;
     }
-    for (int e = tid; e < j0 * j0; e += 256) {
+    for (int e = tid; e < j0 * j0; e += 1024) {
         const int r = e % j0, c = e / j0;
         t11[r][c] = r <= c ? T[r + (int64_t)c * ldt] : 0.0;
     }
@@ -447,7 +453,7 @@ __global__ __launch_bounds__(256) void k_qr_gt(int S, int j0, int j1, const doub
     __syncthreads();
     if (j0 > 0) {
         // thread (r, h): row r, columns 8 h .. 8 h + 7, eight independent sums
-        for (int e = tid; e < j0 * 4; e += 256) {  // X = (V1^T V2) T22
+        for (int e = tid; e < j0 * 4; e += 1024) {  // X = (V1^T V2) T22
             const int r = e % j0, h = e / j0;
             double acc[8];
 #pragma unroll
@@ -461,7 +467,7 @@ __global__ __launch_bounds__(256) void k_qr_gt(int S, int j0, int j1, const doub
             for (int c = 0; c < 8; ++c) x[r][8 * h + c] = acc[c];
         }
         __syncthreads();
-        for (int e = tid; e < j0 * 4; e += 256) {  // T12 = -T11 X
+        for (int e = tid; e < j0 * 4; e += 1024) {  // T12 = -T11 X
             const int r = e % j0, h = e / j0;
             double acc[8];
 #pragma unroll
@@ -477,7 +483,7 @@ __global__ __launch_bounds__(256) void k_qr_gt(int S, int j0, int j1, const doub
         }
     }
     // T22 and zeros below it (the rows up to kOB: the products read the whole block)
-    for (int e = tid; e < (kOB - j0) * b; e += 256) {
+    for (int e = tid; e < (kOB - j0) * b; e += 1024) {
         const int r = e % (kOB - j0), c = e / (kOB - j0);
         T[(j0 + r) + (int64_t)(j0 + c) * ldt] = r < kQB ? t22[r][c] : 0.0;
     }
@@ -613,7 +619,8 @@ int launch_qr_gt(int S, int j0, int j1, const double *part, const double *tau, d
                  const int32_t *info, hipStream_t s) {
     if (j1 <= j0) return FLAME_OK;
     if (j0 < 0 || j1 > kOB || j1 - j0 > kQB) return FLAME_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(k_qr_gt, dim3(1), dim3(256), 0, s, S, j0, j1, part, tau, T, ldt, info);
+    if (S > kGramMax) return FLAME_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_qr_gt, dim3(1), dim3(1024), 0, s, S, j0, j1, part, tau, T, ldt, info);
     FLAME_CHECK_LAUNCH();
     return FLAME_OK;
 }
