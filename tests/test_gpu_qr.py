@@ -91,6 +91,22 @@ def test_qr_graded_columns():
     assert np.all(np.max(np.abs(R - Ro), axis=1) <= 1e-11 * rows)
 
 
+def test_qr_tall_many_workgroups():
+    # ceil(70000 / 512) = 137 workgroups exchange their sums for every column
+    m, n = 70000, 40
+    print(f"[qr] m={m} n={n}", flush=True)
+    A = inputs.qr_matrix(m, n, seed=13)
+    T = to_dev(A)
+    tau, info = fl.qr(T)
+    W = to_host(T)
+    assert int(info.item()) == 0
+    Wo, to = oracle.geqrf(A)
+    scale = float(np.max(np.abs(np.triu(Wo[:n]))))
+    assert np.max(np.abs(np.triu(W[:n]) - np.triu(Wo[:n]))) <= 1e-12 * scale
+    assert np.max(np.abs(np.tril(W, -1) - np.tril(Wo, -1))) <= 1e-12
+    assert np.max(np.abs(tau.cpu().numpy() - to)) <= 1e-12
+
+
 def test_qr_repeat_is_bitwise_identical():
     A = inputs.qr_matrix(1500, 700, seed=2)
     T1, T2 = to_dev(A), to_dev(A)
