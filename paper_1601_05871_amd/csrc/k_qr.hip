@@ -37,7 +37,7 @@ constexpr int kRpt = 1;                  // panel rows per thread
 constexpr int kWgRows = kPT * kRpt;      // panel rows per workgroup
 constexpr int kGroups = kPT / 32;        // half-wavefronts
 constexpr int kOB = 128;                 // outer block (order of T)
-constexpr int kGramMax = 16;             // K slices of the Gram product at most
+constexpr int kGramMax = 32;             // K slices of the Gram product at most
 constexpr long long kQrSpin = 1LL << 22; // sleep rounds before a wait gives up
 // The empty-slot marker: a signalling NaN.  Arithmetic never produces one and
 // published values are canonicalized (any NaN becomes the quiet NaN), so a
@@ -341,8 +341,9 @@ __device__ __forceinline__ void skinny_slice(const SkinnyJob &q, int64_t s, Skin
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = 0.0;
-    double xr[2 * TM], yr[2 * TN];
-    auto fetch = [&](int64_t kb) {
+    // two groups of 32 rows in flight in registers while one is used
+    double xa[2 * TM], ya[2 * TN], xb[2 * TM], yb[2 * TN];
+    auto fetch = [&](double *xr, double *yr, int64_t kb) {
         const int64_t k = kb + kr;
         const bool in = k < k1;
 #pragma unroll
@@ -356,14 +357,14 @@ __device__ __forceinline__ void skinny_slice(const SkinnyJob &q, int64_t s, Skin
             yr[u] = (in && j < q.N) ? q.Y[k + j * q.ldy] : 0.0;
         }
     };
-    fetch(k0);
-    for (int64_t kb = k0; kb < k1; kb += 32) {
+    auto use = [&](const double *xr, const double *yr) {
 #pragma unroll
         for (int u = 0; u < 2 * TM; ++u) L.xs[kr][cg + 8 * u] = xr[u];
 #pragma unroll
         for (int u = 0; u < 2 * TN; ++u) L.ys[kr][cg + 8 * u] = yr[u];
         __syncthreads();
-        if (kb + 32 < k1) fetch(kb + 32);
+    };
+    auto multiply = [&]() {
 #pragma unroll 4
         for (int r = 0; r < 32; ++r) {
             double xv[TM], yv[TN];
@@ -377,6 +378,18 @@ __device__ __forceinline__ void skinny_slice(const SkinnyJob &q, int64_t s, Skin
                 for (int b = 0; b < TN; ++b) acc[a][b] += xv[a] * yv[b];
         }
         __syncthreads();
+    };
+    fetch(xa, ya, k0);
+    fetch(xb, yb, k0 + 32);
+    for (int64_t kb = k0; kb < k1; kb += 64) {
+        use(xa, ya);
+        fetch(xa, ya, kb + 64);
+        multiply();
+        if (kb + 32 < k1) {  // uniform
+            use(xb, yb);
+            fetch(xb, yb, kb + 96);
+            multiply();
+        }
     }
     double *dst = q.part + s * q.M * q.N;
 #pragma unroll

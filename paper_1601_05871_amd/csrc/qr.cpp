@@ -44,7 +44,7 @@ constexpr int kIB = 32;        // panel
 constexpr int kOB = 128;       // outer block
 constexpr int kSideCus = 16;   // compute units the side stream's large product leaves to the panels
 constexpr int kSlices = 128;   // K slices of a skinny product at most
-constexpr int kGramSlices = 16;  // (k_qr_gt adds at most 16)
+constexpr int kGramSlices = 32;  // (k_qr_gt adds at most 32)
 
 struct QrBuf {  // one outer block's reflectors (two of them: the side stream reads one while the next is built)
     double *Vs;  // m x kOB, ld ldvs
