@@ -13,7 +13,8 @@
  *   - matrices are column-major: element (i, j) of A is A[i + j*lda];
  *   - only the upper triangle (i <= j) of a symmetric operand is read; only
  *     the upper triangle of A is written; the strictly lower triangle is never
- *     referenced;
+ *     referenced (except with FLAME_OPT_LOWER, and by flame_lu and flame_qr,
+ *     whose operands are general matrices, read and written whole);
  *   - pointers are DEVICE pointers unless marked "host"; the caller owns all
  *     memory it passes and the library never frees it;
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream);

@@ -10,7 +10,9 @@ fallback).
 
 Matrices are column-major: a 2-D torch tensor ``A`` with ``A.stride(0) == 1``
 and ``A.stride(1) == lda >= n`` (for a contiguous row-major tensor pass
-``A.mT``, or use :func:`colmajor`).  Only the upper triangle is read/written.
+``A.mT``, or use :func:`colmajor`).  Only the upper triangle is read/written
+(except by :func:`lu` and :func:`qr`, which factor general matrices, and
+with ``lower=True``).
 """
 from __future__ import annotations
 
