@@ -83,6 +83,8 @@ def main() -> int:
     ap.add_argument("--table-seeds", default="0,1,2")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="leave out the complex / LU / QR timings at n = 8192 of the default line")
     ap.add_argument("--batch", type=int, default=10000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -247,6 +249,13 @@ def main() -> int:
         result["batched"] = batched_leg(args, dev, fl, inputs, torch)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_leg(P, n, args.cpu_seconds)
+    if not args.no_extensions:
+        # the conclusion's extensions of the loop at n = 8192 (see --extensions)
+        recs = []
+        ext = argparse.Namespace(**vars(args))
+        ext.ext_ns, ext.ext_cases, ext.steps, ext.warmup, ext.no_cpu = "8192", "complex,lu,qr", 3, 1, True
+        extensions_mode(ext, dev, fl, inputs, torch, emit=recs.append)
+        result["extensions"] = {"n": 8192, "median_of": 3, "cases": recs}
     print(json.dumps(result), flush=True)
     return 0
 
@@ -541,7 +550,7 @@ def dag_mode(args, dev, fl, inputs, torch) -> int:
     return 0
 
 
-def extensions_mode(args, dev, fl, inputs, torch) -> int:
+def extensions_mode(args, dev, fl, inputs, torch, emit=None) -> int:
     """The loop's extensions the paper's conclusion lists: the complex
     Hermitian factorization A = U^H U (flame_factor on complex128, 4 n^3 / 3
     real flops) and the LU without pivoting (flame_lu, 2 n^3 / 3 flops), each
@@ -555,6 +564,12 @@ def extensions_mode(args, dev, fl, inputs, torch) -> int:
     import time
 
     import oracle
+
+    def out(rec):
+        if emit is None:
+            print(json.dumps(rec), flush=True)
+        else:
+            emit(rec)
 
     stream = torch.cuda.current_stream()
 
@@ -595,25 +610,22 @@ def extensions_mode(args, dev, fl, inputs, torch) -> int:
         if "qr" in cases and not cases & {"complex", "lu"}:
             G = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
             ms, err = timed(G.mT.contiguous().mT, lambda W: fl.qr(W)[1], qr_err)
-            print(json.dumps({"case": "qr_householder", "n": n, "ms": round(ms, 3),
-                              "tflops": round(4 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "gram_error": err}),
-                  flush=True)
+            out({"case": "qr_householder", "n": n, "ms": round(ms, 3),
+                 "tflops": round(4 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "gram_error": err})
             continue
         B = torch.randn(n, n, dtype=torch.complex128, device=dev, generator=g)
         P = B @ B.conj().T
         P.diagonal().copy_(P.diagonal().real + n)
         P = (torch.triu(P) + torch.triu(P, 1).conj().T).mT.contiguous().mT
         ms, err = timed(P, lambda W: fl.factor(W, variant=fl.VAR_RIGHT, nb=128), herm_err)
-        print(json.dumps({"case": "complex_hermitian", "n": n, "ms": round(ms, 3),
-                          "tflops": round(4 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "backward_error": err}),
-              flush=True)
+        out({"case": "complex_hermitian", "n": n, "ms": round(ms, 3),
+             "tflops": round(4 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "backward_error": err})
         del B, P
         G = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
         P = (G + 2.0 * (n + 1) * torch.eye(n, dtype=torch.float64, device=dev)).mT.contiguous().mT
         ms, err = timed(P, lambda W: fl.lu(W), lu_err)
-        print(json.dumps({"case": "lu_nopiv", "n": n, "ms": round(ms, 3),
-                          "tflops": round(2 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "backward_error": err}),
-              flush=True)
+        out({"case": "lu_nopiv", "n": n, "ms": round(ms, 3),
+             "tflops": round(2 * n ** 3 / 3 / (ms * 1e-3) / 1e12, 3), "backward_error": err})
         del G, P
         G = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
         P = G.mT.contiguous().mT
@@ -633,7 +645,7 @@ def extensions_mode(args, dev, fl, inputs, torch) -> int:
         except RuntimeError as e:
             rec["torch_geqrf_ms"] = None
             rec["torch_geqrf_error"] = str(e)[:120]
-        print(json.dumps(rec), flush=True)
+        out(rec)
         del G, P
         torch.cuda.empty_cache()
     if not args.no_cpu:
@@ -650,8 +662,8 @@ def extensions_mode(args, dev, fl, inputs, torch) -> int:
         t0 = time.perf_counter()
         oracle.geqrf(A)
         t_q = time.perf_counter() - t0
-        print(json.dumps({"case": "oracle", "n": n, "cores": 1, "complex_hermitian_s": round(t_z, 3),
-                          "lu_nopiv_s": round(t_l, 3), "qr_householder_s": round(t_q, 3)}), flush=True)
+        out({"case": "oracle", "n": n, "cores": 1, "complex_hermitian_s": round(t_z, 3),
+             "lu_nopiv_s": round(t_l, 3), "qr_householder_s": round(t_q, 3)})
     return 0
 
 
