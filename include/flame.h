@@ -177,7 +177,10 @@ int flame_lu(int32_t dtype, int64_t n, void *A, int64_t lda, int32_t *info, void
  *   A, lda device, column-major, lda >= max(1, m)
  *   tau    device, n doubles (output)
  *   info   device, one int32: 0, or 1 if a wait between the panel kernel's
- *          workgroups gave up (not expected; A and tau are then invalid)
+ *          workgroups gave up (not expected; A and tau are then invalid;
+ *          the environment variable FLAME_QR_SPIN_CAP bounds those waits in
+ *          sleep rounds, a negative value makes them give up at once, for
+ *          tests of this path)
  *   stream as for flame_factor
  * Device workspace of about 2 KB per row and column (V in two layouts, the
  * block products) plus the split-K buffer of the trailing product, allocated

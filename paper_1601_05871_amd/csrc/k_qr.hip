@@ -23,6 +23,7 @@
 // H_0 ... H_{k-1} = I - V T V^T column by column (T(j, j) = tau_j,
 // T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^T v_j) from the Gram matrix of V.
 #include <algorithm>
+#include <cstdlib>
 
 #include "dev_sync.h"
 #include "flame_internal.h"
@@ -63,6 +64,7 @@ struct QrPanelP {
     // workgroups are no more than these), nreset doubles; none when P = 1
     double *xnext;
     int64_t nreset;
+    long long spin_cap;  // bound of each wait in sleep rounds (< 0: give up at once)
     int32_t *info;
 };
 
@@ -70,9 +72,14 @@ __device__ __forceinline__ double publishable(double v) {
     return v != v ? __longlong_as_double(0x7FF8000000000000ll) : v;
 }
 
-// Waits (bounded) until *p holds a value; false when *stop is set or the
-// wait gives up (then *stop := 1).
-__device__ bool poll_slot(const double *p, int32_t *stop, double *out) {
+// Waits (bounded: cap sleep rounds) until *p holds a value; false when
+// *stop is set or the wait gives up (then *stop := 1).  cap < 0: gives up at
+// once (the host's way to exercise this path).
+__device__ bool poll_slot(const double *p, int32_t *stop, double *out, long long cap) {
+    if (cap < 0) {
+        store_dev(stop, 1);
+        return false;
+    }
     long long spins = 0;
     for (;;) {
         const double v = load_dev(p);
@@ -80,13 +87,11 @@ __device__ bool poll_slot(const double *p, int32_t *stop, double *out) {
             *out = v;
             return true;
         }
-        if ((++spins & 63) == 0) {  // the stop flag every 64 rounds: one load per round otherwise
-            if (load_dev(stop) != 0) return false;
-            if (spins > kQrSpin) {
-                store_dev(stop, 1);
-                return false;
-            }
+        if (++spins > cap) {
+            store_dev(stop, 1);
+            return false;
         }
+        if ((spins & 63) == 0 && load_dev(stop) != 0) return false;  // one load per round otherwise
         __builtin_amdgcn_s_sleep(1);
     }
 }
@@ -213,12 +218,12 @@ __global__ __launch_bounds__(kPT) void k_qr_panel(QrPanelP p) {
             bool ok = true;
             for (int q = g; q < p.P && ok; q += kGroups) {
                 double v = 0.0;
-                ok = poll_slot(p.xch + ((int64_t)j * p.P + q) * kQB + c, p.info, &v);
+                ok = poll_slot(p.xch + ((int64_t)j * p.P + q) * kQB + c, p.info, &v, p.spin_cap);
                 s += v;
             }
             if (ok && g == 0) {
                 double v = 0.0;
-                ok = poll_slot(xrow + (int64_t)j * kQB + c, p.info, &v);
+                ok = poll_slot(xrow + (int64_t)j * kQB + c, p.info, &v, p.spin_cap);
                 prow[1][c] = v;
             }
             grp[g][c] = s;
@@ -557,6 +562,10 @@ int launch_qr_panel(int64_t m, int b, double *A, int64_t lda, double *tau, doubl
     p.xch = xch;
     p.xnext = xnext;
     p.nreset = p.P > 1 ? (int64_t)kQB * p.P * kQB + (int64_t)kQB * kQB : 0;
+    // FLAME_QR_SPIN_CAP (environment): the waits' bound, for tests of the
+    // give-up path; kQrSpin otherwise
+    const char *cap = getenv("FLAME_QR_SPIN_CAP");
+    p.spin_cap = (cap != nullptr && *cap != '\0') ? atoll(cap) : kQrSpin;
     p.info = info;
     const int tr = trace_begin(FLAME_KC_CHOL, s);
     hipLaunchKernelGGL(k_qr_panel, dim3((unsigned)p.P), dim3(kPT), 0, s, p);

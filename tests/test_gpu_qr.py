@@ -107,6 +107,21 @@ def test_qr_tall_many_workgroups():
     assert np.max(np.abs(tau.cpu().numpy() - to)) <= 1e-12
 
 
+def test_qr_wait_give_up_is_reported_and_recovers(monkeypatch):
+    # the host makes every wait of the panel's exchange give up at once: info
+    # is set, the later kernels skip, nothing waits; the next call is whole
+    m, n = 1500, 64  # three workgroups exchange
+    A = inputs.qr_matrix(m, n, seed=21)
+    monkeypatch.setenv("FLAME_QR_SPIN_CAP", "-1")
+    _, info = fl.qr(to_dev(A))
+    assert int(info.item()) == 1
+    monkeypatch.delenv("FLAME_QR_SPIN_CAP")
+    T = to_dev(A)
+    tau, info = fl.qr(T)
+    assert int(info.item()) == 0
+    _check_against_oracle(A, to_host(T), tau.cpu().numpy())
+
+
 def test_qr_repeat_is_bitwise_identical():
     A = inputs.qr_matrix(1500, 700, seed=2)
     T1, T2 = to_dev(A), to_dev(A)
