@@ -19,9 +19,12 @@
 // of them and adds them in workgroup order, so that every workgroup derives
 // the same scalars bit for bit.  One workgroup (m <= 512) skips the exchange.
 //
-// k_qr_gt forms the upper triangular T of the block reflector
-// H_0 ... H_{k-1} = I - V T V^T column by column (T(j, j) = tau_j,
-// T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^T v_j) from the Gram matrix of V.
+// The rest serves the block form H_0 ... H_{k-1} = I - V T V^T (T upper
+// triangular, T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^T v_j):
+// k_qr_skinny forms products X^T Y with a long K as slices (the Gram columns
+// V^T V_p of a panel, V^T C of a block), k_qr_gt adds the Gram slices and
+// appends the panel's columns to T in block form, k_qr_wy adds the slices of
+// V^T C and forms Y = T^T V^T C for the update C -= V Y.
 #include <algorithm>
 #include <cstdlib>
 
@@ -309,11 +312,8 @@ __global__ __launch_bounds__(256) void k_qr_zero2(int64_t rows, double *__restri
     }
 }
 
-// Partial products of the skinny C -= X^T Y (M, N <= 128, K long): workgroup
-// s forms X(K_s, :)^T Y(K_s, :) over its slice K_s of kc rows and stores it
-// at part + s M N (column-major, ld M); the caller adds the slices in order.
-// Rows staged through LDS 32 at a time; thread (ti, tj) forms the outputs
-// (ti + 16 a, tj + 16 b), a < TM, b < TN (16 TM >= M, 16 TN >= N).
+// One skinny product X^T Y (X: K x M, Y: K x N, column-major), cut into
+// slices of kc rows whose products go to part + s M N.
 struct SkinnyJob {
     int M, N;  // <= kOB
     int64_t K, kc;
