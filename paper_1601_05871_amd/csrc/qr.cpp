@@ -4,19 +4,19 @@
 //
 //   for each outer block of 128 columns (the rows below it: V, T, the update):
 //     for each panel of 32 columns inside it:
-//       factor the panel into reflectors              k_qr_panel
-//       G(:, panel) := -V^T V_panel                   matrix-core product
-//       T(:, panel) from G and tau                    k_qr_t
-//       C := (I - V_p T_pp^T V_p^T) C for the block's columns right of the
-//            panel (three matrix-core products, below)
-//     A2 := (I - V T^T V^T) A2 for the columns right of the block
+//       factor the panel into reflectors                   k_qr_panel
+//       V^T V_p and V_p^T C (C: the block's columns right
+//         of the panel), as slices of one launch           k_qr_skinny
+//       T's new columns from the Gram slices and tau       k_qr_gt
+//       Y := T_pp^T V_p^T C from the slices                k_qr_wy
+//       C -= V_p Y                                         matrix cores
+//     the next block's columns: the same with the block's V and T
+//     the columns beyond it (side stream, one block ahead):
+//       W := 0 - V^T C (split over K), Y := 0 - T^T W, C -= V Y
 //
-// Q^T C = C - V T^T V^T C goes as
-//   W  := 0 - V^T C        (K = rows of C: split over K)
-//   Y  := 0 - T^T W        (= T^T V^T C)
-//   C  := C - (V^T)^T Y    (K = block width)
-// with V kept twice, as columns (Vs, for V^T C) and as rows (Vt, for V Y), so
-// that every product is the trailing-update kernel's C -= X^T Y.
+// Q^T C = (I - V T V^T)^T C = C - V T^T V^T C; V is kept twice, as columns
+// (Vs, for V^T C) and as rows (Vt, for V Y), so that the large products are
+// the trailing-update kernel's C -= X^T Y.
 #include <algorithm>
 
 #include "flame_internal.h"
