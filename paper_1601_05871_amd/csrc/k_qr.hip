@@ -136,6 +136,51 @@ __device__ __forceinline__ double sum_groups(const double (*t)[LD], int c) {
     return v[0];
 }
 
+// The panel step's live columns C0..31 (C0 = 16 once the first 16 are
+// final): the thread's row's share of d_c = x A(r, c), summed over each
+// half-wavefront by recursive halving into red[half-wavefront][c].
+template <int C0>
+__device__ __forceinline__ void step_sums(const double (&a)[kQB], double xm, int tid, int lane,
+                                          double (*red)[kQB]) {
+    constexpr int L = kQB - C0;
+    double d[L];
+#pragma unroll
+    for (int c = 0; c < L; ++c) d[c] = xm * a[C0 + c];
+    if constexpr (L == 32) {  // afterwards lane l holds column l & 31 of its half's 32 lanes
+        halve<16, 16>(d, lane);
+        halve<8, 8>(d, lane);
+        halve<4, 4>(d, lane);
+        halve<2, 2>(d, lane);
+        halve<1, 1>(d, lane);
+        red[tid >> 5][lane & (kQB - 1)] = d[0];
+    } else {  // 16 columns: lane l holds column C0 + ((l >> 1) & 15), lanes l, l ^ 1 alike
+        static_assert(L == 16, "32 or 16 live columns");
+        halve<8, 16>(d, lane);
+        halve<4, 8>(d, lane);
+        halve<2, 4>(d, lane);
+        halve<1, 2>(d, lane);
+        d[0] += xor_lane<1>(d[0]);
+        if ((lane & 1) == 0) red[tid >> 5][C0 + ((lane >> 1) & 15)] = d[0];
+    }
+}
+
+// Column j of the row (a product with the j-th unit vector over the live
+// columns: exact for finite values, no per-element select).
+template <int C0>
+__device__ __forceinline__ double pick_col(const double (&a)[kQB], int j) {
+    double x = 0.0;
+#pragma unroll
+    for (int c = C0; c < kQB; ++c) x = fma(a[c], c == j ? 1.0 : 0.0, x);
+    return x;
+}
+
+// The row's update over the live columns: A(r, c) mul_c - tw_c v.
+template <int C0>
+__device__ __forceinline__ void step_update(double (&a)[kQB], const double *mul, const double *tw, double v) {
+#pragma unroll
+    for (int c = C0; c < kQB; ++c) a[c] = fma(a[c], mul[c], -(tw[c] * v));
+}
+
 __global__ __launch_bounds__(256) void k_qr_fill_empty(int64_t count, double *__restrict__ p) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < count) p[i] = __longlong_as_double((long long)kEmpty);
@@ -165,38 +210,18 @@ __global__ __launch_bounds__(kPT) void k_qr_panel(QrPanelP p) {
     if (tid == 0) s_bad = 0;
     double *const xrow = p.xch + (int64_t)p.b * p.P * kQB;
     for (int j = 0; j < p.b; ++j) {
-        // column j of this thread's rows below the pivot (0 for the others),
-        // picked by a product with the j-th unit vector (uniform, scalar):
-        // exact for finite values, and no per-element select
-        double xm[kRpt];
-        bool below[kRpt];
-#pragma unroll
-        for (int i = 0; i < kRpt; ++i) {
-            const int64_t r = r0 + kPT * i;
-            below[i] = r > j && r < p.m;
-            double x = 0.0;
-#pragma unroll
-            for (int c = 0; c < kQB; ++c) x = fma(a[i][c], c == j ? 1.0 : 0.0, x);
-            xm[i] = below[i] ? x : 0.0;
-        }
-        {
-            double d[kQB];  // (the columns left of j are formed too, and not used)
-#pragma unroll
-            for (int c = 0; c < kQB; ++c) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < kRpt; ++i) s = fma(xm[i], a[i][c], s);
-                d[c] = s;
-            }
-            // sum over each half-wavefront by recursive halving: afterwards
-            // lane l holds column l & 31 of its half's 32 lanes
-            halve<16, 16>(d, lane);
-            halve<8, 8>(d, lane);
-            halve<4, 4>(d, lane);
-            halve<2, 2>(d, lane);
-            halve<1, 1>(d, lane);
-            red[tid >> 5][lane & (kQB - 1)] = d[0];
-        }
+        // column j of this thread's row if it lies below the pivot, else 0;
+        // the columns left of 16 are final once j >= 16: those steps work on
+        // the live columns only (a uniform choice; a third tier at 24
+        // measured no faster)
+        static_assert(kRpt == 1, "one panel row per thread");
+        const int64_t r = r0;
+        const bool below = r > j && r < p.m;
+        const bool late = j >= 16;
+        const double x = late ? pick_col<16>(a[0], j) : pick_col<0>(a[0], j);
+        const double xm = below ? x : 0.0;
+        if (late) step_sums<16>(a[0], xm, tid, lane, red);
+        else step_sums<0>(a[0], xm, tid, lane, red);
         if (wg == 0 && tid == j) {
 #pragma unroll
             for (int c = 0; c < kQB; ++c) prow[0][c] = a[0][c];
@@ -266,17 +291,13 @@ __global__ __launch_bounds__(kPT) void k_qr_panel(QrPanelP p) {
         // A(r, j) := v_r, as A(r, c) mul_c - tau w_c v_r (mul_c = 1 except
         // mul_j = 1 / (alpha - beta)); the pivot row: A(j, c) -= tau w_c and
         // A(j, j) := beta, as A(j, c) keep_c - tau w_c + beta (1 - keep_c)
+        if (below) {
+            const double v = xm * den;
+            if (late) step_update<16>(a[0], mulv, tws, v);
+            else step_update<0>(a[0], mulv, tws, v);
+        } else if (r == j) {
 #pragma unroll
-        for (int i = 0; i < kRpt; ++i) {
-            const int64_t r = r0 + kPT * i;
-            if (below[i]) {
-                const double v = xm[i] * den;
-#pragma unroll
-                for (int c = 0; c < kQB; ++c) a[i][c] = fma(a[i][c], mulv[c], -(tws[c] * v));
-            } else if (r == j) {
-#pragma unroll
-                for (int c = 0; c < kQB; ++c) a[i][c] = fma(a[i][c], keep[c], fma(beta, 1.0 - keep[c], -tws[c]));
-            }
+            for (int c = 0; c < kQB; ++c) a[0][c] = fma(a[0][c], keep[c], fma(beta, 1.0 - keep[c], -tws[c]));
         }
     }
 #pragma unroll
