@@ -106,6 +106,66 @@ int zpotrf_block(const ZWork &w, int64_t k, int64_t n, int64_t nb, int32_t *info
     return FLAME_OK;
 }
 
+// C -= P^H P for the upper triangle of the M x N block C at (i0, i0) of the
+// trailing matrix (the HERK's rows i0 .. i0 + M, columns from i0), P the K x n
+// panel (planes, ld w.ld) with its imaginary part negated in Pn (ld K): four
+// real products on the trailing-update kernel.
+int herk_part(const ZWork &w, int64_t a12, int64_t a22, const double *Pn, int64_t i0, int64_t M, int64_t N,
+              int64_t K, const int32_t *info, hipStream_t s, int reserve_cus) {
+    const int64_t ld = w.ld;
+    const double *Pr = w.R + a12 + i0 * ld, *Pi = w.I + a12 + i0 * ld, *Pni = Pn + i0 * K;
+    double *Cr = w.R + a22 + i0 + i0 * ld, *Ci = w.I + a22 + i0 + i0 * ld;
+    int rc = launch_gemm_tn(Prec::F64, true, true, M, N, K, Pr, ld, Pr, ld, Cr, ld, info, s, reserve_cus);
+    if (!rc) rc = launch_gemm_tn(Prec::F64, true, true, M, N, K, Pi, ld, Pi, ld, Cr, ld, info, s, reserve_cus);
+    if (!rc) rc = launch_gemm_tn(Prec::F64, true, true, M, N, K, Pr, ld, Pi, ld, Ci, ld, info, s, reserve_cus);
+    if (!rc) rc = launch_gemm_tn(Prec::F64, true, true, M, N, K, Pni, K, Pr, ld, Ci, ld, info, s, reserve_cus);
+    return rc;
+}
+
+constexpr int64_t kLookN = 2048;  // side stream only while more rows than this remain beyond the next block
+constexpr int kSideCus = 16;
+
+// The outer loop at block nb with one block of lookahead: the HERK's rows of
+// the next block first (main stream), the rest of the trailing matrix on the
+// side stream beside the next block's chain (its diagonal block and panel
+// solve, which read only those rows); the next block's HERK waits for it.
+// The negated imaginary panel alternates between two buffers.
+int zfactor_outer(const ZWork &w, int64_t n, int64_t nb, double *const Pnb[2], int32_t *info, hipStream_t s,
+                  hipStream_t side, hipEvent_t ev_next, hipEvent_t ev_rest, bool *side_pending) {
+    const int64_t ld = w.ld;
+    for (int64_t k0 = 0, step = 0; k0 < n; k0 += nb, ++step) {
+        const int64_t bk = std::min<int64_t>(nb, n - k0), m = n - k0 - bk;
+        int rc = zpotrf_block(w, k0, bk, kZB, info, k0, s);
+        if (rc) return rc;
+        if (m == 0) break;
+        rc = ztrsm(w, k0, bk, k0 + bk, m, info, s);
+        if (rc) return rc;
+        // A22 -= A12^H A12 (upper); the previous block's side part covered
+        // rows of it too
+        if (*side_pending) FLAME_HIP(hipStreamWaitEvent(s, ev_rest, 0));
+        *side_pending = false;
+        const int64_t a12 = k0 + (k0 + bk) * ld, a22 = (k0 + bk) + (k0 + bk) * ld;
+        double *Pn = Pnb[step & 1];
+        rc = launch_scaled_copy(bk, m, w.I + a12, ld, Pn, bk, -1.0, info, s);
+        if (rc) return rc;
+        const int64_t nb2 = std::min<int64_t>(nb, m), far = m - nb2;
+        if (far <= kLookN) {
+            rc = herk_part(w, a12, a22, Pn, 0, m, m, bk, info, s, 0);
+            if (rc) return rc;
+            continue;
+        }
+        rc = herk_part(w, a12, a22, Pn, 0, nb2, m, bk, info, s, 0);
+        if (rc) return rc;
+        FLAME_HIP(hipEventRecord(ev_next, s));
+        FLAME_HIP(hipStreamWaitEvent(side, ev_next, 0));
+        rc = herk_part(w, a12, a22, Pn, nb2, far, far, bk, info, side, kSideCus);
+        if (rc) return rc;
+        FLAME_HIP(hipEventRecord(ev_rest, side));
+        *side_pending = true;
+    }
+    return FLAME_OK;
+}
+
 }  // namespace
 
 int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t s) {
@@ -115,7 +175,7 @@ int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t 
     DevCtx *ctx = ctx_for_current_device();
     if (ctx == nullptr) return FLAME_ERR_HIP;
     const size_t plane = (size_t)n * (size_t)n;
-    const size_t doubles = 2 * plane + 2 * (size_t)kZB * (size_t)n + (size_t)nb * (size_t)n + 2 * kZB * kZB;
+    const size_t doubles = 2 * plane + 2 * (size_t)kZB * (size_t)n + 3 * (size_t)nb * (size_t)n + 2 * kZB * kZB;
     void *ws = nullptr;
     rc = ctx_workspace(ctx, kWsComplex, doubles * sizeof(double), &ws);
     if (rc) return rc;
@@ -129,8 +189,15 @@ int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t 
     w.Pn = w.Ti + (size_t)kZB * n;
     w.Vr = w.Pn + (size_t)nb * n;
     w.Vi = w.Vr + kZB * kZB;
+    double *const Pnb[2] = {w.Vi + kZB * kZB, w.Vi + kZB * kZB + (size_t)nb * n};
+    hipStream_t side = ctx_side_stream(ctx);
+    hipEvent_t ev_next = ctx_event(ctx, 2);  // main: the next block's rows updated
+    hipEvent_t ev_rest = ctx_event(ctx, 3);  // side: the rest of the trailing matrix updated
+    bool side_pending = false;
     rc = launch_z_split(n, A, lda, w.R, w.I, n, s);
-    if (!rc) rc = zpotrf_block(w, 0, n, nb, info, 0, s);
+    if (!rc) rc = zfactor_outer(w, n, nb, Pnb, info, s, side, ev_next, ev_rest, &side_pending);
+    // the side stream's last part joins the caller's stream (also after an error)
+    if (side_pending) FLAME_HIP(hipStreamWaitEvent(s, ev_rest, 0));
     if (!rc) rc = launch_z_merge(n, w.R, w.I, n, A, lda, s);
     return rc;
 }
