@@ -25,13 +25,14 @@ namespace flame {
 namespace {
 
 constexpr int kZB = 64;  // inner block (LDS kernels)
+constexpr int kSlots = 8;  // inverses kept, one per 64-block of an outer block (nb <= 512)
 
 struct ZWork {
     double *R, *I;  // planes, ld = n
     int64_t ld;
     double *Tr, *Ti;  // scratch panel, kZB x n
     double *Pn;       // negated imaginary operand, up to nb x n
-    double *Vr, *Vi;  // -U_ss^{-1}, kZB x kZB
+    double *Vr, *Vi;  // -U_ss^{-1} of the outer block's 64-blocks, kSlots x (kZB x kZB)
 };
 
 // C -= P^H Q; P is K x M (ldp), Q is K x N (ldq), C is M x N (ldc), each given
@@ -54,19 +55,23 @@ int zgemm_h(bool upper, int64_t M, int64_t N, int64_t K, const double *Pr, const
 }
 
 // X := triu(U)^{-H} X for the b x b block U at (k, k) and the b x m panel X
-// at (k, c0) of the planes.
-int ztrsm(const ZWork &w, int64_t k, int64_t b, int64_t c0, int64_t m, const int32_t *info, hipStream_t s) {
+// at (k, c0) of the planes.  The inverse of the 64-block s lives in slot
+// slot0 + s; those of the first `reuse` blocks are there already (the inner
+// loop's solves formed them), the others are formed here.
+int ztrsm(const ZWork &w, int64_t k, int64_t b, int64_t c0, int64_t m, const int32_t *info, hipStream_t s,
+          int slot0, int reuse) {
     const int64_t ld = w.ld;
     for (int64_t s0 = 0; s0 < b; s0 += kZB) {
         const int64_t bs = std::min<int64_t>(kZB, b - s0);
         const int64_t us = (k + s0) + (k + s0) * ld;  // U_ss
         const int64_t xs = (k + s0) + c0 * ld;         // X_s
-        int rc = launch_ztrinv_lds((int)bs, w.R + us, w.I + us, ld, w.Vr, w.Vi, kZB, info, s);
+        const int ib = (int)(s0 / kZB);
+        double *Vr = w.Vr + (int64_t)(slot0 + ib) * kZB * kZB, *Vi = w.Vi + (int64_t)(slot0 + ib) * kZB * kZB;
+        int rc = ib < reuse ? FLAME_OK : launch_ztrinv_lds((int)bs, w.R + us, w.I + us, ld, Vr, Vi, kZB, info, s);
         // T := 0 - (-V)^H X_s = V^H X_s, then X_s := T
         if (!rc) rc = launch_fill0(bs, m, w.Tr, kZB, s);
         if (!rc) rc = launch_fill0(bs, m, w.Ti, kZB, s);
-        if (!rc)
-            rc = zgemm_h(false, bs, m, bs, w.Vr, w.Vi, kZB, w.R + xs, w.I + xs, ld, w.Tr, w.Ti, kZB, w.Pn, info, s);
+        if (!rc) rc = zgemm_h(false, bs, m, bs, Vr, Vi, kZB, w.R + xs, w.I + xs, ld, w.Tr, w.Ti, kZB, w.Pn, info, s);
         if (!rc) rc = launch_scaled_copy(bs, m, w.Tr, kZB, w.R + xs, ld, 1.0, info, s);
         if (!rc) rc = launch_scaled_copy(bs, m, w.Ti, kZB, w.I + xs, ld, 1.0, info, s);
         if (rc) return rc;
@@ -84,18 +89,19 @@ int ztrsm(const ZWork &w, int64_t k, int64_t b, int64_t c0, int64_t m, const int
 }
 
 // Chol of the n x n diagonal block at (k, k) of the planes, by the loop at
-// block nb (<= kZB: the LDS kernel).
+// block nb (<= kZB: the LDS kernel); the inverses its solves form go to the
+// slots from slot_base (one per 64-block).
 int zpotrf_block(const ZWork &w, int64_t k, int64_t n, int64_t nb, int32_t *info, int64_t info_base,
-                 hipStream_t s) {
+                 hipStream_t s, int slot_base) {
     const int64_t ld = w.ld;
     if (n <= kZB) return launch_zchol_lds((int)n, w.R + k + k * ld, w.I + k + k * ld, ld, info, info_base, s);
     for (int64_t k0 = 0; k0 < n; k0 += nb) {
         const int64_t bk = std::min<int64_t>(nb, n - k0);
         const int64_t m = n - k0 - bk;
-        int rc = zpotrf_block(w, k + k0, bk, kZB, info, info_base + k0, s);
+        int rc = zpotrf_block(w, k + k0, bk, kZB, info, info_base + k0, s, slot_base + (int)(k0 / kZB));
         if (rc) return rc;
         if (m == 0) break;
-        rc = ztrsm(w, k + k0, bk, k + k0 + bk, m, info, s);
+        rc = ztrsm(w, k + k0, bk, k + k0 + bk, m, info, s, slot_base + (int)(k0 / kZB), 0);
         if (rc) return rc;
         // A22 -= A12^H A12 (upper)
         const int64_t a12 = (k + k0) + (k + k0 + bk) * ld, a22 = (k + k0 + bk) + (k + k0 + bk) * ld;
@@ -135,10 +141,11 @@ int zfactor_outer(const ZWork &w, int64_t n, int64_t nb, double *const Pnb[2], i
     const int64_t ld = w.ld;
     for (int64_t k0 = 0, step = 0; k0 < n; k0 += nb, ++step) {
         const int64_t bk = std::min<int64_t>(nb, n - k0), m = n - k0 - bk;
-        int rc = zpotrf_block(w, k0, bk, kZB, info, k0, s);
+        int rc = zpotrf_block(w, k0, bk, kZB, info, k0, s, 0);
         if (rc) return rc;
         if (m == 0) break;
-        rc = ztrsm(w, k0, bk, k0 + bk, m, info, s);
+        // the inner loop's solves formed the inverses of all 64-blocks but the last
+        rc = ztrsm(w, k0, bk, k0 + bk, m, info, s, 0, (int)((bk + kZB - 1) / kZB) - 1);
         if (rc) return rc;
         // A22 -= A12^H A12 (upper); the previous block's side part covered
         // rows of it too
@@ -175,7 +182,8 @@ int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t 
     DevCtx *ctx = ctx_for_current_device();
     if (ctx == nullptr) return FLAME_ERR_HIP;
     const size_t plane = (size_t)n * (size_t)n;
-    const size_t doubles = 2 * plane + 2 * (size_t)kZB * (size_t)n + 3 * (size_t)nb * (size_t)n + 2 * kZB * kZB;
+    const size_t doubles =
+        2 * plane + 2 * (size_t)kZB * (size_t)n + 3 * (size_t)nb * (size_t)n + 2 * (size_t)kSlots * kZB * kZB;
     void *ws = nullptr;
     rc = ctx_workspace(ctx, kWsComplex, doubles * sizeof(double), &ws);
     if (rc) return rc;
@@ -188,8 +196,8 @@ int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t 
     w.Ti = w.Tr + (size_t)kZB * n;
     w.Pn = w.Ti + (size_t)kZB * n;
     w.Vr = w.Pn + (size_t)nb * n;
-    w.Vi = w.Vr + kZB * kZB;
-    double *const Pnb[2] = {w.Vi + kZB * kZB, w.Vi + kZB * kZB + (size_t)nb * n};
+    w.Vi = w.Vr + (size_t)kSlots * kZB * kZB;
+    double *const Pnb[2] = {w.Vi + (size_t)kSlots * kZB * kZB, w.Vi + (size_t)kSlots * kZB * kZB + (size_t)nb * n};
     hipStream_t side = ctx_side_stream(ctx);
     hipEvent_t ev_next = ctx_event(ctx, 2);  // main: the next block's rows updated
     hipEvent_t ev_rest = ctx_event(ctx, 3);  // side: the rest of the trailing matrix updated
