@@ -187,6 +187,10 @@ int launch_ztrinv_lds(int n, const double *R, const double *I, int64_t ld, doubl
 int launch_zgemm_h(bool upper, int64_t M, int64_t N, int64_t K, const double *Pr, const double *Pi, int64_t ldp,
                    const double *Qr, const double *Qi, int64_t ldq, double *Cr, double *Ci, int64_t ldc,
                    const int32_t *info, hipStream_t s);
+// X := -P^H X in place (M <= 64 rows; P is K x M, planes), one row of
+// workgroup tiles.
+int launch_zgemm_h_inplace(int64_t M, int64_t N, int64_t K, const double *Pr, const double *Pi, int64_t ldp,
+                           double *Xr, double *Xi, int64_t ldx, const int32_t *info, hipStream_t s);
 // The complex factorization of flame_factor (dtype FLAME_Z64), upper storage.
 int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t s);
 

@@ -202,18 +202,24 @@ __device__ __forceinline__ zd4 zmma(double x, double y, zd4 acc) {
 // 16-k chunk, rows, columns and k beyond the matrices clamped or zeroed.
 // upper: only i <= j of C is written (tiles entirely below skipped).
 // Skips if *info != 0.
-__global__ __launch_bounds__(256) void k_zgemm_h(int64_t M, int64_t N, int64_t K, const double *__restrict__ Pr,
-                                                 const double *__restrict__ Pi, int64_t ldp,
-                                                 const double *__restrict__ Qr, const double *__restrict__ Qi,
-                                                 int64_t ldq, double *__restrict__ Cr, double *__restrict__ Ci,
-                                                 int64_t ldc, int upper, const int32_t *__restrict__ info) {
+// INPLACE: C and Q are the same (M <= 64, one row of workgroup tiles, so each
+// workgroup owns its columns) and C := -P^H Q is written over it: no
+// wavefront leaves early, and all of them have read their Q before any
+// writes C (a barrier between).
+template <bool INPLACE>
+__global__ __launch_bounds__(256) void k_zgemm_h(int64_t M, int64_t N, int64_t K, const double *Pr, const double *Pi,
+                                                 int64_t ldp, const double *Qr, const double *Qi, int64_t ldq,
+                                                 double *Cr, double *Ci, int64_t ldc, int upper,
+                                                 const int32_t *__restrict__ info) {
     if (*info != 0) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
     const int64_t row0 = (int64_t)blockIdx.x * 64 + (wave >> 1) * 32;
     const int64_t col0 = (int64_t)blockIdx.y * 64 + (wave & 1) * 32;
-    if (row0 >= M || col0 >= N) return;
-    if (upper && row0 > col0 + 31) return;
+    if (!INPLACE) {
+        if (row0 >= M || col0 >= N) return;
+        if (upper && row0 > col0 + 31) return;
+    }
     zd4 are[2][2], aim[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -255,6 +261,7 @@ __global__ __launch_bounds__(256) void k_zgemm_h(int64_t M, int64_t N, int64_t K
                     aim[a][b] = zmma(xi[a][t], yr[b][t], aim[a][b]);   // + Pi^T Qr
                 }
     }
+    if (INPLACE) __syncthreads();
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -263,8 +270,13 @@ __global__ __launch_bounds__(256) void k_zgemm_h(int64_t M, int64_t N, int64_t K
             for (int v = 0; v < 4; ++v) {
                 const int64_t i = row0 + 16 * a + r, j = col0 + 16 * b + g + 4 * v;
                 if (i < M && j < N && (!upper || i <= j)) {
-                    Cr[i + j * ldc] += are[a][b][v];
-                    Ci[i + j * ldc] += aim[a][b][v];
+                    if (INPLACE) {
+                        Cr[i + j * ldc] = are[a][b][v];
+                        Ci[i + j * ldc] = aim[a][b][v];
+                    } else {
+                        Cr[i + j * ldc] += are[a][b][v];
+                        Ci[i + j * ldc] += aim[a][b][v];
+                    }
                 }
             }
 }
@@ -308,8 +320,19 @@ int launch_zgemm_h(bool upper, int64_t M, int64_t N, int64_t K, const double *Pr
                    const int32_t *info, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return FLAME_OK;
     const dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64));
-    hipLaunchKernelGGL(k_zgemm_h, grid, dim3(256), 0, s, M, N, K, Pr, Pi, ldp, Qr, Qi, ldq, Cr, Ci, ldc,
+    hipLaunchKernelGGL(k_zgemm_h<false>, grid, dim3(256), 0, s, M, N, K, Pr, Pi, ldp, Qr, Qi, ldq, Cr, Ci, ldc,
                        upper ? 1 : 0, info);
+    FLAME_CHECK_LAUNCH();
+    return FLAME_OK;
+}
+
+int launch_zgemm_h_inplace(int64_t M, int64_t N, int64_t K, const double *Pr, const double *Pi, int64_t ldp,
+                           double *Xr, double *Xi, int64_t ldx, const int32_t *info, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return FLAME_OK;
+    if (M > 64) return FLAME_ERR_UNSUPPORTED;
+    const dim3 grid(1u, (unsigned)((N + 63) / 64));
+    hipLaunchKernelGGL(k_zgemm_h<true>, grid, dim3(256), 0, s, M, N, K, Pr, Pi, ldp, Xr, Xi, ldx, Xr, Xi, ldx, 0,
+                       info);
     FLAME_CHECK_LAUNCH();
     return FLAME_OK;
 }

@@ -12,8 +12,9 @@
 //   P^H Q = (Pr^T Qr + Pi^T Qi) + i (Pr^T Qi - Pi^T Qr),
 // the last one with a negated copy of Pi.  The HERK of each iteration is one
 // such product (upper triangle only); the panel solve goes by diagonal blocks
-// of 64: the block's inverse V = U_ss^{-1} (k_ztrinv_lds), X_s := V^H X_s as a
-// product into a scratch panel, and X_t -= U_st^H X_s for the blocks below.
+// of 64: V = -U_ss^{-1} (k_ztrinv_lds), X_s := -V^H X_s = U_ss^{-H} X_s in
+// place by the fused complex product, and X_t -= U_st^H X_s for the blocks
+// below.
 // Diagonal blocks of the outer loop (nb) are factored by the same loop at
 // block 64, whose diagonal blocks go to the LDS kernel k_zchol_lds.
 #include <algorithm>
@@ -30,9 +31,8 @@ constexpr int kSlots = 8;  // inverses kept, one per 64-block of an outer block 
 struct ZWork {
     double *R, *I;  // planes, ld = n
     int64_t ld;
-    double *Tr, *Ti;  // scratch panel, kZB x n
     double *Pn;       // negated imaginary operand, up to nb x n
-    double *Vr, *Vi;  // -U_ss^{-1} of the outer block's 64-blocks, kSlots x (kZB x kZB)
+    double *Vr, *Vi;  // V = -U_ss^{-1} of the outer block's 64-blocks, kSlots x (kZB x kZB)
 };
 
 // C -= P^H Q; P is K x M (ldp), Q is K x N (ldq), C is M x N (ldc), each given
@@ -68,12 +68,8 @@ int ztrsm(const ZWork &w, int64_t k, int64_t b, int64_t c0, int64_t m, const int
         const int ib = (int)(s0 / kZB);
         double *Vr = w.Vr + (int64_t)(slot0 + ib) * kZB * kZB, *Vi = w.Vi + (int64_t)(slot0 + ib) * kZB * kZB;
         int rc = ib < reuse ? FLAME_OK : launch_ztrinv_lds((int)bs, w.R + us, w.I + us, ld, Vr, Vi, kZB, info, s);
-        // T := 0 - (-V)^H X_s = V^H X_s, then X_s := T
-        if (!rc) rc = launch_fill0(bs, m, w.Tr, kZB, s);
-        if (!rc) rc = launch_fill0(bs, m, w.Ti, kZB, s);
-        if (!rc) rc = zgemm_h(false, bs, m, bs, Vr, Vi, kZB, w.R + xs, w.I + xs, ld, w.Tr, w.Ti, kZB, w.Pn, info, s);
-        if (!rc) rc = launch_scaled_copy(bs, m, w.Tr, kZB, w.R + xs, ld, 1.0, info, s);
-        if (!rc) rc = launch_scaled_copy(bs, m, w.Ti, kZB, w.I + xs, ld, 1.0, info, s);
+        // X_s := -V^H X_s = U_ss^{-H} X_s, in place
+        if (!rc) rc = launch_zgemm_h_inplace(bs, m, bs, Vr, Vi, kZB, w.R + xs, w.I + xs, ld, info, s);
         if (rc) return rc;
         const int64_t rest = b - s0 - bs;
         if (rest > 0) {
@@ -183,7 +179,7 @@ int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t 
     if (ctx == nullptr) return FLAME_ERR_HIP;
     const size_t plane = (size_t)n * (size_t)n;
     const size_t doubles =
-        2 * plane + 2 * (size_t)kZB * (size_t)n + 3 * (size_t)nb * (size_t)n + 2 * (size_t)kSlots * kZB * kZB;
+        2 * plane + 3 * (size_t)nb * (size_t)n + 2 * (size_t)kSlots * kZB * kZB;
     void *ws = nullptr;
     rc = ctx_workspace(ctx, kWsComplex, doubles * sizeof(double), &ws);
     if (rc) return rc;
@@ -192,9 +188,7 @@ int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t 
     w.R = p;
     w.I = p + plane;
     w.ld = n;
-    w.Tr = p + 2 * plane;
-    w.Ti = w.Tr + (size_t)kZB * n;
-    w.Pn = w.Ti + (size_t)kZB * n;
+    w.Pn = p + 2 * plane;
     w.Vr = w.Pn + (size_t)nb * n;
     w.Vi = w.Vr + (size_t)kSlots * kZB * kZB;
     double *const Pnb[2] = {w.Vi + (size_t)kSlots * kZB * kZB, w.Vi + (size_t)kSlots * kZB * kZB + (size_t)nb * n};
