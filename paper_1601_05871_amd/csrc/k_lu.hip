@@ -55,56 +55,83 @@ __global__ __launch_bounds__(256) void k_lu_lds(int n, double *__restrict__ A, i
 // For the factored n x n block (L\U): P1 := -(L^{-1})^T and P2 := -U^{-1}
 // (n x n each, ld kL, zero outside the triangles), so that the
 // trailing-update kernel's C -= X^T Y gives C + L^{-1} Y with X = P1 and
-// C + U^{-T} Y with X = P2.  512 threads: the first 256 form the columns of
-// L^{-1} (forward substitution, L w = e_t, unit diagonal), the others those
-// of U^{-1} (back substitution, U v = e_t), both row by row in lockstep, the
-// sum over k of each row split over four threads (k mod 4) and combined after
-// a barrier.  The block, the columns and the partial sums in LDS.
+// C + U^{-T} Y with X = P2.  The block is padded to 64 with the identity, and
+// each inverse is formed by doubling: the four 16 x 16 diagonal blocks by
+// substitution (a thread per column, no barriers), then pairs of blocks of
+// order h = 16 and 32 joined by
+//   W(hi, lo) = -W(hi, hi) L(hi, lo) W(lo, lo)     (W = L^{-1}, lower)
+//   V(lo, hi) = -V(lo, lo) U(lo, hi) V(hi, hi)     (V = U^{-1}, upper)
+// as two products each, the inner one kept in the inverse's other (unused)
+// triangle.  512 threads: the first 256 form W, the others V.  In LDS,
+// [row][column].
 __global__ __launch_bounds__(512) void k_lu_inv(int n, const double *__restrict__ A, int64_t lda,
                                                 double *__restrict__ P1, double *__restrict__ P2,
                                                 const int32_t *__restrict__ info) {
-    __shared__ double a[kL][kL + 1];   // [column][row]
-    __shared__ double w[kL][kL + 1];   // [column t][row] of L^{-1}
-    __shared__ double v[kL][kL + 1];   // [column t][row] of U^{-1}
-    __shared__ double part[2][4][kL];  // partial sums [triangle][k mod 4][column]
+    __shared__ double a[kL][kL + 1];
+    __shared__ double w[kL][kL + 1];
+    __shared__ double v[kL][kL + 1];
     if (*info != 0) return;
-    const int tid = threadIdx.x, t = tid & (kL - 1), q = (tid >> 6) & 3, up = tid >> 8;
+    const int tid = threadIdx.x, t = tid & 255;
+    const bool up = tid >= 256;  // uniform per wavefront
     for (int e = tid; e < kL * kL; e += 512) {
-        const int i = e & (kL - 1), j = e >> 6;
-        if (i < n && j < n) a[j][i] = A[i + (int64_t)j * lda];
+        const int r = e & (kL - 1), c = e >> 6;
+        a[r][c] = (r < n && c < n) ? A[r + (int64_t)c * lda] : (r == c ? 1.0 : 0.0);
+        w[r][c] = 0.0;
+        v[r][c] = 0.0;
     }
     __syncthreads();
-    for (int step = 0; step < n; ++step) {
-        double s = 0.0;
-        if (t < n) {
-            if (!up) {  // row i of L w = e_t: w_i = delta - sum_{t <= k < i} L(i, k) w_k
-                const int i = step;
-                if (i > t)
-                    for (int k = t + q; k < i; k += 4) s += a[k][i] * w[t][k];
-            } else {  // row i of U v = e_t: v_i = (delta - sum_{i < k <= t} U(i, k) v_k) / U(i, i)
-                const int i = n - 1 - step;
-                if (i <= t)
-                    for (int k = i + 1 + q; k <= t; k += 4) s += a[k][i] * v[t][k];
+    if (t < kL) {  // the diagonal 16-blocks: block b, column j of it
+        const int b = t >> 4, j = t & 15, c = 16 * b + j;
+        if (!up) {  // unit lower: rows j .. 15
+            for (int i = j; i < 16; ++i) {
+                const int r = 16 * b + i;
+                double sum = (i == j) ? 1.0 : 0.0;
+                for (int k = j; k < i; ++k) sum -= a[r][16 * b + k] * w[16 * b + k][c];
+                w[r][c] = sum;
+            }
+        } else {  // upper: rows j .. 0
+            for (int i = j; i >= 0; --i) {
+                const int r = 16 * b + i;
+                double sum = (i == j) ? 1.0 : 0.0;
+                for (int k = i + 1; k <= j; ++k) sum -= a[r][16 * b + k] * v[16 * b + k][c];
+                v[r][c] = sum / a[r][r];
             }
         }
-        part[up][q][t] = s;
-        __syncthreads();
-        if (q == 0 && t < n) {
-            const double sum = (part[up][0][t] + part[up][1][t]) + (part[up][2][t] + part[up][3][t]);
+    }
+    __syncthreads();
+    for (int h = 16; h < kL; h *= 2) {
+        const int outs = (kL / (2 * h)) * h * h;  // pairs x h^2
+        for (int e = t; e < outs; e += 256) {     // the inner products, into the other triangle
+            const int p = e / (h * h), q = e % (h * h), i = q % h, j = q / h;
+            const int lo = 2 * h * p, hi = lo + h;
+            double sum = 0.0;
             if (!up) {
-                const int i = step;
-                w[t][i] = (i < t) ? 0.0 : (((i == t) ? 1.0 : 0.0) - sum);
+                for (int k = j; k < h; ++k) sum += a[hi + i][lo + k] * w[lo + k][lo + j];  // L(hi, lo) W(lo, lo)
+                w[lo + i][hi + j] = sum;
             } else {
-                const int i = n - 1 - step;
-                v[t][i] = (i > t) ? 0.0 : (((i == t) ? 1.0 : 0.0) - sum) / a[i][i];
+                for (int k = 0; k <= j; ++k) sum += a[lo + i][hi + k] * v[hi + k][hi + j];  // U(lo, hi) V(hi, hi)
+                v[hi + i][lo + j] = sum;
+            }
+        }
+        __syncthreads();
+        for (int e = t; e < outs; e += 256) {
+            const int p = e / (h * h), q = e % (h * h), i = q % h, j = q / h;
+            const int lo = 2 * h * p, hi = lo + h;
+            double sum = 0.0;
+            if (!up) {
+                for (int k = 0; k <= i; ++k) sum += w[hi + i][hi + k] * w[lo + k][hi + j];
+                w[hi + i][lo + j] = -sum;
+            } else {
+                for (int k = i; k < h; ++k) sum += v[lo + i][lo + k] * v[hi + k][lo + j];
+                v[lo + i][hi + j] = -sum;
             }
         }
         __syncthreads();
     }
     for (int e = tid; e < n * n; e += 512) {
         const int i = e % n, c = e / n;
-        P1[c + (int64_t)i * kL] = -w[c][i];  // P1(c, i) = -W(i, c)
-        P2[i + (int64_t)c * kL] = -v[c][i];  // P2(i, c) = -V(i, c)
+        P1[c + (int64_t)i * kL] = i >= c ? -w[i][c] : 0.0;  // P1(c, i) = -W(i, c)
+        P2[i + (int64_t)c * kL] = i <= c ? -v[i][c] : 0.0;  // P2(i, c) = -V(i, c)
     }
 }
 
