@@ -133,54 +133,80 @@ __global__ __launch_bounds__(256) void k_zchol_lds(int n, double *__restrict__ R
 }
 
 // V := -U^{-1} for the n x n (n <= 64) upper triangular U in the planes
-// (real diagonal), into the planes Vr, Vi (ldv), zero below the diagonal:
-// column t of U^{-1} by back substitution, U v = e_t, row by row from the
-// last; the sum over k of each row is split over four threads (k mod 4) and
-// combined after a barrier.  256 threads; U, the columns and the partial
-// sums in LDS.  Skips if *info != 0.
+// (real diagonal), into the planes Vr, Vi (ldv), zero below the diagonal.
+// U is padded to 64 with the identity and W = U^{-1} formed by doubling: the
+// four 16 x 16 diagonal blocks by back substitution (a thread per column, no
+// barriers), then pairs of blocks of order h = 16 and 32 joined by
+// W(lo, hi) = -W(lo, lo) U(lo, hi) W(hi, hi), the inner product kept in W's
+// unused lower triangle.  256 threads; U and W in LDS, [row][column].  Skips
+// if *info != 0.
 __global__ __launch_bounds__(256) void k_ztrinv_lds(int n, const double *__restrict__ R, const double *__restrict__ I,
                                                     int64_t ld, double *__restrict__ Vr, double *__restrict__ Vi,
                                                     int64_t ldv, const int32_t *__restrict__ info) {
-    __shared__ double ur[kZ][kZ + 1], ui[kZ][kZ + 1];  // [column][row]
-    __shared__ double vr[kZ][kZ + 1], vi[kZ][kZ + 1];  // [column t][row]
-    __shared__ double pr[4][kZ], pi[4][kZ];             // partial sums [k mod 4][column]
+    __shared__ double ur[kZ][kZ + 1], ui[kZ][kZ + 1];
+    __shared__ double wr[kZ][kZ + 1], wi[kZ][kZ + 1];
     if (*info != 0) return;
-    const int tid = threadIdx.x, t = tid & (kZ - 1), q = tid >> 6;
+    const int tid = threadIdx.x;
     for (int e = tid; e < kZ * kZ; e += 256) {
-        const int i = e & (kZ - 1), j = e >> 6;
-        if (i <= j && j < n) {
-            ur[j][i] = R[i + (int64_t)j * ld];
-            ui[j][i] = I[i + (int64_t)j * ld];
+        const int r = e & (kZ - 1), c = e >> 6;
+        const bool in = r <= c && c < n;
+        ur[r][c] = in ? R[r + (int64_t)c * ld] : (r == c ? 1.0 : 0.0);
+        ui[r][c] = in ? I[r + (int64_t)c * ld] : 0.0;
+        wr[r][c] = 0.0;
+        wi[r][c] = 0.0;
+    }
+    __syncthreads();
+    if (tid < kZ) {  // the diagonal 16-blocks: block b, column j of it, rows j .. 0
+        const int b = tid >> 4, j = tid & 15, c = 16 * b + j;
+        for (int i = j; i >= 0; --i) {
+            const int r = 16 * b + i;
+            double sr = (i == j) ? 1.0 : 0.0, si = 0.0;
+            for (int k = i + 1; k <= j; ++k) {
+                const int q = 16 * b + k;
+                sr -= ur[r][q] * wr[q][c] - ui[r][q] * wi[q][c];
+                si -= ur[r][q] * wi[q][c] + ui[r][q] * wr[q][c];
+            }
+            const double d = ur[r][r];  // real diagonal
+            wr[r][c] = sr / d;
+            wi[r][c] = si / d;
         }
     }
     __syncthreads();
-    for (int i = n - 1; i >= 0; --i) {
-        double sr = 0.0, si = 0.0;
-        if (t < n && i <= t) {
-            for (int k = i + 1 + q; k <= t; k += 4) {
-                sr += ur[k][i] * vr[t][k] - ui[k][i] * vi[t][k];
-                si += ur[k][i] * vi[t][k] + ui[k][i] * vr[t][k];
+    for (int h = 16; h < kZ; h *= 2) {
+        const int outs = (kZ / (2 * h)) * h * h;  // pairs x h^2
+        for (int e = tid; e < outs; e += 256) {   // T = U(lo, hi) W(hi, hi), into W(hi, lo)'s place
+            const int p = e / (h * h), q = e % (h * h), i = q % h, j = q / h;
+            const int lo = 2 * h * p, hi = lo + h;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k <= j; ++k) {
+                const double a = ur[lo + i][hi + k], b = ui[lo + i][hi + k];
+                const double x = wr[hi + k][hi + j], y = wi[hi + k][hi + j];
+                sr += a * x - b * y;
+                si += a * y + b * x;
             }
+            wr[hi + i][lo + j] = sr;
+            wi[hi + i][lo + j] = si;
         }
-        pr[q][t] = sr;
-        pi[q][t] = si;
         __syncthreads();
-        if (q == 0 && t < n) {
-            double ar = 0.0, ai = 0.0;
-            if (i <= t) {
-                const double d = ur[i][i];  // real diagonal
-                ar = (((i == t) ? 1.0 : 0.0) - ((pr[0][t] + pr[1][t]) + (pr[2][t] + pr[3][t]))) / d;
-                ai = (0.0 - ((pi[0][t] + pi[1][t]) + (pi[2][t] + pi[3][t]))) / d;
+        for (int e = tid; e < outs; e += 256) {  // W(lo, hi) = -W(lo, lo) T
+            const int p = e / (h * h), q = e % (h * h), i = q % h, j = q / h;
+            const int lo = 2 * h * p, hi = lo + h;
+            double sr = 0.0, si = 0.0;
+            for (int k = i; k < h; ++k) {
+                const double a = wr[lo + i][lo + k], b = wi[lo + i][lo + k];
+                const double x = wr[hi + k][lo + j], y = wi[hi + k][lo + j];
+                sr += a * x - b * y;
+                si += a * y + b * x;
             }
-            vr[t][i] = ar;
-            vi[t][i] = ai;
+            wr[lo + i][hi + j] = -sr;
+            wi[lo + i][hi + j] = -si;
         }
         __syncthreads();
     }
     for (int e = tid; e < n * n; e += 256) {
         const int i = e % n, c = e / n;
-        Vr[i + (int64_t)c * ldv] = -vr[c][i];
-        Vi[i + (int64_t)c * ldv] = -vi[c][i];
+        Vr[i + (int64_t)c * ldv] = i <= c ? -wr[i][c] : 0.0;
+        Vi[i + (int64_t)c * ldv] = i <= c ? -wi[i][c] : 0.0;
     }
 }
 
