@@ -15,34 +15,97 @@ namespace {
 
 constexpr int kL = 64;
 
+// v of lane `lane` (uniform) for every lane.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
 // A := L\U for the n x n (n <= 64) block, one workgroup, the block in LDS
-// ([column][row], padded).  Step j: pivot A(j,j) (zero or not finite:
-// *info = info_base + j + 1, stop), column below divided by it, then
-// A(r,c) -= A(r,j) A(j,c) for r, c > j, the 256 threads on (column, row
-// group) pairs.  Skips if *info != 0 on entry.
+// ([column][row], padded), blocked by 16 columns.  For the panel of columns
+// k0 .. k0 + 15:
+//   wavefront 0 factors the panel A(k0:n, k0:k0+16) with a lane per row and
+//     the row's 16 values in registers: step j takes the pivot row from lane
+//     j (readlane; zero or not finite: *info = info_base + column, stop),
+//     each row below divides its entry by the pivot and subtracts the
+//     multiple of the pivot row (no barriers: one wavefront);
+//   a thread per column forms U12 := L11^{-1} A12 (forward substitution);
+//   all threads apply A22 -= L21 U12, pivot by pivot.
+// Each entry sees the same operations in the same order as in the unblocked
+// loop (a(r, c) -= l(r, j) u(j, c) for j ascending), only grouped by panel.
+// Skips if *info != 0 on entry.
 __global__ __launch_bounds__(256) void k_lu_lds(int n, double *__restrict__ A, int64_t lda, int32_t *__restrict__ info,
                                                 int64_t info_base) {
     __shared__ double a[kL][kL + 1];
+    __shared__ int s_bad;
     if (*info != 0) return;
     const int tid = threadIdx.x;
     for (int e = tid; e < kL * kL; e += 256) {
         const int i = e & (kL - 1), j = e >> 6;
         if (i < n && j < n) a[j][i] = A[i + (int64_t)j * lda];
     }
+    if (tid == 0) s_bad = 0;
     __syncthreads();
-    const int cl = tid & (kL - 1), rg = tid >> 6;
-    for (int j = 0; j < n; ++j) {
-        const double piv = a[j][j];
-        if (piv == 0.0 || !isfinite(piv)) {  // the same value in every thread: a uniform exit
-            if (tid == 0) *info = (int32_t)(info_base + j + 1);
+    for (int k0 = 0; k0 < n; k0 += 16) {
+        const int w = min(16, n - k0);  // panel width
+        if (tid < 64) {                 // the panel: lane tid holds row k0 + tid
+            const int r = k0 + tid;
+            const bool live = r < n;
+            double x[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) x[c] = (live && c < w) ? a[k0 + c][r] : 0.0;
+            int bad = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < w && bad == 0) {  // uniform
+                    double prow[16];
+#pragma unroll
+                    for (int c = j; c < 16; ++c) prow[c] = lane_value(x[c], j);
+                    const double piv = prow[j];
+                    if (piv == 0.0 || !isfinite(piv)) {
+                        bad = k0 + j + 1;
+                    } else if (tid > j && live) {
+                        const double l = x[j] / piv;
+                        x[j] = l;
+#pragma unroll
+                        for (int c = j + 1; c < 16; ++c) x[c] -= l * prow[c];
+                    }
+                }
+            }
+            if (live) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (c < w) a[k0 + c][r] = x[c];
+            }
+            if (tid == 0 && bad != 0) s_bad = bad;
+        }
+        __syncthreads();
+        if (s_bad != 0) {  // uniform
+            if (tid == 0) *info = (int32_t)(info_base + s_bad);
             return;
         }
-        for (int r = j + 1 + tid; r < n; r += 256) a[j][r] = a[j][r] / piv;
+        const int c0 = k0 + w, rest = n - c0;
+        if (rest <= 0) break;
+        if (tid < rest) {  // U12 := L11^{-1} A12, column c0 + tid
+            const int c = c0 + tid;
+            double y[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) y[i] = i < w ? a[c][k0 + i] : 0.0;
+#pragma unroll
+            for (int i = 1; i < 16; ++i)
+#pragma unroll
+                for (int k = 0; k < i; ++k) y[i] -= a[k0 + k][k0 + i] * y[k];  // L(k0 + i, k0 + k)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < w) a[c][k0 + i] = y[i];
+        }
         __syncthreads();
-        const int c = j + 1 + cl;
-        if (c < n) {
-            const double ujc = a[c][j];
-            for (int r = j + 1 + rg; r < n; r += 4) a[c][r] -= a[j][r] * ujc;
+        for (int e = tid; e < rest * rest; e += 256) {  // A22 -= L21 U12, pivot by pivot
+            const int rr = c0 + e % rest, cc = c0 + e / rest;
+            double v = a[cc][rr];
+            for (int k = 0; k < w; ++k) v -= a[k0 + k][rr] * a[cc][k0 + k];
+            a[cc][rr] = v;
         }
         __syncthreads();
     }
