@@ -195,12 +195,12 @@ int launch_zgemm_h_inplace(int64_t M, int64_t N, int64_t K, const double *Pr, co
 int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t s);
 
 // ---- LU without pivoting (k_lu.hip, lu.cpp) ---------------------------------
-// Diagonal block (n <= 64) := L\U in place; on a zero or non-finite pivot
-// *info = info_base + column.  P1 := -(L^{-1})^T, P2 := -U^{-1} (n x n, ld 64)
-// of a factored block.  dst (cols x rows) := src^T.  All skip if *info
-// (the transpose only when info is given).
-int launch_lu_lds(int n, double *A, int64_t lda, int32_t *info, int64_t info_base, hipStream_t s);
-int launch_lu_inv(int n, const double *A, int64_t lda, double *P1, double *P2, const int32_t *info, hipStream_t s);
+// Diagonal block (n <= 64) := L\U in place (on a zero or non-finite pivot
+// *info = info_base + column) and, unless P1 and P2 are null, P1 :=
+// -(L^{-1})^T, P2 := -U^{-1} (n x n, ld 64), in one launch.  dst (cols x rows)
+// := src^T.  Both skip if *info (the transpose only when info is given).
+int launch_lu_diag(int n, double *A, int64_t lda, int32_t *info, int64_t info_base, double *P1, double *P2,
+                   hipStream_t s);
 int launch_transpose_copy(int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst, int64_t ldd,
                           const int32_t *info, hipStream_t s);
 int lu_factor(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s);

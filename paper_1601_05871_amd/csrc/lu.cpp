@@ -1,7 +1,7 @@
 // LU without pivoting (flame_lu), right-looking at block 64 (the kernels are in
 // k_lu.hip):
-//   A11 := L\U(A11)                      k_lu_lds (LDS, one workgroup)
-//   P1 := -(L11^{-1})^T, P2 := -U11^{-1}  k_lu_inv
+//   A11 := L\U(A11),                     k_lu_diag (LDS, one workgroup,
+//   P1 := -(L11^{-1})^T, P2 := -U11^{-1}  one launch)
 //   A12 := L11^{-1} A12                  T := 0 - P1^T A12, A12 := T
 //   A21 := A21 U11^{-1}, kept transposed: S := A21^T, S' := 0 - P2^T S
 //                                        (= U11^{-T} A21^T)
@@ -35,10 +35,9 @@ int lu_steps(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s, hi
         double *S2 = S2buf[step & 1];
         // the step's chain: it reads only what the previous step's first
         // products (main stream) updated
-        rc = launch_lu_lds((int)bk, A11, lda, info, k, s);
+        rc = launch_lu_diag((int)bk, A11, lda, info, k, m > 0 ? P1 : nullptr, m > 0 ? P2 : nullptr, s);
         if (rc) return rc;
         if (m == 0) break;
-        rc = launch_lu_inv((int)bk, A11, lda, P1, P2, info, s);
         // A12 := L11^{-1} A12
         if (!rc) rc = launch_fill0(bk, m, T, kB, s);
         if (!rc) rc = launch_gemm_tn(Prec::F64, true, false, bk, m, bk, P1, kB, A12, lda, T, kB, info, s);
