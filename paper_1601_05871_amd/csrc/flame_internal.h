@@ -198,11 +198,12 @@ int zfactor(int64_t n, void *A, int64_t lda, int nb, int32_t *info, hipStream_t 
 // Diagonal block (n <= 64) := L\U in place (on a zero or non-finite pivot
 // *info = info_base + column) and, unless P1 and P2 are null, P1 :=
 // -(L^{-1})^T, P2 := -U^{-1} (n x n, ld 64), in one launch.  dst (cols x rows)
-// := src^T.  Both skip if *info (the transpose only when info is given).
+// := src^T, and z1, z2 (null or shaped as dst) := 0.  Both skip if *info (the
+// transpose only when info is given).
 int launch_lu_diag(int n, double *A, int64_t lda, int32_t *info, int64_t info_base, double *P1, double *P2,
                    hipStream_t s);
 int launch_transpose_copy(int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst, int64_t ldd,
-                          const int32_t *info, hipStream_t s);
+                          const int32_t *info, hipStream_t s, double *z1 = nullptr, double *z2 = nullptr);
 int lu_factor(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s);
 
 // ---- Householder QR (k_qr.hip, qr.cpp) -----------------------------------

@@ -199,10 +199,13 @@ __global__ __launch_bounds__(NT) void k_lu_diag(int n, double *__restrict__ A, i
     }
 }
 
-// dst (cols x rows, ldd) := src^T (src rows x cols, lds), 64 x 64 tiles
-// through LDS, grid (row tiles, column tiles); skipped if info && *info.
+// dst (cols x rows, ldd) := src^T, 64 x 64 tiles through LDS, grid (row
+// tiles, column tiles); z1 and z2 (each null or cols x rows with ld ldd) are
+// set to zero over the same tiles, which saves the fills of the products'
+// scratch a launch each.  Skipped if info && *info.
 __global__ __launch_bounds__(256) void k_transpose_copy(int64_t rows, int64_t cols, const double *__restrict__ src,
                                                         int64_t lds, double *__restrict__ dst, int64_t ldd,
+                                                        double *__restrict__ z1, double *__restrict__ z2,
                                                         const int32_t *__restrict__ info) {
     __shared__ double tile[kL][kL + 1];
     if (info != nullptr && *info != 0) return;
@@ -215,7 +218,11 @@ __global__ __launch_bounds__(256) void k_transpose_copy(int64_t rows, int64_t co
     __syncthreads();
     for (int k = ty; k < kL; k += 4) {
         const int64_t dr = c0 + tx, dc = r0 + k;  // dst(dr, dc) = src(dc, dr)
-        if (dr < cols && dc < rows) dst[dr + dc * ldd] = tile[tx][k];
+        if (dr < cols && dc < rows) {
+            dst[dr + dc * ldd] = tile[tx][k];
+            if (z1 != nullptr) z1[dr + dc * ldd] = 0.0;
+            if (z2 != nullptr) z2[dr + dc * ldd] = 0.0;
+        }
     }
 }
 
@@ -232,10 +239,10 @@ int launch_lu_diag(int n, double *A, int64_t lda, int32_t *info, int64_t info_ba
 }
 
 int launch_transpose_copy(int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst, int64_t ldd,
-                          const int32_t *info, hipStream_t s) {
+                          const int32_t *info, hipStream_t s, double *z1, double *z2) {
     if (rows <= 0 || cols <= 0) return FLAME_OK;
     const dim3 grid((unsigned)((rows + kL - 1) / kL), (unsigned)((cols + kL - 1) / kL));
-    hipLaunchKernelGGL(k_transpose_copy, grid, dim3(256), 0, s, rows, cols, src, lds, dst, ldd, info);
+    hipLaunchKernelGGL(k_transpose_copy, grid, dim3(256), 0, s, rows, cols, src, lds, dst, ldd, z1, z2, info);
     FLAME_CHECK_LAUNCH();
     return FLAME_OK;
 }
