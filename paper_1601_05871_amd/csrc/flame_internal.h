@@ -177,11 +177,11 @@ int launch_z_merge(int64_t n, const double *R, const double *I, int64_t ld, void
 int launch_scaled_copy(int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst, int64_t ldd,
                        double scale, const int32_t *info, hipStream_t s);
 int launch_fill0(int64_t rows, int64_t cols, double *dst, int64_t ldd, hipStream_t s);
-// Complex diagonal block (n <= 64, planes): A := Chol(A); on breakdown
-// *info = info_base + column.  V := -U^{-1} (n <= 64).  Both skip if *info.
-int launch_zchol_lds(int n, double *R, double *I, int64_t ld, int32_t *info, int64_t info_base, hipStream_t s);
-int launch_ztrinv_lds(int n, const double *R, const double *I, int64_t ld, double *Vr, double *Vi, int64_t ldv,
-                      const int32_t *info, hipStream_t s);
+// Complex diagonal block (n <= 64, planes): A := Chol(A) (on breakdown
+// *info = info_base + column) and V := -U^{-1} (planes Vr, Vi, ldv >= n), in
+// one launch.  Skips if *info.
+int launch_zchol_lds(int n, double *R, double *I, int64_t ld, int32_t *info, int64_t info_base, double *Vr,
+                     double *Vi, int64_t ldv, hipStream_t s);
 // C -= P^H Q on planes in one matrix-core pass (P K x M, Q K x N, C M x N;
 // upper: i <= j only).  Skips if *info.
 int launch_zgemm_h(bool upper, int64_t M, int64_t N, int64_t K, const double *Pr, const double *Pi, int64_t ldp,

@@ -66,10 +66,20 @@ __global__ __launch_bounds__(256) void k_fill0(int64_t rows, double *__restrict_
 // elements (i, c), j < i <= c, with conj(U(j,i)) U(j,c) (selects, no
 // per-element branch).  A pivot that is not > 0: *info = info_base + j + 1
 // and every thread leaves (the planes then hold nothing of this block's
-// result).  Skips if *info != 0 on entry.
+// result).  Then V := -U^{-1} into the planes Vr, Vi (ldv), zero below the
+// diagonal, from U as the registers hold it (the panel solves' operand: one
+// launch for both).  U is padded to 64 with the identity and W = U^{-1}
+// formed by doubling: the four 16 x 16 diagonal blocks by back substitution
+// (a thread per column, no barriers), then pairs of blocks of order h = 16
+// and 32 joined by W(lo, hi) = -W(lo, lo) U(lo, hi) W(hi, hi), the inner
+// product kept in W's unused lower triangle; U and W in LDS, [row][column].
+// Skips if *info != 0 on entry.
 __global__ __launch_bounds__(256) void k_zchol_lds(int n, double *__restrict__ R, double *__restrict__ I, int64_t ld,
-                                                   int32_t *__restrict__ info, int64_t info_base) {
+                                                   int32_t *__restrict__ info, int64_t info_base,
+                                                   double *__restrict__ Vr, double *__restrict__ Vi, int64_t ldv) {
     __shared__ double rowr[2][kZ], rowi[2][kZ], pivb[2];
+    __shared__ double ur[kZ][kZ + 1], ui[kZ][kZ + 1];
+    __shared__ double wr[kZ][kZ + 1], wi[kZ][kZ + 1];
     if (*info != 0) return;
     const int tid = threadIdx.x, c = tid & (kZ - 1), g = tid >> 6;
     double ar[16], ai[16];
@@ -125,35 +135,18 @@ __global__ __launch_bounds__(256) void k_zchol_lds(int n, double *__restrict__ R
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int i = g + 4 * k;
-        if (i <= c && c < n) {
+        const bool in = i <= c && c < n;
+        if (in) {
             R[i + (int64_t)c * ld] = ar[k];
             I[i + (int64_t)c * ld] = ai[k];
         }
+        ur[i][c] = in ? ar[k] : (i == c ? 1.0 : 0.0);
+        ui[i][c] = in ? ai[k] : 0.0;
     }
-}
-
-// V := -U^{-1} for the n x n (n <= 64) upper triangular U in the planes
-// (real diagonal), into the planes Vr, Vi (ldv), zero below the diagonal.
-// U is padded to 64 with the identity and W = U^{-1} formed by doubling: the
-// four 16 x 16 diagonal blocks by back substitution (a thread per column, no
-// barriers), then pairs of blocks of order h = 16 and 32 joined by
-// W(lo, hi) = -W(lo, lo) U(lo, hi) W(hi, hi), the inner product kept in W's
-// unused lower triangle.  256 threads; U and W in LDS, [row][column].  Skips
-// if *info != 0.
-__global__ __launch_bounds__(256) void k_ztrinv_lds(int n, const double *__restrict__ R, const double *__restrict__ I,
-                                                    int64_t ld, double *__restrict__ Vr, double *__restrict__ Vi,
-                                                    int64_t ldv, const int32_t *__restrict__ info) {
-    __shared__ double ur[kZ][kZ + 1], ui[kZ][kZ + 1];
-    __shared__ double wr[kZ][kZ + 1], wi[kZ][kZ + 1];
-    if (*info != 0) return;
-    const int tid = threadIdx.x;
     for (int e = tid; e < kZ * kZ; e += 256) {
-        const int r = e & (kZ - 1), c = e >> 6;
-        const bool in = r <= c && c < n;
-        ur[r][c] = in ? R[r + (int64_t)c * ld] : (r == c ? 1.0 : 0.0);
-        ui[r][c] = in ? I[r + (int64_t)c * ld] : 0.0;
-        wr[r][c] = 0.0;
-        wi[r][c] = 0.0;
+        const int r = e & (kZ - 1), cc = e >> 6;
+        wr[r][cc] = 0.0;
+        wi[r][cc] = 0.0;
     }
     __syncthreads();
     if (tid < kZ) {  // the diagonal 16-blocks: block b, column j of it, rows j .. 0
@@ -363,19 +356,11 @@ int launch_zgemm_h_inplace(int64_t M, int64_t N, int64_t K, const double *Pr, co
     return FLAME_OK;
 }
 
-int launch_zchol_lds(int n, double *R, double *I, int64_t ld, int32_t *info, int64_t info_base, hipStream_t s) {
+int launch_zchol_lds(int n, double *R, double *I, int64_t ld, int32_t *info, int64_t info_base, double *Vr,
+                     double *Vi, int64_t ldv, hipStream_t s) {
     if (n <= 0) return FLAME_OK;
-    if (n > kZ) return FLAME_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(k_zchol_lds, dim3(1), dim3(256), 0, s, n, R, I, ld, info, info_base);
-    FLAME_CHECK_LAUNCH();
-    return FLAME_OK;
-}
-
-int launch_ztrinv_lds(int n, const double *R, const double *I, int64_t ld, double *Vr, double *Vi, int64_t ldv,
-                      const int32_t *info, hipStream_t s) {
-    if (n <= 0) return FLAME_OK;
-    if (n > kZ) return FLAME_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(k_ztrinv_lds, dim3(1), dim3(256), 0, s, n, R, I, ld, Vr, Vi, ldv, info);
+    if (n > kZ || ldv < n) return FLAME_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_zchol_lds, dim3(1), dim3(256), 0, s, n, R, I, ld, info, info_base, Vr, Vi, ldv);
     FLAME_CHECK_LAUNCH();
     return FLAME_OK;
 }

@@ -12,11 +12,11 @@
 //   P^H Q = (Pr^T Qr + Pi^T Qi) + i (Pr^T Qi - Pi^T Qr),
 // the last one with a negated copy of Pi.  The HERK of each iteration is one
 // such product (upper triangle only); the panel solve goes by diagonal blocks
-// of 64: V = -U_ss^{-1} (k_ztrinv_lds), X_s := -V^H X_s = U_ss^{-H} X_s in
-// place by the fused complex product, and X_t -= U_st^H X_s for the blocks
-// below.
+// of 64: V = -U_ss^{-1}, X_s := -V^H X_s = U_ss^{-H} X_s in place by the
+// fused complex product, and X_t -= U_st^H X_s for the blocks below.
 // Diagonal blocks of the outer loop (nb) are factored by the same loop at
-// block 64, whose diagonal blocks go to the LDS kernel k_zchol_lds.
+// block 64, whose diagonal blocks go to the LDS kernel k_zchol_lds; it forms
+// each 64-block's V in the same launch, kept for the outer panel solve.
 #include <algorithm>
 
 #include "flame_internal.h"
@@ -55,21 +55,18 @@ int zgemm_h(bool upper, int64_t M, int64_t N, int64_t K, const double *Pr, const
 }
 
 // X := triu(U)^{-H} X for the b x b block U at (k, k) and the b x m panel X
-// at (k, c0) of the planes.  The inverse of the 64-block s lives in slot
-// slot0 + s; those of the first `reuse` blocks are there already (the inner
-// loop's solves formed them), the others are formed here.
+// at (k, c0) of the planes.  The negated inverse of the 64-block s is in slot
+// slot0 + s already: the diagonal-block kernel formed it with the factor.
 int ztrsm(const ZWork &w, int64_t k, int64_t b, int64_t c0, int64_t m, const int32_t *info, hipStream_t s,
-          int slot0, int reuse) {
+          int slot0) {
     const int64_t ld = w.ld;
     for (int64_t s0 = 0; s0 < b; s0 += kZB) {
         const int64_t bs = std::min<int64_t>(kZB, b - s0);
-        const int64_t us = (k + s0) + (k + s0) * ld;  // U_ss
         const int64_t xs = (k + s0) + c0 * ld;         // X_s
         const int ib = (int)(s0 / kZB);
         double *Vr = w.Vr + (int64_t)(slot0 + ib) * kZB * kZB, *Vi = w.Vi + (int64_t)(slot0 + ib) * kZB * kZB;
-        int rc = ib < reuse ? FLAME_OK : launch_ztrinv_lds((int)bs, w.R + us, w.I + us, ld, Vr, Vi, kZB, info, s);
         // X_s := -V^H X_s = U_ss^{-H} X_s, in place
-        if (!rc) rc = launch_zgemm_h_inplace(bs, m, bs, Vr, Vi, kZB, w.R + xs, w.I + xs, ld, info, s);
+        int rc = launch_zgemm_h_inplace(bs, m, bs, Vr, Vi, kZB, w.R + xs, w.I + xs, ld, info, s);
         if (rc) return rc;
         const int64_t rest = b - s0 - bs;
         if (rest > 0) {
@@ -85,19 +82,21 @@ int ztrsm(const ZWork &w, int64_t k, int64_t b, int64_t c0, int64_t m, const int
 }
 
 // Chol of the n x n diagonal block at (k, k) of the planes, by the loop at
-// block nb (<= kZB: the LDS kernel); the inverses its solves form go to the
-// slots from slot_base (one per 64-block).
+// block nb (<= kZB: the LDS kernel, which also forms the 64-block's negated
+// inverse); the inverses go to the slots from slot_base (one per 64-block).
 int zpotrf_block(const ZWork &w, int64_t k, int64_t n, int64_t nb, int32_t *info, int64_t info_base,
                  hipStream_t s, int slot_base) {
     const int64_t ld = w.ld;
-    if (n <= kZB) return launch_zchol_lds((int)n, w.R + k + k * ld, w.I + k + k * ld, ld, info, info_base, s);
+    if (n <= kZB)
+        return launch_zchol_lds((int)n, w.R + k + k * ld, w.I + k + k * ld, ld, info, info_base,
+                                w.Vr + (int64_t)slot_base * kZB * kZB, w.Vi + (int64_t)slot_base * kZB * kZB, kZB, s);
     for (int64_t k0 = 0; k0 < n; k0 += nb) {
         const int64_t bk = std::min<int64_t>(nb, n - k0);
         const int64_t m = n - k0 - bk;
         int rc = zpotrf_block(w, k + k0, bk, kZB, info, info_base + k0, s, slot_base + (int)(k0 / kZB));
         if (rc) return rc;
         if (m == 0) break;
-        rc = ztrsm(w, k + k0, bk, k + k0 + bk, m, info, s, slot_base + (int)(k0 / kZB), 0);
+        rc = ztrsm(w, k + k0, bk, k + k0 + bk, m, info, s, slot_base + (int)(k0 / kZB));
         if (rc) return rc;
         // A22 -= A12^H A12 (upper)
         const int64_t a12 = (k + k0) + (k + k0 + bk) * ld, a22 = (k + k0 + bk) + (k + k0 + bk) * ld;
@@ -140,8 +139,8 @@ int zfactor_outer(const ZWork &w, int64_t n, int64_t nb, double *const Pnb[2], i
         int rc = zpotrf_block(w, k0, bk, kZB, info, k0, s, 0);
         if (rc) return rc;
         if (m == 0) break;
-        // the inner loop's solves formed the inverses of all 64-blocks but the last
-        rc = ztrsm(w, k0, bk, k0 + bk, m, info, s, 0, (int)((bk + kZB - 1) / kZB) - 1);
+        // the diagonal-block kernels formed the inverses of all its 64-blocks
+        rc = ztrsm(w, k0, bk, k0 + bk, m, info, s, 0);
         if (rc) return rc;
         // A22 -= A12^H A12 (upper); the previous block's side part covered
         // rows of it too
