@@ -119,3 +119,23 @@ def test_complex_sampled_large():
     for cols in (slice(0, 64), slice(n - 64, n)):
         assert np.max(np.abs(np.triu(W)[:, cols] - np.triu(Uo)[:, cols])) <= 1e-13 * s
     assert oracle.zfactor_backward_error(A, W) <= 1e-14
+
+
+def test_complex_lookahead_leading_block():
+    """n = 3072 at block 256: the outer loop's lookahead is on (more than 2048
+    rows beyond the next block).  U's leading 512 x 512 block is the factor of
+    A's leading block, against the oracle element by element; the whole
+    factorization by its backward error."""
+    n, k = 3072, 512
+    A = inputs.hpd_bbh(n, 13)
+    Uo, io = oracle.zpotrf(np.asfortranarray(A[:k, :k]))
+    _, T = _dev(A, n)
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    o = fl.Opts(fl.VAR_RIGHT, 256, 0, 0, 0, 0)
+    rc = fl.lib().flame_factor(fl.Z64, n, T.data_ptr(), n, ctypes.byref(o), info.data_ptr(), fl._stream_ptr())
+    assert rc == 0
+    W = _host(T)
+    assert int(info.item()) == io == 0
+    s = np.max(np.abs(Uo))
+    assert np.max(np.abs(np.triu(W)[:k, :k] - np.triu(Uo))) <= 1e-13 * s
+    assert oracle.zfactor_backward_error(A, W) <= 1e-14

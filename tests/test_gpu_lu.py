@@ -62,3 +62,20 @@ def test_lu_sampled_large():
     for cols in (slice(0, 64), slice(n // 2, n // 2 + 64), slice(n - 64, n)):
         assert np.max(np.abs(W[:, cols] - Wo[:, cols])) <= 1e-13 * s
     assert oracle.lu_backward_error(A, W) <= 1e-14
+
+
+def test_lu_lookahead_leading_block():
+    """n = 4672: the lookahead is on (more than 2048 rows beyond the next
+    step's) and the write-backs of A12 and A21 run on both streams (beyond
+    4096 rows on the main one, below on the side one).  The leading 1024 x 1024
+    block of the packed factors is the LU of A's leading block, against the
+    oracle element by element; the whole factorization by its backward error."""
+    n, k = 4672, 1024
+    A = inputs.diag_dominant(n, 23)
+    Wo, io = oracle.getrf_nopiv(np.asfortranarray(A[:k, :k]))
+    T = to_dev(A)
+    assert int(fl.lu(T).item()) == io == 0
+    W = to_host(T)
+    s = np.max(np.abs(np.triu(Wo)))
+    assert np.max(np.abs(W[:k, :k] - Wo)) <= 1e-13 * s
+    assert oracle.lu_backward_error(A, W) <= 1e-14
